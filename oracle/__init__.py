@@ -1,0 +1,226 @@
+"""ctypes binding of the plain FP64 CPU oracle (test infrastructure only).
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py``
+may import this package.  The product library never loads it.
+
+Arrays use the oracle's own layout: one patch box of 15^3 cells (9^3 interior + 3 halo layers
+per face), cell-major with the 59 slots innermost: ``Q[patch, z, y, x, slot]``.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "libccz4_oracle.so")
+
+NV, NB, P, H = 59, 15, 9, 3
+
+
+def build():
+    subprocess.check_call(["sh", os.path.join(_HERE, "build.sh")])
+
+
+def _load():
+    if not os.path.exists(_LIB):
+        build()
+    return ctypes.CDLL(_LIB)
+
+
+_lib = _load()
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_i8p = np.ctypeslib.ndpointer(dtype=np.int8, flags="C_CONTIGUOUS")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("kappa1", ctypes.c_double), ("kappa2", ctypes.c_double), ("kappa3", ctypes.c_double),
+        ("tau", ctypes.c_double), ("e", ctypes.c_double), ("c", ctypes.c_double),
+        ("mu", ctypes.c_double), ("f", ctypes.c_double), ("eta", ctypes.c_double),
+        ("ko_eps", ctypes.c_double), ("slicing", ctypes.c_int), ("shift", ctypes.c_int),
+    ]
+
+
+def params(**kw):
+    d = dict(kappa1=0.1, kappa2=0.0, kappa3=0.5, tau=1.0, e=1.0, c=1.0, mu=0.2, f=0.75,
+             eta=2.0, ko_eps=0.1, slicing=1, shift=1)
+    d.update(kw)
+    return Params(**d)
+
+
+def _sig(name, res, args):
+    fn = getattr(_lib, name)
+    fn.restype = res
+    fn.argtypes = args
+    return fn
+
+
+_PP = ctypes.POINTER(Params)
+_rhs_point = _sig("orc_rhs_point", None, [_PP, _dp, _dp, _dp])
+_cons_point = _sig("orc_constraints_point", None, [_dp, _dp, _dp])
+_fd4 = _sig("orc_fd4", ctypes.c_double, [_dp, ctypes.c_double])
+_ko = _sig("orc_ko", ctypes.c_double, [_dp, ctypes.c_double, ctypes.c_double])
+_rhs_box = _sig("orc_rhs_box", None, [_PP, _dp, _dp, _dp])
+_cons_box = _sig("orc_constraints_box", None, [_dp, _dp, _dp])
+_mesh_create = _sig("orc_mesh_create", ctypes.c_void_p,
+                    [_ip, _dp, _dp, ctypes.c_int, ctypes.c_int, _ip])
+_mesh_destroy = _sig("orc_mesh_destroy", None, [ctypes.c_void_p])
+_mesh_np = _sig("orc_mesh_npatches", ctypes.c_int64, [ctypes.c_void_p])
+_mesh_ids = _sig("orc_mesh_patch_ids", None, [ctypes.c_void_p, _ip])
+_mesh_geom = _sig("orc_mesh_patch_geom", None, [ctypes.c_void_p, _dp])
+_init_point = _sig("orc_init_point", ctypes.c_int, [ctypes.c_int, _dp, _dp, _dp])
+_init = _sig("orc_init", ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_int, _dp])
+_set_bg = _sig("orc_set_background", None, [ctypes.c_void_p, _dp])
+_fill = _sig("orc_fill_halos", None, [ctypes.c_void_p, _dp])
+_rhs = _sig("orc_rhs", None, [ctypes.c_void_p, _PP, _dp, _dp])
+_rhs_subset = _sig("orc_rhs_subset", None,
+                   [ctypes.c_void_p, _PP, _dp, _dp, ctypes.c_int64, _i64p])
+_rk4 = _sig("orc_rk4_stage", ctypes.c_int,
+            [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp])
+_project = _sig("orc_project_point", None, [_dp])
+_cons = _sig("orc_constraints", ctypes.c_int64,
+             [ctypes.c_void_p, _dp, ctypes.c_void_p, ctypes.c_double, _dp])
+_tag_ind = _sig("orc_tag_indicator", None, [ctypes.c_void_p, _dp, _dp])
+_tag = _sig("orc_tag_refine", None,
+            [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _i8p])
+
+
+def _c(a, dt=np.float64):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def rhs_point(pr, q, dq):
+    out = np.zeros(NV)
+    _rhs_point(ctypes.byref(pr), _c(q), _c(dq).reshape(-1), out)
+    return out
+
+
+def constraints_point(q, dq):
+    out = np.zeros(4)
+    _cons_point(_c(q), _c(dq).reshape(-1), out)
+    return out
+
+
+def fd4(v5, dx):
+    return _fd4(_c(v5), dx)
+
+
+def ko(v7, dx, eps):
+    return _ko(_c(v7), dx, eps)
+
+
+def rhs_box(pr, dx, box):
+    box = _c(box)
+    out = np.zeros_like(box)
+    _rhs_box(ctypes.byref(pr), _c(dx), box, out)
+    return out
+
+
+def constraints_box(dx, box):
+    out = np.zeros((729, 4))
+    _cons_box(_c(dx), _c(box), out)
+    return out
+
+
+def init_point(scenario, sp, x):
+    q = np.zeros(NV)
+    if _init_point(scenario, _c(sp), _c(x), q):
+        raise ValueError("unknown scenario")
+    return q
+
+
+def project_point(q):
+    q = _c(q).copy()
+    _project(q)
+    return q
+
+
+class Mesh:
+    """Forest of 9^3-cell patches (oracle side).  bc: 0 periodic, 1 Neumann, 2 Sommerfeld."""
+
+    def __init__(self, n0, origin, extent, bc=0, refined=()):
+        ref = np.asarray(refined, dtype=np.int32).reshape(-1, 4)
+        self.n_refined = ref.shape[0]
+        ref = _c(ref if ref.size else np.zeros((1, 4)), np.int32)
+        self._h = _mesh_create(_c(n0, np.int32), _c(origin), _c(extent), bc, self.n_refined, ref)
+        self.np = int(_mesh_np(self._h))
+        self.ids = np.zeros((self.np, 4), dtype=np.int32)
+        _mesh_ids(self._h, self.ids)
+        self.geom = np.zeros((self.np, 6))
+        _mesh_geom(self._h, self.geom)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _mesh_destroy(self._h)
+            self._h = None
+
+    def zeros(self):
+        return np.zeros((self.np, NB, NB, NB, NV))
+
+    def cell_centers(self, p):
+        """(15,15,15,3) centres of box cells of leaf p, [z,y,x,axis]."""
+        org, dx = self.geom[p, :3], self.geom[p, 3:]
+        c = (np.arange(NB) - H + 0.5)
+        X = org[0] + c[None, None, :] * dx[0]
+        Y = org[1] + c[None, :, None] * dx[1]
+        Z = org[2] + c[:, None, None] * dx[2]
+        out = np.zeros((NB, NB, NB, 3))
+        out[..., 0], out[..., 1], out[..., 2] = np.broadcast_arrays(X, Y, Z)
+        return out
+
+    def init(self, Q, scenario, sp):
+        if _init(self._h, Q, scenario, _c(sp)):
+            raise ValueError("init failed")
+
+    def set_background(self, Q):
+        _set_bg(self._h, Q)
+
+    def fill_halos(self, Q):
+        _fill(self._h, Q)
+
+    def rhs(self, pr, Q, k=None, subset=None):
+        if k is None:
+            k = np.zeros_like(Q)
+        if subset is None:
+            _rhs(self._h, ctypes.byref(pr), Q, k)
+        else:
+            sel = _c(subset, np.int64)
+            _rhs_subset(self._h, ctypes.byref(pr), Q, k, sel.size, sel)
+        return k
+
+    def rk4_stage(self, s, dt, Qn, k, acc, Qnext):
+        if _rk4(self._h, s, dt, Qn, k, acc, Qnext):
+            raise ValueError("bad stage")
+
+    def constraints(self, Q, r_excise=0.0, want_fields=False):
+        norms = np.zeros(3)
+        HM = np.zeros((self.np, 729, 4)) if want_fields else None
+        _cons(self._h, Q, HM.ctypes.data if want_fields else None, r_excise, norms)
+        return (norms, HM) if want_fields else norms
+
+    def tag_indicator(self, Q):
+        ind = np.zeros((self.np, 3))
+        _tag_ind(self._h, Q, ind)
+        return ind
+
+    def tag_refine(self, Q, theta_r, theta_c, max_level):
+        tags = np.zeros(self.np, dtype=np.int8)
+        _tag(self._h, Q, theta_r, theta_c, max_level, tags)
+        return tags
+
+    def rk4_step(self, pr, Q, dt):
+        """One classical RK4 step: four (fill, rhs, stage) sweeps."""
+        acc = np.zeros_like(Q)
+        Qs = Q.copy()
+        Qnew = Q.copy()
+        for s in range(4):
+            self.fill_halos(Qs)
+            k = self.rhs(pr, Qs)
+            Qnext = Q.copy() if s < 3 else Qnew
+            self.rk4_stage(s, dt, Q, k, acc, Qnext)
+            Qs = Qnext
+        return Qnew

@@ -1,0 +1,905 @@
+/*
+ * Oracle (test infrastructure only): stencils, patch boxes, mesh of patches, initial data,
+ * halo filling, RK4 stage combine, algebraic projection, constraints and tagging for the
+ * first-order CCZ4 FD4 hot path of arXiv:2406.11626.  Plain loops in FP64; nothing here is
+ * blocked, fused or reordered beyond what the paper's definitions state.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include "ccz4_oracle.h"
+
+#define NV ORC_NV
+#define NB ORC_NB
+#define PP ORC_P
+#define HH ORC_H
+
+static int64_t cix(int x, int y, int z) { return ((int64_t)z * NB + y) * NB + x; }
+
+/* ----------------------------------------------------------------------------------------
+ * One-dimensional stencils (App. D).
+ * Central fourth-order first derivative, eq. (eq_exa_fd4_central_difference):
+ *   dQ/dx = [8 (Q+ - Q-) - (Q++ - Q--)] / (12 dx).
+ * Kreiss-Oliger dissipation of order N = 3, eq. (eq_exa_fd4_ko):
+ *   KO = eps/(64 dx) (Q--- - 6Q-- + 15Q- - 20Q + 15Q+ - 6Q++ + Q+++).
+ * ---------------------------------------------------------------------------------------- */
+double orc_fd4(const double *v, double dx)
+{
+    return (8.0 * (v[3] - v[1]) - (v[4] - v[0])) / (12.0 * dx);
+}
+
+double orc_ko(const double *v, double dx, double eps)
+{
+    return eps / (64.0 * dx) *
+           (v[0] - 6.0 * v[1] + 15.0 * v[2] - 20.0 * v[3] + 15.0 * v[4] - 6.0 * v[5] + v[6]);
+}
+
+static int frozen_slot(const orc_params *pr, int v)
+{
+    /* beta^i (7-9), b^i (22-24), B_k^i (28-36) do not evolve with the static shift */
+    if (pr->shift) return 0;
+    return (v >= 7 && v <= 9) || (v >= 22 && v <= 24) || (v >= 28 && v <= 36);
+}
+
+/* Right-hand side on the 9^3 interior of one box whose halos are filled.  Algorithm 1 of
+   the paper (FD4 first-order step): per volume, the source and the non-conservative
+   products from the central FD4 derivatives along x, y, z, plus the KO sum over the axes.
+   Slots 11..57 are differentiated; KO acts on the 58 evolved slots. */
+void orc_rhs_box(const orc_params *pr, const double dx[3], const double *box, double *out)
+{
+    int x, y, z, a, v, s;
+    double dq[3 * NV], q[NV], r[NV], w[7];
+    for (z = HH; z < HH + PP; z++)
+        for (y = HH; y < HH + PP; y++)
+            for (x = HH; x < HH + PP; x++) {
+                const int64_t c = cix(x, y, z);
+                memcpy(q, box + c * NV, sizeof(q));
+                memset(dq, 0, sizeof(dq));
+                for (a = 0; a < 3; a++) {
+                    for (v = 11; v <= 57; v++) {
+                        for (s = -2; s <= 2; s++) {
+                            int xx = x + (a == 0 ? s : 0), yy = y + (a == 1 ? s : 0),
+                                zz = z + (a == 2 ? s : 0);
+                            w[s + 2] = box[cix(xx, yy, zz) * NV + v];
+                        }
+                        dq[a * NV + v] = orc_fd4(w, dx[a]);
+                    }
+                }
+                orc_rhs_point(pr, q, dq, r);
+                for (v = 0; v < 58; v++) {
+                    double ko = 0;
+                    if (frozen_slot(pr, v)) continue;
+                    for (a = 0; a < 3; a++) {
+                        for (s = -3; s <= 3; s++) {
+                            int xx = x + (a == 0 ? s : 0), yy = y + (a == 1 ? s : 0),
+                                zz = z + (a == 2 ? s : 0);
+                            w[s + 3] = box[cix(xx, yy, zz) * NV + v];
+                        }
+                        ko += orc_ko(w, dx[a], pr->ko_eps);
+                    }
+                    r[v] += ko;
+                }
+                r[58] = 0.0;
+                memcpy(out + c * NV, r, sizeof(r));
+            }
+}
+
+/* Constraints on the 9^3 interior of one box: hm[cell][4] = (H, M_x, M_y, M_z), interior
+   cells in x-fastest order.  Derivatives are the same central FD4 differences. */
+void orc_constraints_box(const double dx[3], const double *box, double *hm)
+{
+    int x, y, z, a, v, s;
+    double dq[3 * NV], w[5];
+    int64_t n = 0;
+    for (z = HH; z < HH + PP; z++)
+        for (y = HH; y < HH + PP; y++)
+            for (x = HH; x < HH + PP; x++, n++) {
+                memset(dq, 0, sizeof(dq));
+                for (a = 0; a < 3; a++)
+                    for (v = 11; v <= 57; v++) {
+                        for (s = -2; s <= 2; s++) {
+                            int xx = x + (a == 0 ? s : 0), yy = y + (a == 1 ? s : 0),
+                                zz = z + (a == 2 ? s : 0);
+                            w[s + 2] = box[cix(xx, yy, zz) * NV + v];
+                        }
+                        dq[a * NV + v] = orc_fd4(w, dx[a]);
+                    }
+                orc_constraints_point(box + cix(x, y, z) * NV, dq, hm + 4 * n);
+            }
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Mesh of patches: a forest of n0 level-0 cubes over [origin, origin+extent], each refined
+ * cube split into 3^3 children (tri-partitioning, ratio 3).  Leaves carry the data.  The
+ * leaves are ordered by (level, k, j, i).
+ * ---------------------------------------------------------------------------------------- */
+struct orc_mesh {
+    int n0[3];
+    double origin[3], extent[3];
+    int bc;
+    int nref;
+    int *ref;      /* refined cubes: lev,i,j,k */
+    int64_t np;
+    int *id;       /* leaves: lev,i,j,k */
+    double *bg;    /* Sommerfeld background: one full box per leaf touching the boundary */
+    int64_t *bgix; /* leaf -> background box index or -1 */
+};
+
+static int lev_n(const orc_mesh *m, int lev, int a)
+{
+    int n = m->n0[a];
+    while (lev-- > 0) n *= 3;
+    return n;
+}
+
+/* keys are (lev, k, j, i) compared lexicographically: the canonical leaf order */
+static int cmp4(const void *pa, const void *pb)
+{
+    const int *x = (const int *)pa, *y = (const int *)pb;
+    static const int ord[4] = {0, 3, 2, 1};
+    int t;
+    for (t = 0; t < 4; t++)
+        if (x[ord[t]] != y[ord[t]]) return x[ord[t]] < y[ord[t]] ? -1 : 1;
+    return 0;
+}
+
+static int is_refined(const orc_mesh *m, int lev, int i, int j, int k)
+{
+    int key[4] = {lev, i, j, k};
+    return m->nref > 0 && bsearch(key, m->ref, m->nref, sizeof(int) * 4, cmp4) != NULL;
+}
+
+/* A cube exists if it is level 0 or its parent is refined. */
+static int exists(const orc_mesh *m, int lev, int i, int j, int k)
+{
+    if (i < 0 || j < 0 || k < 0 || i >= lev_n(m, lev, 0) || j >= lev_n(m, lev, 1) ||
+        k >= lev_n(m, lev, 2))
+        return 0;
+    if (lev == 0) return 1;
+    return is_refined(m, lev - 1, i / 3, j / 3, k / 3) && exists(m, lev - 1, i / 3, j / 3, k / 3);
+}
+
+static int64_t find_leaf(const orc_mesh *m, int lev, int i, int j, int k)
+{
+    int key[4] = {lev, i, j, k};
+    const int *hit;
+    if (m->np == 0) return -1;
+    hit = (const int *)bsearch(key, m->id, m->np, sizeof(int) * 4, cmp4);
+    return hit ? (int64_t)(hit - m->id) / 4 : -1;
+}
+
+static void push4(int **arr, int64_t *n, int64_t *cap, int l, int i, int j, int k)
+{
+    if (*n == *cap) {
+        *cap = *cap ? 2 * *cap : 1024;
+        *arr = (int *)realloc(*arr, sizeof(int) * 4 * *cap);
+    }
+    (*arr)[4 * *n] = l;
+    (*arr)[4 * *n + 1] = i;
+    (*arr)[4 * *n + 2] = j;
+    (*arr)[4 * *n + 3] = k;
+    (*n)++;
+}
+
+orc_mesh *orc_mesh_create(const int n0[3], const double origin[3], const double extent[3],
+                          int bc, int n_refined, const int *refined)
+{
+    orc_mesh *m = (orc_mesh *)calloc(1, sizeof(orc_mesh));
+    int a, i, j, k, u, v, w;
+    int64_t cap = 0, r;
+    for (a = 0; a < 3; a++) {
+        m->n0[a] = n0[a];
+        m->origin[a] = origin[a];
+        m->extent[a] = extent[a];
+    }
+    m->bc = bc;
+    m->nref = n_refined > 0 ? n_refined : 0;
+    m->ref = (int *)malloc(sizeof(int) * 4 * (m->nref > 0 ? m->nref : 1));
+    if (m->nref > 0) memcpy(m->ref, refined, sizeof(int) * 4 * (size_t)m->nref);
+    qsort(m->ref, m->nref, sizeof(int) * 4, cmp4);
+    m->id = NULL;
+    m->np = 0;
+    /* level-0 cubes, then the children of every refined cube; keep the unrefined ones */
+    for (k = 0; k < n0[2]; k++)
+        for (j = 0; j < n0[1]; j++)
+            for (i = 0; i < n0[0]; i++)
+                if (!is_refined(m, 0, i, j, k)) push4(&m->id, &m->np, &cap, 0, i, j, k);
+    for (r = 0; r < m->nref; r++) {
+        const int *c = m->ref + 4 * r;
+        if (!exists(m, c[0], c[1], c[2], c[3])) continue;
+        for (w = 0; w < 3; w++)
+            for (v = 0; v < 3; v++)
+                for (u = 0; u < 3; u++)
+                    if (!is_refined(m, c[0] + 1, 3 * c[1] + u, 3 * c[2] + v, 3 * c[3] + w))
+                        push4(&m->id, &m->np, &cap, c[0] + 1, 3 * c[1] + u, 3 * c[2] + v,
+                              3 * c[3] + w);
+    }
+    qsort(m->id, m->np, sizeof(int) * 4, cmp4);
+    m->bgix = (int64_t *)malloc(sizeof(int64_t) * (m->np ? m->np : 1));
+    for (r = 0; r < m->np; r++) m->bgix[r] = -1;
+    return m;
+}
+
+void orc_mesh_destroy(orc_mesh *m)
+{
+    if (!m) return;
+    free(m->ref);
+    free(m->id);
+    free(m->bg);
+    free(m->bgix);
+    free(m);
+}
+
+int64_t orc_mesh_npatches(const orc_mesh *m) { return m->np; }
+
+void orc_mesh_patch_ids(const orc_mesh *m, int *ids) { memcpy(ids, m->id, sizeof(int) * 4 * m->np); }
+
+static void patch_geom(const orc_mesh *m, int64_t p, double org[3], double dx[3])
+{
+    int a, lev = m->id[4 * p];
+    for (a = 0; a < 3; a++) {
+        double L = m->extent[a] / lev_n(m, lev, a);
+        org[a] = m->origin[a] + L * m->id[4 * p + 1 + a];
+        dx[a] = L / PP;
+    }
+}
+
+void orc_mesh_patch_geom(const orc_mesh *m, double *geom)
+{
+    int64_t p;
+    for (p = 0; p < m->np; p++) patch_geom(m, p, geom + 6 * p, geom + 6 * p + 3);
+}
+
+/* centre of box cell (x,y,z) (box coordinates 0..14, interior 3..11) */
+static void cell_center(const orc_mesh *m, int64_t p, int x, int y, int z, double out[3])
+{
+    double org[3], dx[3];
+    int c[3] = {x, y, z}, a;
+    patch_geom(m, p, org, dx);
+    for (a = 0; a < 3; a++) out[a] = org[a] + (c[a] - HH + 0.5) * dx[a];
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Initial data.
+ *  0: gauge wave (the paper's gauge-wave section): H = 1 - A sin(k pi (x - t)) at t = 0,
+ *     alpha = sqrt(H), gamma = diag(H,1,1), phi = H^(-1/6), K_xx = -d_t H/(2 alpha),
+ *     K = K_xx/H; conformal variables and the auxiliaries A, D, P follow from their
+ *     definitions; Ghat = Gt (Z = 0), Theta = 0, zero shift.
+ *  1: single puncture (the paper's single black hole section): psi = 1 + M/(2r),
+ *     phi = psi^-2, gt = delta, K_ij = 0; lapse kind sp[4]: 0 -> alpha = psi^-2,
+ *     1 -> alpha = ((1 - M/2r)/(1 + M/2r) + 1)/2 (the paper's averaged lapse),
+ *     2 -> alpha = (1 - M/2r)/(1 + M/2r) (static isotropic Schwarzschild).
+ *  2: two Brill-Lindquist punctures with Bowen-York extrinsic curvature (no spin, no
+ *     puncture correction): psi = 1 + sum m_a/(2 r_a), At = psi^-6 Ahat,
+ *     Ahat_ij = sum 3/(2 r_a^2) [P_i n_j + P_j n_i - (delta_ij - n_i n_j) P.n], K = 0,
+ *     alpha = psi^-2.
+ * ---------------------------------------------------------------------------------------- */
+int orc_init_point(int scenario, const double *sp, const double xx[3], double *q)
+{
+    int i, j, k;
+    memset(q, 0, sizeof(double) * NV);
+    if (scenario == 0) {
+        const double A = sp[0], kk = sp[1], pi = 3.14159265358979323846;
+        const double Hh = 1.0 - A * sin(kk * pi * xx[0]);
+        const double Hp = -A * kk * pi * cos(kk * pi * xx[0]); /* dH/dx (= -dH/dt) */
+        const double al = sqrt(Hh);
+        const double Kxx = Hp / (2.0 * al); /* -d_t H / (2 alpha) with d_t H = -H' */
+        const double Kt = Kxx / Hh;
+        q[0] = pow(Hh, 2.0 / 3.0);           /* gt_xx */
+        q[3] = pow(Hh, -1.0 / 3.0);          /* gt_yy */
+        q[5] = pow(Hh, -1.0 / 3.0);          /* gt_zz */
+        q[6] = al;
+        q[10] = pow(Hh, -1.0 / 6.0);
+        q[11] = 2.0 / 3.0 * pow(Hh, -1.0 / 3.0) * Kxx;  /* At_xx */
+        q[14] = -1.0 / 3.0 * pow(Hh, -4.0 / 3.0) * Kxx; /* At_yy */
+        q[16] = -1.0 / 3.0 * pow(Hh, -4.0 / 3.0) * Kxx; /* At_zz */
+        q[17] = Kt;
+        q[19] = 2.0 / 3.0 * pow(Hh, -5.0 / 3.0) * Hp;   /* Ghat^x = Gt^x */
+        q[25] = Hp / (2.0 * al);                        /* A_x */
+        q[37 + 0] = 1.0 / 3.0 * pow(Hh, -1.0 / 3.0) * Hp;  /* D_xxx */
+        q[37 + 3] = -1.0 / 6.0 * pow(Hh, -4.0 / 3.0) * Hp; /* D_xyy */
+        q[37 + 5] = -1.0 / 6.0 * pow(Hh, -4.0 / 3.0) * Hp; /* D_xzz */
+        q[55] = -1.0 / 6.0 * pow(Hh, -7.0 / 6.0) * Hp;     /* P_x */
+        return 0;
+    }
+    if (scenario == 1) {
+        const double M = sp[0];
+        double d[3], r, psi, dpsi[3], al, dal[3];
+        for (i = 0; i < 3; i++) d[i] = xx[i] - sp[1 + i];
+        r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        psi = 1.0 + M / (2.0 * r);
+        for (i = 0; i < 3; i++) dpsi[i] = -M * d[i] / (2.0 * r * r * r);
+        q[0] = q[3] = q[5] = 1.0;
+        q[10] = 1.0 / (psi * psi);
+        for (i = 0; i < 3; i++) q[55 + i] = -2.0 / (psi * psi * psi) * dpsi[i];
+        if ((int)sp[4] == 0) {
+            al = 1.0 / (psi * psi);
+            for (i = 0; i < 3; i++) dal[i] = -2.0 / (psi * psi * psi) * dpsi[i];
+        } else {
+            /* alpha_s = (1 - M/2r)/(1 + M/2r) = (2 - psi)/psi,  d alpha_s = -2 dpsi / psi^2 */
+            double as = (2.0 - psi) / psi;
+            double w = ((int)sp[4] == 1) ? 0.5 : 1.0;
+            al = ((int)sp[4] == 1) ? 0.5 * (as + 1.0) : as;
+            for (i = 0; i < 3; i++) dal[i] = w * (-2.0 / (psi * psi)) * dpsi[i];
+        }
+        q[6] = al;
+        for (i = 0; i < 3; i++) q[25 + i] = dal[i];
+        return 0;
+    }
+    if (scenario == 2) {
+        double psi = 1.0, dpsi[3] = {0, 0, 0}, Ah[3][3] = {{0}};
+        int a;
+        for (a = 0; a < 2; a++) {
+            const double *s = sp + 7 * a;
+            double d[3], r, n[3], Pn = 0;
+            for (i = 0; i < 3; i++) d[i] = xx[i] - s[1 + i];
+            r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            for (i = 0; i < 3; i++) n[i] = d[i] / r;
+            psi += s[0] / (2.0 * r);
+            for (i = 0; i < 3; i++) dpsi[i] += -s[0] * d[i] / (2.0 * r * r * r);
+            for (i = 0; i < 3; i++) Pn += s[4 + i] * n[i];
+            for (i = 0; i < 3; i++)
+                for (j = 0; j < 3; j++)
+                    Ah[i][j] += 3.0 / (2.0 * r * r) *
+                                (s[4 + i] * n[j] + s[4 + j] * n[i] -
+                                 ((i == j ? 1.0 : 0.0) - n[i] * n[j]) * Pn);
+        }
+        q[0] = q[3] = q[5] = 1.0;
+        q[10] = 1.0 / (psi * psi);
+        q[6] = 1.0 / (psi * psi);
+        for (i = 0; i < 3; i++) {
+            q[55 + i] = -2.0 / (psi * psi * psi) * dpsi[i];
+            q[25 + i] = q[55 + i];
+        }
+        k = 11;
+        for (i = 0; i < 3; i++)
+            for (j = i; j < 3; j++) q[k++] = pow(psi, -6.0) * Ah[i][j];
+        return 0;
+    }
+    return -1;
+}
+
+static int on_phys_boundary(const orc_mesh *m, int64_t p, int a, int side)
+{
+    int lev = m->id[4 * p], i = m->id[4 * p + 1 + a];
+    if (m->bc == ORC_BC_PERIODIC) return 0;
+    return side < 0 ? (i == 0) : (i == lev_n(m, lev, a) - 1);
+}
+
+/* Initial data on the interior of every leaf and, with the Sommerfeld condition, on the
+   ghost layers of faces on the domain boundary (those ghosts are evolved, not filled).
+   The interior and the Sommerfeld ghosts are then projected (det gt = 1, tr At = 0). */
+int orc_init(const orc_mesh *m, double *Q, int scenario, const double *sp)
+{
+    int64_t p;
+    int x, y, z;
+    for (p = 0; p < m->np; p++) {
+        double *box = Q + p * (int64_t)ORC_BOXCELLS * NV;
+        for (z = 0; z < NB; z++)
+            for (y = 0; y < NB; y++)
+                for (x = 0; x < NB; x++) {
+                    int c[3] = {x, y, z}, a, nin = 0, ghost_ok = 0;
+                    double xx[3];
+                    for (a = 0; a < 3; a++) nin += (c[a] >= HH && c[a] < HH + PP);
+                    if (nin == 3) ghost_ok = 1;
+                    else if (nin == 2 && m->bc == ORC_BC_SOMMERFELD) {
+                        for (a = 0; a < 3; a++) {
+                            if (c[a] < HH && on_phys_boundary(m, p, a, -1)) ghost_ok = 1;
+                            if (c[a] >= HH + PP && on_phys_boundary(m, p, a, +1)) ghost_ok = 1;
+                        }
+                    }
+                    if (!ghost_ok) continue;
+                    cell_center(m, p, x, y, z, xx);
+                    if (orc_init_point(scenario, sp, xx, box + cix(x, y, z) * NV)) return -1;
+                    if (nin == 3) orc_project_point(box + cix(x, y, z) * NV);
+                }
+    }
+    orc_set_background((orc_mesh *)m, Q);
+    return 0;
+}
+
+/* Snapshot the Sommerfeld ghost values of every boundary leaf as Q_ini. */
+void orc_set_background(orc_mesh *m, const double *Q)
+{
+    int64_t p, nb = 0;
+    int a;
+    free(m->bg);
+    m->bg = NULL;
+    for (p = 0; p < m->np; p++) {
+        int any = 0;
+        for (a = 0; a < 3; a++) any |= on_phys_boundary(m, p, a, -1) | on_phys_boundary(m, p, a, 1);
+        m->bgix[p] = any ? nb++ : -1;
+    }
+    if (!nb) return;
+    m->bg = (double *)malloc(sizeof(double) * nb * ORC_BOXCELLS * NV);
+    for (p = 0; p < m->np; p++)
+        if (m->bgix[p] >= 0)
+            memcpy(m->bg + m->bgix[p] * ORC_BOXCELLS * NV, Q + p * (int64_t)ORC_BOXCELLS * NV,
+                   sizeof(double) * ORC_BOXCELLS * NV);
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Halo filling (paper: patch/face data layout, boundary treatment, AMR and App. E).
+ * For every leaf and each of its six faces (axis a, side s):
+ *   - same-level leaf neighbour (with periodic wrap): copy its three interior layers;
+ *   - domain boundary: Neumann copies the boundary layer outwards layer by layer,
+ *     Sommerfeld leaves the ghosts alone (they are evolved by the RHS and RK stage);
+ *   - neighbour refined (finer leaves behind the face): RESTRICT, coarse halo layers
+ *     c3,c4,c5 = (R_avg x R_avg x R_perp) of the fine interior layers f3,f4,f5;
+ *   - neighbour covered by a coarser leaf: PROLONG, fine halo layers f0,f1,f2 =
+ *     (P_par x P_par x P_perp) of the coarse layers c0..c5 (c3..c5 = coarse halo).
+ * All restrictions are done before any prolongation because P_perp reads c3.
+ * Edges and corners of the box are never filled (the stencils are axis-aligned).
+ * ---------------------------------------------------------------------------------------- */
+
+/* P_parallel (3p x p): row F maps to coarse u = (F+1/2)/3 - 1/2, linear between
+   l = clamp(floor(u), 0, p-2) and l+1 (rows of App. E, with extrapolation at both ends). */
+static void build_P_par(double Ppar[3 * PP][PP])
+{
+    int F, l;
+    memset(Ppar, 0, sizeof(double) * 3 * PP * PP);
+    for (F = 0; F < 3 * PP; F++) {
+        double u = (F + 0.5) / 3.0 - 0.5;
+        l = (int)floor(u);
+        if (l < 0) l = 0;
+        if (l > PP - 2) l = PP - 2;
+        Ppar[F][l] = 1.0 - (u - l);
+        Ppar[F][l + 1] = u - l;
+    }
+}
+
+static const double P_perp[3][6] = {{0, 1.0 / 3, 2.0 / 3, 0, 0, 0},
+                                    {0, 0, 1, 0, 0, 0},
+                                    {0, 0, 2.0 / 3, 1.0 / 3, 0, 0}};
+static const double R_perp[3][6] = {{0, 0, 0, 1.0 / 3, 1.0 / 3, 1.0 / 3},
+                                    {0, 0, 0, 0, -2, 3},
+                                    {0, 0, 0, 0, -5, 6}};
+
+/* box coordinate of a cell at "depth" d from a face: d = 1..3 inside (1 adjacent to the
+   face), d = -1..-3 outside (ghost layer -d, -1 adjacent) */
+static int layer_coord(int side, int d)
+{
+    if (side > 0) return d > 0 ? HH + PP - d : HH + PP - 1 - d;
+    return d > 0 ? HH - 1 + d : HH + d;
+}
+
+static double *cellp(double *Q, int64_t p, int c[3])
+{
+    return Q + (p * (int64_t)ORC_BOXCELLS + cix(c[0], c[1], c[2])) * NV;
+}
+
+static void fill_face_copy(const orc_mesh *m, double *Q, int64_t p, int a, int side, int64_t nb)
+{
+    int t1, t2, L, c[3], cn[3];
+    const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+    for (L = 1; L <= 3; L++)
+        for (t2 = HH; t2 < HH + PP; t2++)
+            for (t1 = HH; t1 < HH + PP; t1++) {
+                c[b1] = cn[b1] = t1;
+                c[b2] = cn[b2] = t2;
+                c[a] = layer_coord(side, -L);
+                cn[a] = layer_coord(-side, L); /* neighbour's interior layer L from the shared face */
+                memcpy(cellp(Q, p, c), cellp(Q, nb, cn), sizeof(double) * NV);
+            }
+    (void)m;
+}
+
+static void fill_face_neumann(double *Q, int64_t p, int a, int side)
+{
+    /* Q_out = Q_in layer by layer outwards: ghost L takes the value of ghost L-1, ghost 1
+       that of the boundary interior layer, so every ghost equals the boundary layer. */
+    int t1, t2, L, c[3], ci[3];
+    const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+    for (L = 1; L <= 3; L++)
+        for (t2 = HH; t2 < HH + PP; t2++)
+            for (t1 = HH; t1 < HH + PP; t1++) {
+                c[b1] = ci[b1] = t1;
+                c[b2] = ci[b2] = t2;
+                c[a] = layer_coord(side, -L);
+                ci[a] = (L == 1) ? layer_coord(side, 1) : layer_coord(side, -(L - 1));
+                memcpy(cellp(Q, p, c), cellp(Q, p, ci), sizeof(double) * NV);
+            }
+}
+
+/* coarse leaf p (level lev) face (a, side) whose neighbour cube is refined: restrict from
+   the 9 fine children that touch the face. */
+static void fill_face_restrict(const orc_mesh *m, double *Q, int64_t p, int a, int side,
+                               int ni[3])
+{
+    const int b1 = (a + 1) % 3, b2 = (a + 2) % 3, lev = m->id[4 * p];
+    int64_t kids[3][3];
+    int u1, u2, L, v, F1, F2, m6, c[3];
+    /* fine children of the neighbour cube adjacent to the shared face */
+    for (u2 = 0; u2 < 3; u2++)
+        for (u1 = 0; u1 < 3; u1++) {
+            int ci[3];
+            ci[a] = 3 * ni[a] + (side > 0 ? 0 : 2);
+            ci[b1] = 3 * ni[b1] + u1;
+            ci[b2] = 3 * ni[b2] + u2;
+            kids[u2][u1] = find_leaf(m, lev + 1, ci[0], ci[1], ci[2]);
+        }
+    for (L = 1; L <= 3; L++)           /* coarse halo layer c_{2+L} */
+        for (u2 = 0; u2 < PP; u2++)    /* coarse tangential index along b2 */
+            for (u1 = 0; u1 < PP; u1++) {
+                double acc[NV];
+                memset(acc, 0, sizeof(acc));
+                /* sum over fine tangential F1, F2 in [0,27) and fine layers f0..f5 */
+                for (F2 = 0; F2 < 3 * PP; F2++)
+                    for (F1 = 0; F1 < 3 * PP; F1++) {
+                        double w1 = (F1 / 3 == u1) ? 1.0 / 3.0 : 0.0; /* R_avg */
+                        double w2 = (F2 / 3 == u2) ? 1.0 / 3.0 : 0.0;
+                        if (w1 == 0.0 || w2 == 0.0) continue;
+                        for (m6 = 3; m6 < 6; m6++) {
+                            double w = w1 * w2 * R_perp[L - 1][m6];
+                            int64_t kid = kids[F2 / PP][F1 / PP];
+                            int cf[3];
+                            if (w == 0.0) continue;
+                            cf[b1] = HH + F1 % PP;
+                            cf[b2] = HH + F2 % PP;
+                            /* fine layer f_{m6}, m6 = 3..5: fine interior depth m6-2 from the
+                               face shared with the coarse leaf (that face is -side for the kid) */
+                            cf[a] = layer_coord(-side, m6 - 2);
+                            const double *src = cellp(Q, kid, cf);
+                            for (v = 0; v < NV; v++) acc[v] += w * src[v];
+                        }
+                    }
+                c[b1] = HH + u1;
+                c[b2] = HH + u2;
+                c[a] = layer_coord(side, -L);
+                memcpy(cellp(Q, p, c), acc, sizeof(acc));
+            }
+}
+
+/* fine leaf p face (a, side) whose neighbour region is covered by the coarse leaf cp */
+static void fill_face_prolong(const orc_mesh *m, double *Q, int64_t p, int a, int side,
+                              int64_t cp, const int ni[3])
+{
+    static double Ppar[3 * PP][PP];
+    static int built = 0;
+    const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+    int L, t1, t2, l1, l2, m6, v, c[3];
+    int o1, o2;
+    if (!built) { build_P_par(Ppar); built = 1; }
+    /* position of this fine patch inside the coarse face: fine index minus 3 * coarse index */
+    o1 = ni[b1] - 3 * m->id[4 * cp + 1 + b1];
+    o2 = ni[b2] - 3 * m->id[4 * cp + 1 + b2];
+    for (L = 1; L <= 3; L++) {        /* fine ghost layer L -> f_{3-L} */
+        const int frow = 3 - L;
+        for (t2 = 0; t2 < PP; t2++)
+            for (t1 = 0; t1 < PP; t1++) {
+                double acc[NV];
+                const int F1 = PP * o1 + t1, F2 = PP * o2 + t2;
+                memset(acc, 0, sizeof(acc));
+                for (l2 = 0; l2 < PP; l2++)
+                    for (l1 = 0; l1 < PP; l1++) {
+                        double w12 = Ppar[F1][l1] * Ppar[F2][l2];
+                        if (w12 == 0.0) continue;
+                        for (m6 = 0; m6 < 6; m6++) {
+                            double w = w12 * P_perp[frow][m6];
+                            int cc[3];
+                            if (w == 0.0) continue;
+                            cc[b1] = HH + l1;
+                            cc[b2] = HH + l2;
+                            /* coarse layer c_{m6}: c0..c2 interior depth 3..1 from the shared face
+                               (which is face -side of the coarse leaf), c3..c5 its halo 1..3 */
+                            cc[a] = m6 < 3 ? layer_coord(-side, 3 - m6) : layer_coord(-side, -(m6 - 2));
+                            const double *src = cellp(Q, cp, cc);
+                            for (v = 0; v < NV; v++) acc[v] += w * src[v];
+                        }
+                    }
+                c[b1] = HH + t1;
+                c[b2] = HH + t2;
+                c[a] = layer_coord(side, -L);
+                memcpy(cellp(Q, p, c), acc, sizeof(acc));
+            }
+    }
+}
+
+typedef struct { int kind; int64_t nb; int ni[3]; } face_t; /* 0 copy 1 bc 2 restrict 3 prolong */
+
+static face_t classify(const orc_mesh *m, int64_t p, int a, int side)
+{
+    face_t f;
+    int lev = m->id[4 * p], n[3], b;
+    memset(&f, 0, sizeof(f));
+    for (b = 0; b < 3; b++) n[b] = m->id[4 * p + 1 + b];
+    n[a] += side;
+    if (n[a] < 0 || n[a] >= lev_n(m, lev, a)) {
+        if (m->bc != ORC_BC_PERIODIC) { f.kind = 1; return f; }
+        n[a] = (n[a] + lev_n(m, lev, a)) % lev_n(m, lev, a);
+    }
+    for (b = 0; b < 3; b++) f.ni[b] = n[b];
+    f.nb = find_leaf(m, lev, n[0], n[1], n[2]);
+    if (f.nb >= 0) { f.kind = 0; return f; }
+    if (exists(m, lev, n[0], n[1], n[2]) && is_refined(m, lev, n[0], n[1], n[2])) {
+        f.kind = 2;
+        return f;
+    }
+    f.kind = 3;
+    f.nb = find_leaf(m, lev - 1, n[0] / 3, n[1] / 3, n[2] / 3);
+    return f;
+}
+
+void orc_fill_halos(const orc_mesh *m, double *Q)
+{
+    int64_t p;
+    int a, side;
+    for (p = 0; p < m->np; p++)
+        for (a = 0; a < 3; a++)
+            for (side = -1; side <= 1; side += 2) {
+                face_t f = classify(m, p, a, side);
+                if (f.kind == 0) fill_face_copy(m, Q, p, a, side, f.nb);
+                else if (f.kind == 1) { if (m->bc == ORC_BC_NEUMANN) fill_face_neumann(Q, p, a, side); }
+                else if (f.kind == 2) fill_face_restrict(m, Q, p, a, side, f.ni);
+            }
+    for (p = 0; p < m->np; p++)
+        for (a = 0; a < 3; a++)
+            for (side = -1; side <= 1; side += 2) {
+                face_t f = classify(m, p, a, side);
+                if (f.kind == 3) fill_face_prolong(m, Q, p, a, side, f.nb, f.ni);
+            }
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Right-hand side over the mesh.  Interior cells per orc_rhs_box; on faces at the domain
+ * boundary with the Sommerfeld condition, every ghost layer L is an ODE unknown with
+ *   G_L = -c (r/|x_n|) (Q_L - Q_{L-1})/dx_n - (c/r)(Q_L - Q_ini,L),   c = 1,
+ * the layered finite-difference form of the paper's radiative condition
+ * (eq_exa_sommerfeld_inter), r and x_n taken at the ghost itself, Q_{L-1} the next layer
+ * inwards (L = 1: the last interior layer).  K_0 and frozen-shift slots get 0.
+ * ---------------------------------------------------------------------------------------- */
+static void sommerfeld_box(const orc_mesh *m, const orc_params *pr, int64_t p, const double *box,
+                           double *out)
+{
+    int a, side, L, t1, t2, v, c[3], ci[3];
+    double org[3], dx[3];
+    const double *bg;
+    if (m->bc != ORC_BC_SOMMERFELD || m->bgix[p] < 0) return;
+    bg = m->bg + m->bgix[p] * ORC_BOXCELLS * NV;
+    patch_geom(m, p, org, dx);
+    for (a = 0; a < 3; a++)
+        for (side = -1; side <= 1; side += 2) {
+            const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
+            if (!on_phys_boundary(m, p, a, side)) continue;
+            for (L = 1; L <= 3; L++)
+                for (t2 = HH; t2 < HH + PP; t2++)
+                    for (t1 = HH; t1 < HH + PP; t1++) {
+                        double xx[3], r;
+                        c[b1] = ci[b1] = t1;
+                        c[b2] = ci[b2] = t2;
+                        c[a] = layer_coord(side, -L);
+                        ci[a] = (L == 1) ? layer_coord(side, 1) : layer_coord(side, -(L - 1));
+                        cell_center(m, p, c[0], c[1], c[2], xx);
+                        r = sqrt(xx[0] * xx[0] + xx[1] * xx[1] + xx[2] * xx[2]);
+                        const double *qL = box + cix(c[0], c[1], c[2]) * NV;
+                        const double *qI = box + cix(ci[0], ci[1], ci[2]) * NV;
+                        const double *q0 = bg + cix(c[0], c[1], c[2]) * NV;
+                        double *o = out + cix(c[0], c[1], c[2]) * NV;
+                        for (v = 0; v < 58; v++) {
+                            if (frozen_slot(pr, v)) { o[v] = 0.0; continue; }
+                            o[v] = -1.0 * (r / fabs(xx[a])) * (qL[v] - qI[v]) / dx[a] -
+                                   (1.0 / r) * (qL[v] - q0[v]);
+                        }
+                        o[58] = 0.0;
+                    }
+        }
+}
+
+void orc_rhs_subset(const orc_mesh *m, const orc_params *pr, const double *Q, double *kout,
+                    int64_t n_sel, const int64_t *sel)
+{
+    int64_t s;
+    for (s = 0; s < n_sel; s++) {
+        int64_t p = sel[s];
+        double org[3], dx[3];
+        const double *box = Q + p * (int64_t)ORC_BOXCELLS * NV;
+        double *out = kout + p * (int64_t)ORC_BOXCELLS * NV;
+        patch_geom(m, p, org, dx);
+        orc_rhs_box(pr, dx, box, out);
+        sommerfeld_box(m, pr, p, box, out);
+    }
+}
+
+void orc_rhs(const orc_mesh *m, const orc_params *pr, const double *Q, double *kout)
+{
+    int64_t p;
+    for (p = 0; p < m->np; p++) orc_rhs_subset(m, pr, Q, kout, 1, &p);
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Algebraic constraints det(gt) = 1 and tr(At) = 0 enforced pointwise after a time step
+ * (the paper's post-processing): gt <- gt / det(gt)^(1/3), then At <- At - gt (gt^kl At_kl)/3
+ * with the rescaled metric.
+ * ---------------------------------------------------------------------------------------- */
+void orc_project_point(double *q)
+{
+    double g[3][3], ig[3][3], d, s, tr = 0;
+    int i, j;
+    static const int si[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+    for (i = 0; i < 3; i++)
+        for (j = 0; j < 3; j++) g[i][j] = q[si[i][j]];
+    d = g[0][0] * (g[1][1] * g[2][2] - g[1][2] * g[2][1]) -
+        g[0][1] * (g[1][0] * g[2][2] - g[1][2] * g[2][0]) +
+        g[0][2] * (g[1][0] * g[2][1] - g[1][1] * g[2][0]);
+    s = 1.0 / cbrt(d);
+    for (i = 0; i < 3; i++)
+        for (j = 0; j < 3; j++) g[i][j] *= s;
+    d = g[0][0] * (g[1][1] * g[2][2] - g[1][2] * g[2][1]) -
+        g[0][1] * (g[1][0] * g[2][2] - g[1][2] * g[2][0]) +
+        g[0][2] * (g[1][0] * g[2][1] - g[1][1] * g[2][0]);
+    ig[0][0] = (g[1][1] * g[2][2] - g[1][2] * g[2][1]) / d;
+    ig[0][1] = (g[0][2] * g[2][1] - g[0][1] * g[2][2]) / d;
+    ig[0][2] = (g[0][1] * g[1][2] - g[0][2] * g[1][1]) / d;
+    ig[1][0] = (g[1][2] * g[2][0] - g[1][0] * g[2][2]) / d;
+    ig[1][1] = (g[0][0] * g[2][2] - g[0][2] * g[2][0]) / d;
+    ig[1][2] = (g[0][2] * g[1][0] - g[0][0] * g[1][2]) / d;
+    ig[2][0] = (g[1][0] * g[2][1] - g[1][1] * g[2][0]) / d;
+    ig[2][1] = (g[0][1] * g[2][0] - g[0][0] * g[2][1]) / d;
+    ig[2][2] = (g[0][0] * g[1][1] - g[0][1] * g[1][0]) / d;
+    for (i = 0; i < 3; i++)
+        for (j = 0; j < 3; j++) tr += ig[i][j] * q[11 + si[i][j]];
+    for (i = 0; i < 3; i++)
+        for (j = i; j < 3; j++) {
+            q[si[i][j]] = g[i][j];
+            q[11 + si[i][j]] -= g[i][j] * tr / 3.0;
+        }
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Classical RK4 (the paper allows Runge-Kutta up to order four; the classical tableau is
+ * the reading here), in two-register form over interior cells and Sommerfeld ghosts:
+ *   s=0: acc = Qn + dt/6 k0, Qnext = Qn + dt/2 k0
+ *   s=1: acc += dt/3 k1,     Qnext = Qn + dt/2 k1
+ *   s=2: acc += dt/3 k2,     Qnext = Qn + dt k2
+ *   s=3: Qnext = acc + dt/6 k3, then the projection on interior cells.
+ * ---------------------------------------------------------------------------------------- */
+int orc_rk4_stage(const orc_mesh *m, int s, double dt, const double *Qn, const double *k,
+                  double *acc, double *Qnext)
+{
+    static const double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    static const double aw[3] = {0.5, 0.5, 1.0};
+    int64_t p;
+    int x, y, z, v;
+    if (s < 0 || s > 3 || !(dt > 0)) return -1;
+    for (p = 0; p < m->np; p++)
+        for (z = 0; z < NB; z++)
+            for (y = 0; y < NB; y++)
+                for (x = 0; x < NB; x++) {
+                    int c[3] = {x, y, z}, a, nin = 0, active = 0;
+                    for (a = 0; a < 3; a++) nin += (c[a] >= HH && c[a] < HH + PP);
+                    if (nin == 3) active = 1;
+                    else if (nin == 2 && m->bc == ORC_BC_SOMMERFELD)
+                        for (a = 0; a < 3; a++) {
+                            if (c[a] < HH && on_phys_boundary(m, p, a, -1)) active = 1;
+                            if (c[a] >= HH + PP && on_phys_boundary(m, p, a, 1)) active = 1;
+                        }
+                    if (!active) continue;
+                    int64_t o = (p * (int64_t)ORC_BOXCELLS + cix(x, y, z)) * NV;
+                    for (v = 0; v < NV; v++) {
+                        if (s == 0) acc[o + v] = Qn[o + v] + bw[0] * dt * k[o + v];
+                        else if (s < 3) acc[o + v] = acc[o + v] + bw[s] * dt * k[o + v];
+                        if (s < 3) Qnext[o + v] = Qn[o + v] + aw[s] * dt * k[o + v];
+                        else Qnext[o + v] = acc[o + v] + bw[3] * dt * k[o + v];
+                    }
+                    if (s == 3 && nin == 3) orc_project_point(Qnext + o);
+                }
+    return 0;
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Constraint monitor: H and M_i on every interior leaf cell, the norms
+ * L2(H) = sqrt(sum H^2 / n) (the paper's L2 error of the Hamiltonian constraint with
+ * H_theoretical = 0) and L2(|M|) = sqrt(sum |M|^2 / n) over cells with r >= r_excise, and the
+ * count of cells with a non-finite state slot or constraint.  Returns that count.
+ * ---------------------------------------------------------------------------------------- */
+int64_t orc_constraints(const orc_mesh *m, const double *Q, double *HM, double r_excise,
+                        double norms[3])
+{
+    int64_t p, nbad = 0, ncell = 0;
+    double sH = 0, sM = 0;
+    double *hm = (double *)malloc(sizeof(double) * 729 * 4);
+    for (p = 0; p < m->np; p++) {
+        double org[3], dx[3];
+        const double *box = Q + p * (int64_t)ORC_BOXCELLS * NV;
+        int x, y, z, n = 0, v;
+        patch_geom(m, p, org, dx);
+        orc_constraints_box(dx, box, hm);
+        for (z = HH; z < HH + PP; z++)
+            for (y = HH; y < HH + PP; y++)
+                for (x = HH; x < HH + PP; x++, n++) {
+                    double xx[3], r;
+                    int bad = 0;
+                    const double *q = box + cix(x, y, z) * NV;
+                    for (v = 0; v < NV; v++) bad |= !isfinite(q[v]);
+                    for (v = 0; v < 4; v++) bad |= !isfinite(hm[4 * n + v]);
+                    nbad += bad;
+                    if (HM) memcpy(HM + (p * 729 + n) * 4, hm + 4 * n, sizeof(double) * 4);
+                    cell_center(m, p, x, y, z, xx);
+                    r = sqrt(xx[0] * xx[0] + xx[1] * xx[1] + xx[2] * xx[2]);
+                    if (r < r_excise || bad) continue;
+                    sH += hm[4 * n] * hm[4 * n];
+                    sM += hm[4 * n + 1] * hm[4 * n + 1] + hm[4 * n + 2] * hm[4 * n + 2] +
+                          hm[4 * n + 3] * hm[4 * n + 3];
+                    ncell++;
+                }
+    }
+    free(hm);
+    norms[0] = ncell ? sqrt(sH / ncell) : 0.0;
+    norms[1] = ncell ? sqrt(sM / ncell) : 0.0;
+    norms[2] = (double)nbad;
+    return nbad;
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Plain refinement indicator per leaf: the paper's feature-based criterion (largest
+ * difference between two adjacent volumes of a patch) applied to chi = phi^2 and alpha,
+ * and a constraint term dx^2 max|H| over the patch interior.
+ *   ind[p] = (max adjacent |d chi|, max adjacent |d alpha|, dx^2 max |H|)
+ * Tags: e = max of the three; REFINE (+1) if e >= theta_r and lev < max_level; COARSEN (-1)
+ * if lev > 0, e < theta_c, and all 27 siblings are leaves with e < theta_c; else KEEP (0).
+ * ---------------------------------------------------------------------------------------- */
+void orc_tag_indicator(const orc_mesh *m, const double *Q, double *ind)
+{
+    int64_t p;
+    double *hm = (double *)malloc(sizeof(double) * 729 * 4);
+    for (p = 0; p < m->np; p++) {
+        double org[3], dx[3], gc = 0, ga = 0, hmax = 0;
+        const double *box = Q + p * (int64_t)ORC_BOXCELLS * NV;
+        int x, y, z, a, n;
+        patch_geom(m, p, org, dx);
+        for (z = HH; z < HH + PP; z++)
+            for (y = HH; y < HH + PP; y++)
+                for (x = HH; x < HH + PP; x++)
+                    for (a = 0; a < 3; a++) {
+                        int c2[3] = {x, y, z};
+                        c2[a] += 1;
+                        if (c2[a] >= HH + PP) continue;
+                        const double *q1 = box + cix(x, y, z) * NV;
+                        const double *q2 = box + cix(c2[0], c2[1], c2[2]) * NV;
+                        double dc = fabs(q2[10] * q2[10] - q1[10] * q1[10]);
+                        double da = fabs(q2[6] - q1[6]);
+                        if (dc > gc) gc = dc;
+                        if (da > ga) ga = da;
+                    }
+        orc_constraints_box(dx, box, hm);
+        for (n = 0; n < 729; n++)
+            if (fabs(hm[4 * n]) > hmax) hmax = fabs(hm[4 * n]);
+        ind[3 * p] = gc;
+        ind[3 * p + 1] = ga;
+        ind[3 * p + 2] = dx[0] * dx[0] * hmax;
+    }
+    free(hm);
+}
+
+void orc_tag_refine(const orc_mesh *m, const double *Q, double theta_r, double theta_c,
+                    int max_level, int8_t *tags)
+{
+    int64_t p;
+    double *ind = (double *)malloc(sizeof(double) * 3 * (m->np ? m->np : 1));
+    double *e = (double *)malloc(sizeof(double) * (m->np ? m->np : 1));
+    orc_tag_indicator(m, Q, ind);
+    for (p = 0; p < m->np; p++) {
+        double v = ind[3 * p];
+        if (ind[3 * p + 1] > v) v = ind[3 * p + 1];
+        if (ind[3 * p + 2] > v) v = ind[3 * p + 2];
+        e[p] = v;
+    }
+    for (p = 0; p < m->np; p++) {
+        int lev = m->id[4 * p];
+        tags[p] = 0;
+        if (e[p] >= theta_r) { if (lev < max_level) tags[p] = 1; continue; }
+        if (lev > 0 && e[p] < theta_c) {
+            int ok = 1, u, v, w;
+            int pi = m->id[4 * p + 1] / 3, pj = m->id[4 * p + 2] / 3, pk = m->id[4 * p + 3] / 3;
+            for (w = 0; w < 3 && ok; w++)
+                for (v = 0; v < 3 && ok; v++)
+                    for (u = 0; u < 3 && ok; u++) {
+                        int64_t s = find_leaf(m, lev, 3 * pi + u, 3 * pj + v, 3 * pk + w);
+                        if (s < 0 || !(e[s] < theta_c)) ok = 0;
+                    }
+            if (ok) tags[p] = -1;
+        }
+    }
+    free(ind);
+    free(e);
+}

@@ -1,0 +1,106 @@
+/*
+ * ccz4_oracle.h -- plain FP64 CPU oracle for the first-order CCZ4 FD4 + Kreiss-Oliger
+ * hot path of "ExaGRyPE: Numerical General Relativity Solvers Based upon the Hyperbolic
+ * PDEs Solver Engine ExaHyPE" (arXiv:2406.11626).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may include, link or call this
+ * code; only the test-suite, the smoke check and the CPU-baseline leg of the benchmark use it.
+ * It shares no code with the HIP path.
+ *
+ * Conventions (oracle's own):
+ *   - 59 slots per cell: the 58 first-order variables in the order of the paper's eq.
+ *     (first-order-variables) -- gt_ij(6) alpha beta^i(3) phi At_ij(6) K Theta Ghat^i(3)
+ *     b^i(3) A_k(3) B_k^i(9, slot 28+3k+i) D_kij(18, slot 37+6k+sym(ij)) P_k(3) -- plus
+ *     slot 58 = K_0 (the constant of the slicing condition, never evolved).
+ *   - symmetric pairs ordered xx,xy,xz,yy,yz,zz.
+ *   - a patch box is 15^3 cells (9^3 interior + 3 halo layers per face), stored
+ *     cell-major: box[(z*15 + y)*15 + x][slot]  (array-of-structures).
+ */
+#ifndef CCZ4_ORACLE_H
+#define CCZ4_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_NV 59
+#define ORC_P 9
+#define ORC_H 3
+#define ORC_NB 15
+#define ORC_BOXCELLS (ORC_NB * ORC_NB * ORC_NB)
+
+typedef struct {
+    double kappa1, kappa2, kappa3; /* Z4 damping (kappa1, kappa2) and kappa3 of the Gamma eq. */
+    double tau;                    /* relaxation time of det(gt)=1 */
+    double e;                      /* Hamiltonian-constraint cleaning speed */
+    double c;                      /* CCZ4 source switch c */
+    double mu;                     /* constraint-term weight in the B equation */
+    double f, eta;                 /* Gamma-driver parameters */
+    double ko_eps;                 /* Kreiss-Oliger strength epsilon */
+    int slicing;                   /* 0: harmonic g(alpha)=1, 1: 1+log g(alpha)=2/alpha */
+    int shift;                     /* 0: frozen (static) shift, 1: Gamma-driver (s=1) */
+} orc_params;
+
+/* ---- pointwise algebra (App. B) ---- */
+void orc_rhs_point(const orc_params *pr, const double *q, const double *dq /* [3][59] */,
+                   double *out /* [59] */);
+void orc_constraints_point(const double *q, const double *dq /* [3][59] */, double *hm /* [4] */);
+
+/* ---- one-dimensional stencils (App. D) ---- */
+double orc_fd4(const double *v5 /* Q--,Q-,Q,Q+,Q++ */, double dx);
+double orc_ko(const double *v7 /* Q---..Q+++ */, double dx, double eps);
+
+/* ---- one patch box with filled halos ---- */
+void orc_rhs_box(const orc_params *pr, const double dx[3], const double *box, double *out);
+void orc_constraints_box(const double dx[3], const double *box, double *hm /* [729][4] */);
+
+/* ---- mesh of patches ---- */
+typedef struct orc_mesh orc_mesh;
+
+enum { ORC_BC_PERIODIC = 0, ORC_BC_NEUMANN = 1, ORC_BC_SOMMERFELD = 2 };
+
+orc_mesh *orc_mesh_create(const int n0[3], const double origin[3], const double extent[3],
+                          int bc, int n_refined, const int *refined /* [n][4]: lev,i,j,k */);
+void orc_mesh_destroy(orc_mesh *m);
+int64_t orc_mesh_npatches(const orc_mesh *m);
+/* per leaf: lev, i, j, k */
+void orc_mesh_patch_ids(const orc_mesh *m, int *ids /* [n][4] */);
+/* per leaf: origin xyz (lower corner of the interior) and dx xyz */
+void orc_mesh_patch_geom(const orc_mesh *m, double *geom /* [n][6] */);
+
+/* scenario 0 gauge wave (sp: A, k); 1 single puncture (sp: M, x0,y0,z0, lapse kind);
+   2 Brill-Lindquist + Bowen-York (sp: m1,x1,y1,z1,Px1,Py1,Pz1, m2,...)  */
+int orc_init_point(int scenario, const double *sp, const double x[3], double *q /* [59] */);
+int orc_init(const orc_mesh *m, double *Q, int scenario, const double *sp);
+
+void orc_set_background(orc_mesh *m, const double *Q);
+void orc_fill_halos(const orc_mesh *m, double *Q);
+void orc_rhs(const orc_mesh *m, const orc_params *pr, const double *Q, double *kout);
+void orc_rhs_subset(const orc_mesh *m, const orc_params *pr, const double *Q, double *kout,
+                    int64_t n_sel, const int64_t *sel);
+int orc_rk4_stage(const orc_mesh *m, int s, double dt, const double *Qn, const double *k,
+                  double *acc, double *Qnext);
+void orc_project_point(double *q);
+int64_t orc_constraints(const orc_mesh *m, const double *Q, double *HM /* [n][729][4] or NULL */,
+                        double r_excise, double norms[3]);
+void orc_tag_indicator(const orc_mesh *m, const double *Q, double *ind /* [n][3] */);
+void orc_tag_refine(const orc_mesh *m, const double *Q, double theta_r, double theta_c,
+                    int max_level, int8_t *tags);
+
+/* ---- learned-indicator MLP, FP64 with BF16-rounded operands ---- */
+void orc_features(const orc_mesh *m, const double *Q, double *feat /* [n][81] */);
+double orc_bf16_round(double x);
+void orc_mlp_forward(int n, const double *x /* [n][81] */, const double *W1, const double *b1,
+                     const double *W2, const double *b2, const double *W3, const double *b3,
+                     double *h1, double *h2, double *logits);
+double orc_mlp_loss_grad(int n, const double *x, const int *labels, const double *W1,
+                         const double *b1, const double *W2, const double *b2, const double *W3,
+                         const double *b3, double *gW1, double *gb1, double *gW2, double *gb2,
+                         double *gW3, double *gb3);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
