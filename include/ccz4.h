@@ -1,0 +1,163 @@
+/*
+ * ccz4.h -- C ABI of the MI355X (gfx950) CCZ4 FD4 hot-path library.
+ *
+ * The library evaluates the first-order CCZ4 right-hand side of the Einstein equations
+ * (3+1 split; 1+log or harmonic slicing; Gamma-driver or frozen shift) with fourth-order
+ * central finite differences and Kreiss-Oliger dissipation on block-structured Cartesian
+ * patches, and combines the stages of the classical RK4 integrator.  Paper:
+ * "ExaGRyPE: Numerical General Relativity Solvers Based upon the Hyperbolic PDEs Solver
+ * Engine ExaHyPE" (arXiv:2406.11626): the evolution system and its closing relations are its
+ * App. B, the stencils its App. D, the coarse-fine transfer matrices its App. E, the patch
+ * and halo layout its section on spatial discretisation, the boundary treatment its section
+ * on boundary conditions.
+ *
+ * Conventions shared by every call:
+ *  - A state holds 59 double slots per cell: the 58 first-order variables in the paper's
+ *    order -- gt_ij(0-5) alpha(6) beta^i(7-9) phi(10) At_ij(11-16) K(17) Theta(18)
+ *    Ghat^i(19-21) b^i(22-24) A_k(25-27) B_k^i(28+3k+i) D_kij(37+6k+sym(ij)) P_k(55-57) --
+ *    plus slot 58 = K_0, the constant of the slicing condition.  Symmetric pairs are ordered
+ *    xx,xy,xz,yy,yz,zz.
+ *  - Device layout (the caller allocates with the size from ccz4_layout): one slot of
+ *    212400 doubles per leaf patch, leaves in canonical order (level, then k, j, i index);
+ *    inside a patch, slot-major boxes of 15 x 15 x 16 doubles: element (v, z, y, x) at
+ *    v*3600 + z*240 + y*16 + x, with x, y, z in 0..14, the 9^3 interior at 3..11 and 3 halo
+ *    layers per face; x = 15 is padding.  Edge and corner cells of the box are never read
+ *    or written.
+ *  - All pointers named Q, k, acc, Qn, Qnext, HM, tags, indicator are device pointers owned
+ *    by the caller; the library never frees caller memory.  `stream` is a hipStream_t (NULL:
+ *    the null stream).  Calls are asynchronous on `stream` unless stated otherwise.
+ *  - Every call returns a ccz4_status; on failure a message is available from
+ *    ccz4_last_error() (thread-local, valid until the next failing call of that thread).
+ *    Argument errors are reported before anything is launched.  Asynchronous device errors
+ *    surface at the next call that synchronises.
+ */
+#ifndef CCZ4_H
+#define CCZ4_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CCZ4_OK = 0,
+    CCZ4_EINVAL = 1,     /* invalid argument (null pointer, bad size or index, dt <= 0, ...) */
+    CCZ4_ENOMEM = 2,     /* host or device allocation inside the library failed */
+    CCZ4_ELAYOUT = 3,    /* mesh violates an assumption (e.g. a level jump > 1 across a face) */
+    CCZ4_EHIP = 4,       /* a HIP runtime call failed */
+    CCZ4_ENONFINITE = 5, /* ccz4_constraints found non-finite values (norms are still written) */
+    CCZ4_ESTATE = 6      /* call not valid in the context's current state */
+} ccz4_status;
+
+enum { CCZ4_BC_PERIODIC = 0, CCZ4_BC_NEUMANN = 1, CCZ4_BC_SOMMERFELD = 2 };
+enum { CCZ4_SLICING_HARMONIC = 0, CCZ4_SLICING_ONE_PLUS_LOG = 1 };
+enum { CCZ4_SHIFT_FROZEN = 0, CCZ4_SHIFT_GAMMA_DRIVER = 1 };
+enum { CCZ4_PREC_FP64 = 0, CCZ4_PREC_MIXED = 1 };
+enum { CCZ4_SCEN_GAUGE_WAVE = 0, CCZ4_SCEN_PUNCTURE = 1, CCZ4_SCEN_BL_BY = 2 };
+
+/* Parameters of App. B (kappa1..3, tau, e, c, mu, f, eta), the KO strength epsilon of
+   App. D, the slicing function g(alpha) (harmonic: 1; 1+log: 2/alpha) and the shift
+   condition (frozen: beta, b, B do not evolve; Gamma-driver: s = 1). */
+typedef struct {
+    double kappa1, kappa2, kappa3, tau, e, c, mu, f, eta, ko_eps;
+    int32_t slicing, shift;
+} ccz4_params;
+
+/* Forest of n0[0] x n0[1] x n0[2] level-0 cubes over [origin, origin + extent], every cube
+   holding a 9^3 patch.  A refined cube is split into 3^3 children (the paper's
+   tri-partitioning); `refined` lists every refined cube as (level, i, j, k) with indices
+   counted at that level.  Leaves carry data.  Faces between a leaf and finer leaves are
+   coupled by restriction, between a leaf and a coarser leaf by prolongation; leaves that
+   share a face may differ by one level at most.  bc applies to all six domain faces. */
+typedef struct {
+    int32_t n0[3];
+    double origin[3];
+    double extent[3];
+    int32_t bc;
+    int32_t n_refined;
+    const int32_t *refined; /* host array of n_refined x 4 int32, may be NULL if n_refined = 0 */
+} ccz4_grid_desc;
+
+typedef struct ccz4_ctx ccz4_ctx;
+
+/* Builds the leaf table, the face-task plan of the halo fill and the per-level spacings,
+   and uploads them to the current HIP device.  The context owns those tables only. */
+ccz4_status ccz4_create(ccz4_ctx **out, const ccz4_grid_desc *grid, const ccz4_params *prm);
+/* Frees the context (waits for the device).  NULL is accepted. */
+void ccz4_destroy(ccz4_ctx *ctx);
+/* Replaces the parameters used by later calls. */
+ccz4_status ccz4_set_params(ccz4_ctx *ctx, const ccz4_params *prm);
+
+/* n_patches: number of leaves; patch_doubles: doubles per patch slot (212400);
+   bytes_per_state: bytes of one state buffer (n_patches * patch_doubles * 8). */
+ccz4_status ccz4_layout(const ccz4_ctx *ctx, int64_t *n_patches, int64_t *patch_doubles,
+                        int64_t *bytes_per_state);
+/* Host copies of the leaf table: ids[n][4] = (level, i, j, k); geom[n][6] = lower corner of
+   the patch interior (x, y, z) and cell spacing (dx, dy, dz).  Either may be NULL. */
+ccz4_status ccz4_patch_table(const ccz4_ctx *ctx, int32_t *ids, double *geom);
+
+/* a1.  Pointwise initial data on every interior cell and, with the Sommerfeld condition, on
+   the ghost layers of domain-boundary faces (which are evolved, not filled).  Interior cells
+   are then projected (det gt = 1, tr At = 0).  Also records the Sommerfeld background Q_ini.
+   scenario / scen (host array of n_scen doubles):
+     CCZ4_SCEN_GAUGE_WAVE: {A, k}: H = 1 - A sin(k pi x) (paper's gauge-wave test, t = 0);
+     CCZ4_SCEN_PUNCTURE:   {M, x0, y0, z0, lapse}: psi = 1 + M/(2r), phi = psi^-2, gt = delta,
+                           K_ij = 0, beta = 0; lapse 0: psi^-2, 1: the paper's averaged lapse,
+                           2: (1 - M/2r)/(1 + M/2r);
+     CCZ4_SCEN_BL_BY:      {m, x, y, z, Px, Py, Pz} per hole, two holes: Brill-Lindquist
+                           conformal factor with Bowen-York curvature, K = 0, alpha = psi^-2.
+   Does not fill halos. */
+ccz4_status ccz4_init_patches(ccz4_ctx *ctx, double *Q, int32_t scenario, const double *scen,
+                              int32_t n_scen, void *stream);
+/* Records the Sommerfeld ghost values of Q as the background Q_ini (no-op for other bcs). */
+ccz4_status ccz4_set_background(ccz4_ctx *ctx, const double *Q, void *stream);
+
+/* a2.  Fills the six face halos of every leaf from the current values of Q: same-level copy
+   (periodic wrap included), homogeneous Neumann copied layer by layer outwards, restriction
+   of fine interiors into coarse halos (R_avg x R_avg x R_perp of App. E), then prolongation
+   of coarse interiors and restricted halos into fine halos (P_par x P_par x P_perp).
+   Sommerfeld ghosts are left untouched. */
+ccz4_status ccz4_fill_halos(ccz4_ctx *ctx, double *Q, void *stream);
+
+/* a3-a5 (+a9).  k = RHS(Q) on every interior cell: FD4 central derivatives of slots 11..57,
+   the pointwise first-order CCZ4 algebra of App. B, plus the Kreiss-Oliger sum over the axes
+   on the 58 evolved slots (frozen-shift slots get 0; slot 58 gets 0).  On Sommerfeld faces
+   the ghost slots receive G_L = -(r/|x_n|)(Q_L - Q_{L-1})/dx - (Q_L - Q_ini)/r.  Requires
+   filled halos; never modifies Q.  Q and k must not alias.  precision: CCZ4_PREC_FP64, or
+   CCZ4_PREC_MIXED (stencil differences in FP64, nonlinear algebra in FP32, the inverse
+   metric, det gt and every factor of 1/phi in FP64, result promoted to FP64). */
+ccz4_status ccz4_rhs(ccz4_ctx *ctx, const double *Q, double *k, int32_t precision, void *stream);
+
+/* a6.  Stage s (0..3) of classical RK4 in two-register form, on interior cells and
+   Sommerfeld ghosts:  s=0: acc = Qn + dt/6 k, Qnext = Qn + dt/2 k;  s=1: acc += dt/3 k,
+   Qnext = Qn + dt/2 k;  s=2: acc += dt/3 k, Qnext = Qn + dt k;  s=3: Qnext = acc + dt/6 k,
+   then gt <- gt/det(gt)^(1/3) and At <- At - gt tr(At)/3 on interior cells.  dt > 0.
+   Qnext may alias Qn only at s = 3. */
+ccz4_status ccz4_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double *Qn,
+                           const double *k, double *acc, double *Qnext, void *stream);
+
+/* a7.  Hamiltonian H = R + 2/3 K^2 - At_ij At^ij and momentum M_i (App. B) on every interior
+   cell (FD4 derivatives; requires filled halos).  HM (device, may be NULL) receives
+   HM[(p*4 + q)*729 + c] for q = H, Mx, My, Mz and interior cell c = (z*9 + y)*9 + x.
+   norms_host (host, may be NULL): {sqrt(sum H^2/n), sqrt(sum |M|^2/n), count of cells with a
+   non-finite slot or constraint}, sums over finite cells with r >= r_excise.  With
+   norms_host the call synchronises `stream` and returns CCZ4_ENONFINITE if the count is > 0. */
+ccz4_status ccz4_constraints(ccz4_ctx *ctx, const double *Q, double *HM, double r_excise,
+                             double *norms_host, void *stream);
+
+/* a8.  Plain refinement criterion per leaf (requires filled halos): indicator[p] =
+   (max |chi_a - chi_b|, max |alpha_a - alpha_b| over face-adjacent interior cells a, b with
+   chi = phi^2, dx^2 max |H|) and e = the largest of the three.  tags[p] = +1 (refine) if
+   e >= theta_r and level < max_level; -1 (coarsen) if level > 0, e < theta_c and all 27
+   siblings are leaves with e < theta_c; else 0.  indicator (device, n x 3) may be NULL. */
+ccz4_status ccz4_tag_refine(ccz4_ctx *ctx, const double *Q, double theta_r, double theta_c,
+                            int32_t max_level, int8_t *tags, double *indicator, void *stream);
+
+/* Message of the last failing call of this thread ("" if none). */
+const char *ccz4_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,259 @@
+"""ctypes binding of libccz4.so (include/ccz4.h).  Argument marshalling only: every step of
+the path runs in the HIP kernels of the library.  Device buffers are torch tensors (float64,
+CUDA/HIP device) or raw device addresses; streams are torch streams or raw hipStream_t.
+
+The module-level functions carry the C names; ``Context`` bundles them around one handle.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libccz4.so")
+
+PATCH_DOUBLES = 212400
+NV = 59
+
+CCZ4_OK, CCZ4_EINVAL, CCZ4_ENOMEM, CCZ4_ELAYOUT, CCZ4_EHIP, CCZ4_ENONFINITE, CCZ4_ESTATE = range(7)
+BC_PERIODIC, BC_NEUMANN, BC_SOMMERFELD = 0, 1, 2
+PREC_FP64, PREC_MIXED = 0, 1
+SCEN_GAUGE_WAVE, SCEN_PUNCTURE, SCEN_BL_BY = 0, 1, 2
+
+
+class CCZ4Error(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"ccz4 status {status}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("kappa1", ctypes.c_double), ("kappa2", ctypes.c_double), ("kappa3", ctypes.c_double),
+        ("tau", ctypes.c_double), ("e", ctypes.c_double), ("c", ctypes.c_double),
+        ("mu", ctypes.c_double), ("f", ctypes.c_double), ("eta", ctypes.c_double),
+        ("ko_eps", ctypes.c_double), ("slicing", ctypes.c_int32), ("shift", ctypes.c_int32),
+    ]
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [
+        ("n0", ctypes.c_int32 * 3), ("origin", ctypes.c_double * 3), ("extent", ctypes.c_double * 3),
+        ("bc", ctypes.c_int32), ("n_refined", ctypes.c_int32), ("refined", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+def params(**kw):
+    """Black-hole defaults of the paper (kappa1 = 0.1, kappa3 = 0.5, e = c = tau = 1, mu = 0.2,
+    f = 0.75), eta = 2, KO 0.1, 1+log slicing, Gamma-driver shift."""
+    d = dict(kappa1=0.1, kappa2=0.0, kappa3=0.5, tau=1.0, e=1.0, c=1.0, mu=0.2, f=0.75,
+             eta=2.0, ko_eps=0.1, slicing=1, shift=1)
+    d.update(kw)
+    return Params(**d)
+
+
+_lib = None
+
+
+def lib():
+    """Load libccz4.so; raise if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2406_11626_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        i32, i64, f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        sig = {
+            "ccz4_create": (i32, [ctypes.POINTER(P), ctypes.POINTER(GridDesc), ctypes.POINTER(Params)]),
+            "ccz4_destroy": (None, [P]),
+            "ccz4_set_params": (i32, [P, ctypes.POINTER(Params)]),
+            "ccz4_layout": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+            "ccz4_patch_table": (i32, [P, P, P]),
+            "ccz4_init_patches": (i32, [P, P, i32, P, i32, P]),
+            "ccz4_set_background": (i32, [P, P, P]),
+            "ccz4_fill_halos": (i32, [P, P, P]),
+            "ccz4_rhs": (i32, [P, P, P, i32, P]),
+            "ccz4_rk4_stage": (i32, [P, i32, f64, P, P, P, P, P]),
+            "ccz4_constraints": (i32, [P, P, P, f64, P, P]),
+            "ccz4_tag_refine": (i32, [P, P, f64, f64, i32, P, P, P]),
+            "ccz4_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        if not x.is_cuda:
+            raise ValueError("device tensor expected")
+        if not x.is_contiguous():
+            raise ValueError("contiguous tensor expected")
+        return x.data_ptr()
+    return ctypes.cast(x, ctypes.c_void_p).value
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _check(status):
+    if status != CCZ4_OK:
+        raise CCZ4Error(status, lib().ccz4_last_error().decode())
+    return status
+
+
+# ---------------------------------------------------------------- C names
+
+def ccz4_create(n0, origin, extent, bc, prm, refined=()):
+    ref = [int(v) for r in refined for v in r]
+    arr = (ctypes.c_int32 * max(len(ref), 1))(*ref)
+    g = GridDesc()
+    g.n0[:] = [int(v) for v in n0]
+    g.origin[:] = [float(v) for v in origin]
+    g.extent[:] = [float(v) for v in extent]
+    g.bc = int(bc)
+    g.n_refined = len(ref) // 4
+    g.refined = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+    h = ctypes.c_void_p()
+    _check(lib().ccz4_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(prm)))
+    return h
+
+
+def ccz4_destroy(h):
+    lib().ccz4_destroy(h)
+
+
+def ccz4_set_params(h, prm):
+    return _check(lib().ccz4_set_params(h, ctypes.byref(prm)))
+
+
+def ccz4_layout(h):
+    n, pd, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().ccz4_layout(h, ctypes.byref(n), ctypes.byref(pd), ctypes.byref(b)))
+    return n.value, pd.value, b.value
+
+
+def ccz4_patch_table(h):
+    import numpy as np
+    n = ccz4_layout(h)[0]
+    ids = np.zeros((n, 4), dtype=np.int32)
+    geom = np.zeros((n, 6))
+    _check(lib().ccz4_patch_table(h, ids.ctypes.data, geom.ctypes.data))
+    return ids, geom
+
+
+def ccz4_init_patches(h, Q, scenario, scen, stream=None):
+    arr = (ctypes.c_double * max(len(scen), 1))(*[float(v) for v in scen])
+    return _check(lib().ccz4_init_patches(h, _ptr(Q), int(scenario), ctypes.cast(arr, ctypes.c_void_p),
+                                          len(scen), _stream(stream)))
+
+
+def ccz4_set_background(h, Q, stream=None):
+    return _check(lib().ccz4_set_background(h, _ptr(Q), _stream(stream)))
+
+
+def ccz4_fill_halos(h, Q, stream=None):
+    return _check(lib().ccz4_fill_halos(h, _ptr(Q), _stream(stream)))
+
+
+def ccz4_rhs(h, Q, k, precision=PREC_FP64, stream=None):
+    return _check(lib().ccz4_rhs(h, _ptr(Q), _ptr(k), int(precision), _stream(stream)))
+
+
+def ccz4_rk4_stage(h, s, dt, Qn, k, acc, Qnext, stream=None):
+    return _check(lib().ccz4_rk4_stage(h, int(s), float(dt), _ptr(Qn), _ptr(k), _ptr(acc), _ptr(Qnext),
+                                       _stream(stream)))
+
+
+def ccz4_constraints(h, Q, HM=None, r_excise=0.0, want_norms=True, stream=None):
+    norms = (ctypes.c_double * 3)()
+    st = lib().ccz4_constraints(h, _ptr(Q), _ptr(HM), float(r_excise),
+                                ctypes.cast(norms, ctypes.c_void_p) if want_norms else None, _stream(stream))
+    if st not in (CCZ4_OK, CCZ4_ENONFINITE):
+        _check(st)
+    return (list(norms), st) if want_norms else (None, st)
+
+
+def ccz4_tag_refine(h, Q, theta_r, theta_c, max_level, tags, indicator=None, stream=None):
+    return _check(lib().ccz4_tag_refine(h, _ptr(Q), float(theta_r), float(theta_c), int(max_level), _ptr(tags),
+                                        _ptr(indicator), _stream(stream)))
+
+
+def ccz4_last_error():
+    return lib().ccz4_last_error().decode()
+
+
+# ---------------------------------------------------------------- convenience wrapper
+
+class Context:
+    """One mesh of patches on the current device; state buffers are caller-owned tensors."""
+
+    def __init__(self, n0, origin, extent, bc=BC_PERIODIC, prm=None, refined=()):
+        self.prm = prm if prm is not None else params()
+        self.h = ccz4_create(n0, origin, extent, bc, self.prm, refined)
+        self.n_patches, self.patch_doubles, self.bytes_per_state = ccz4_layout(self.h)
+        self.ids, self.geom = ccz4_patch_table(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            try:
+                _lib.ccz4_destroy(self.h)
+            except Exception:
+                pass
+            self.h = None
+
+    __del__ = close
+
+    def new_state(self, fill=0.0):
+        import torch
+        t = torch.empty((self.n_patches, NV, 15, 15, 16), dtype=torch.float64, device="cuda")
+        t.fill_(fill)
+        return t
+
+    def set_params(self, prm):
+        self.prm = prm
+        ccz4_set_params(self.h, prm)
+
+    def init_patches(self, Q, scenario, scen, stream=None):
+        ccz4_init_patches(self.h, Q, scenario, scen, stream)
+
+    def set_background(self, Q, stream=None):
+        ccz4_set_background(self.h, Q, stream)
+
+    def fill_halos(self, Q, stream=None):
+        ccz4_fill_halos(self.h, Q, stream)
+
+    def rhs(self, Q, k, precision=PREC_FP64, stream=None):
+        ccz4_rhs(self.h, Q, k, precision, stream)
+
+    def rk4_stage(self, s, dt, Qn, k, acc, Qnext, stream=None):
+        ccz4_rk4_stage(self.h, s, dt, Qn, k, acc, Qnext, stream)
+
+    def constraints(self, Q, HM=None, r_excise=0.0, stream=None):
+        return ccz4_constraints(self.h, Q, HM, r_excise, True, stream)
+
+    def tag_refine(self, Q, theta_r, theta_c, max_level, tags, indicator=None, stream=None):
+        ccz4_tag_refine(self.h, Q, theta_r, theta_c, max_level, tags, indicator, stream)
+
+    def rk4_step(self, Qn, dt, bufs, precision=PREC_FP64, stream=None):
+        """One RK4 step in place on Qn; bufs = (Qs, k, acc) work tensors of the state shape."""
+        Qs, k, acc = bufs
+        cur = Qn
+        for s in range(4):
+            self.fill_halos(cur, stream)
+            self.rhs(cur, k, precision, stream)
+            nxt = Qn if s == 3 else Qs
+            self.rk4_stage(s, dt, Qn, k, acc, nxt, stream)
+            cur = nxt

@@ -1,0 +1,503 @@
+// Host side of the C ABI (include/ccz4.h): leaf forest, face-task plan of the halo fill,
+// Sommerfeld boundary faces, sibling table of the refinement criterion, and the calls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <new>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/ccz4.h"
+#include "ccz4_kernels.hpp"
+
+using namespace ccz4;
+
+namespace {
+
+thread_local std::string g_err;
+
+ccz4_status fail(ccz4_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(CCZ4_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+    } while (0)
+
+inline uint64_t key(int lev, int i, int j, int k)
+{
+    return ((uint64_t)lev << 48) | ((uint64_t)(uint16_t)k << 32) | ((uint64_t)(uint16_t)j << 16) | (uint16_t)i;
+}
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    hipError_t upload(const std::vector<T> &v)
+    {
+        release();
+        n = v.size();
+        if (!n) return hipSuccess;
+        hipError_t e = hipMalloc((void **)&p, n * sizeof(T));
+        if (e != hipSuccess) { p = nullptr; return e; }
+        return hipMemcpy(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice);
+    }
+    hipError_t alloc(size_t cnt)
+    {
+        release();
+        n = cnt;
+        if (!n) return hipSuccess;
+        hipError_t e = hipMalloc((void **)&p, n * sizeof(T));
+        if (e != hipSuccess) p = nullptr;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+}  // namespace
+
+struct ccz4_ctx {
+    int device = 0;
+    int n0[3];
+    double origin[3], extent[3];
+    int bc;
+    RhsParams prm;
+    std::vector<std::array<int, 4>> leaf;     // lev, i, j, k
+    std::vector<PatchGeom> geom;
+    std::vector<FaceTask> phase1, phase2;     // copy/neumann/restrict, then prolong
+    std::vector<BoundaryFace> bface;
+    std::vector<uint8_t> bmask;
+    std::vector<int32_t> sib;
+    DevBuf<PatchGeom> d_geom;
+    DevBuf<FaceTask> d_ph1, d_ph2;
+    DevBuf<BoundaryFace> d_bf;
+    DevBuf<uint8_t> d_bmask;
+    DevBuf<int32_t> d_sib;
+    DevBuf<double> d_bg, d_part, d_out3, d_hm;
+    double *h_out3 = nullptr;  // pinned
+    bool bg_valid = false;
+};
+
+namespace {
+
+int level_n(const ccz4_ctx *c, int lev, int a)
+{
+    int n = c->n0[a];
+    for (int l = 0; l < lev; ++l) n *= 3;
+    return n;
+}
+
+ccz4_status build_plan(ccz4_ctx *c, const ccz4_grid_desc *g)
+{
+    std::unordered_set<uint64_t> refined;
+    int maxlev = 0;
+    for (int r = 0; r < g->n_refined; ++r) {
+        const int32_t *e = g->refined + 4 * r;
+        if (e[0] < 0 || e[0] > 12 || e[1] < 0 || e[2] < 0 || e[3] < 0)
+            return fail(CCZ4_EINVAL, "refined entry out of range");
+        refined.insert(key(e[0], e[1], e[2], e[3]));
+        maxlev = std::max(maxlev, e[0] + 1);
+    }
+    auto is_ref = [&](int l, int i, int j, int k) { return refined.count(key(l, i, j, k)) > 0; };
+    // leaves: level-0 cubes and the children of refined cubes whose ancestors are refined
+    std::vector<std::array<int, 4>> cubes;
+    for (int k = 0; k < c->n0[2]; ++k)
+        for (int j = 0; j < c->n0[1]; ++j)
+            for (int i = 0; i < c->n0[0]; ++i) cubes.push_back({0, i, j, k});
+    std::vector<std::array<int, 4>> leaves;
+    size_t head = 0;
+    while (head < cubes.size()) {
+        const auto cu = cubes[head++];
+        if (!is_ref(cu[0], cu[1], cu[2], cu[3])) {
+            leaves.push_back(cu);
+            continue;
+        }
+        for (int w = 0; w < 3; ++w)
+            for (int v = 0; v < 3; ++v)
+                for (int u = 0; u < 3; ++u) cubes.push_back({cu[0] + 1, 3 * cu[1] + u, 3 * cu[2] + v, 3 * cu[3] + w});
+    }
+    std::sort(leaves.begin(), leaves.end(), [](const std::array<int, 4> &a, const std::array<int, 4> &b) {
+        if (a[0] != b[0]) return a[0] < b[0];
+        if (a[3] != b[3]) return a[3] < b[3];
+        if (a[2] != b[2]) return a[2] < b[2];
+        return a[1] < b[1];
+    });
+    if (leaves.size() > (size_t)INT32_MAX / 4) return fail(CCZ4_EINVAL, "too many leaves");
+    c->leaf = leaves;
+    std::unordered_map<uint64_t, int> index;
+    for (size_t p = 0; p < leaves.size(); ++p)
+        index[key(leaves[p][0], leaves[p][1], leaves[p][2], leaves[p][3])] = (int)p;
+    auto find = [&](int l, int i, int j, int k) -> int {
+        auto it = index.find(key(l, i, j, k));
+        return it == index.end() ? -1 : it->second;
+    };
+    // geometry
+    c->geom.resize(leaves.size());
+    for (size_t p = 0; p < leaves.size(); ++p) {
+        PatchGeom &pg = c->geom[p];
+        pg.level = leaves[p][0];
+        pg.pad = 0;
+        for (int a = 0; a < 3; ++a) {
+            const double L = c->extent[a] / level_n(c, pg.level, a);
+            pg.org[a] = c->origin[a] + L * leaves[p][1 + a];
+            pg.dx[a] = L / PN;
+        }
+    }
+    // face tasks
+    c->phase1.clear();
+    c->phase2.clear();
+    c->bface.clear();
+    c->bmask.assign(leaves.size(), 0);
+    for (size_t p = 0; p < leaves.size(); ++p) {
+        const int lev = leaves[p][0];
+        for (int a = 0; a < 3; ++a)
+            for (int side = -1; side <= 1; side += 2) {
+                int n[3] = {leaves[p][1], leaves[p][2], leaves[p][3]};
+                n[a] += side;
+                const int na = level_n(c, lev, a);
+                FaceTask t{};
+                t.patch = (int)p;
+                t.axis = a;
+                t.side = side;
+                for (int s = 0; s < 9; ++s) t.src[s] = -1;
+                if (n[a] < 0 || n[a] >= na) {
+                    if (c->bc == CCZ4_BC_PERIODIC) {
+                        n[a] = (n[a] + na) % na;
+                    } else if (c->bc == CCZ4_BC_NEUMANN) {
+                        t.kind = FK_NEUMANN;
+                        c->phase1.push_back(t);
+                        continue;
+                    } else {
+                        BoundaryFace b{(int)p, a, side, (int)c->bface.size()};
+                        c->bface.push_back(b);
+                        c->bmask[p] |= (uint8_t)(1u << (2 * a + (side > 0 ? 1 : 0)));
+                        continue;
+                    }
+                }
+                const int nb = find(lev, n[0], n[1], n[2]);
+                if (nb >= 0) {
+                    t.kind = FK_COPY;
+                    t.src[0] = nb;
+                    c->phase1.push_back(t);
+                    continue;
+                }
+                // tangential axes in increasing order
+                const int b1 = a == 0 ? 1 : 0, b2 = a == 2 ? 1 : 2;
+                bool nbexists = lev == 0 || is_ref(lev - 1, n[0] / 3, n[1] / 3, n[2] / 3);
+                if (nbexists && is_ref(lev, n[0], n[1], n[2])) {
+                    t.kind = FK_RESTRICT;
+                    for (int u2 = 0; u2 < 3; ++u2)
+                        for (int u1 = 0; u1 < 3; ++u1) {
+                            int ci[3];
+                            ci[a] = 3 * n[a] + (side > 0 ? 0 : 2);
+                            ci[b1] = 3 * n[b1] + u1;
+                            ci[b2] = 3 * n[b2] + u2;
+                            const int kid = find(lev + 1, ci[0], ci[1], ci[2]);
+                            if (kid < 0)
+                                return fail(CCZ4_ELAYOUT, "level jump of more than one across a face");
+                            t.src[u2 * 3 + u1] = kid;
+                        }
+                    c->phase1.push_back(t);
+                    continue;
+                }
+                if (lev == 0) return fail(CCZ4_ELAYOUT, "face neighbour missing at level 0");
+                const int cp = find(lev - 1, n[0] / 3, n[1] / 3, n[2] / 3);
+                if (cp < 0) return fail(CCZ4_ELAYOUT, "level jump of more than one across a face");
+                t.kind = FK_PROLONG;
+                t.src[0] = cp;
+                t.o1 = n[b1] - 3 * (n[b1] / 3);
+                t.o2 = n[b2] - 3 * (n[b2] / 3);
+                c->phase2.push_back(t);
+            }
+    }
+    // siblings
+    c->sib.assign(leaves.size() * 27, -1);
+    for (size_t p = 0; p < leaves.size(); ++p) {
+        const int lev = leaves[p][0];
+        if (lev == 0) {
+            c->sib[p * 27] = -2;
+            continue;
+        }
+        const int pi = leaves[p][1] / 3, pj = leaves[p][2] / 3, pk = leaves[p][3] / 3;
+        for (int w = 0; w < 3; ++w)
+            for (int v = 0; v < 3; ++v)
+                for (int u = 0; u < 3; ++u)
+                    c->sib[p * 27 + (w * 3 + v) * 3 + u] = find(lev, 3 * pi + u, 3 * pj + v, 3 * pk + w);
+    }
+    (void)maxlev;
+    return CCZ4_OK;
+}
+
+RhsParams to_rhs(const ccz4_params *p)
+{
+    RhsParams r;
+    r.kappa1 = p->kappa1;
+    r.kappa2 = p->kappa2;
+    r.kappa3 = p->kappa3;
+    r.tau = p->tau;
+    r.e = p->e;
+    r.c = p->c;
+    r.mu = p->mu;
+    r.f = p->f;
+    r.eta = p->eta;
+    r.ko_eps = p->ko_eps;
+    r.slicing = p->slicing;
+    r.shift = p->shift;
+    return r;
+}
+
+ccz4_status check_params(const ccz4_params *p)
+{
+    if (!p) return fail(CCZ4_EINVAL, "params is NULL");
+    if (p->slicing != 0 && p->slicing != 1) return fail(CCZ4_EINVAL, "slicing must be 0 or 1");
+    if (p->shift != 0 && p->shift != 1) return fail(CCZ4_EINVAL, "shift must be 0 or 1");
+    if (!(p->tau > 0)) return fail(CCZ4_EINVAL, "tau must be > 0");
+    return CCZ4_OK;
+}
+
+inline hipStream_t S(void *s) { return (hipStream_t)s; }
+
+ccz4_status check_ptr(const void *p, const char *name)
+{
+    if (!p) return fail(CCZ4_EINVAL, std::string(name) + " is NULL");
+    if (((uintptr_t)p) % 8) return fail(CCZ4_EINVAL, std::string(name) + " is not 8-byte aligned");
+    return CCZ4_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ccz4_last_error(void) { return g_err.c_str(); }
+
+ccz4_status ccz4_create(ccz4_ctx **out, const ccz4_grid_desc *g, const ccz4_params *prm)
+{
+    if (!out) return fail(CCZ4_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!g) return fail(CCZ4_EINVAL, "grid is NULL");
+    ccz4_status st = check_params(prm);
+    if (st) return st;
+    for (int a = 0; a < 3; ++a) {
+        if (g->n0[a] <= 0 || g->n0[a] > 4096) return fail(CCZ4_EINVAL, "n0 out of range");
+        if (!(g->extent[a] > 0)) return fail(CCZ4_EINVAL, "extent must be > 0");
+    }
+    if (g->bc < 0 || g->bc > 2) return fail(CCZ4_EINVAL, "bc must be 0, 1 or 2");
+    if (g->n_refined < 0 || (g->n_refined > 0 && !g->refined)) return fail(CCZ4_EINVAL, "bad refined list");
+    ccz4_ctx *c = new (std::nothrow) ccz4_ctx();
+    if (!c) return fail(CCZ4_ENOMEM, "context allocation failed");
+    for (int a = 0; a < 3; ++a) {
+        c->n0[a] = g->n0[a];
+        c->origin[a] = g->origin[a];
+        c->extent[a] = g->extent[a];
+    }
+    c->bc = g->bc;
+    c->prm = to_rhs(prm);
+    hipError_t he = hipGetDevice(&c->device);
+    if (he != hipSuccess) {
+        delete c;
+        return fail(CCZ4_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
+    }
+    st = build_plan(c, g);
+    if (st) {
+        delete c;
+        return st;
+    }
+    const size_t nbf = c->bface.size();
+    const int64_t nblk = constraints_blocks((int32_t)c->leaf.size());
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = c->d_geom.upload(c->geom);
+    if (e == hipSuccess) e = c->d_ph1.upload(c->phase1);
+    if (e == hipSuccess) e = c->d_ph2.upload(c->phase2);
+    if (e == hipSuccess) e = c->d_bf.upload(c->bface);
+    if (e == hipSuccess) e = c->d_bmask.upload(c->bmask);
+    if (e == hipSuccess) e = c->d_sib.upload(c->sib);
+    if (e == hipSuccess) e = c->d_bg.alloc(nbf * NV * NFACE);
+    if (e == hipSuccess) e = c->d_part.alloc((size_t)nblk * 4);
+    if (e == hipSuccess) e = c->d_out3.alloc(4);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_out3, 4 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        ccz4_destroy(c);
+        return fail(e == hipErrorOutOfMemory ? CCZ4_ENOMEM : CCZ4_EHIP,
+                    std::string("device tables: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return CCZ4_OK;
+}
+
+void ccz4_destroy(ccz4_ctx *c)
+{
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    c->d_geom.release();
+    c->d_ph1.release();
+    c->d_ph2.release();
+    c->d_bf.release();
+    c->d_bmask.release();
+    c->d_sib.release();
+    c->d_bg.release();
+    c->d_part.release();
+    c->d_out3.release();
+    c->d_hm.release();
+    if (c->h_out3) (void)hipHostFree(c->h_out3);
+    delete c;
+}
+
+ccz4_status ccz4_set_params(ccz4_ctx *c, const ccz4_params *prm)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    ccz4_status st = check_params(prm);
+    if (st) return st;
+    c->prm = to_rhs(prm);
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_layout(const ccz4_ctx *c, int64_t *n_patches, int64_t *patch_doubles, int64_t *bytes)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    if (n_patches) *n_patches = (int64_t)c->leaf.size();
+    if (patch_doubles) *patch_doubles = PS;
+    if (bytes) *bytes = (int64_t)c->leaf.size() * PS * (int64_t)sizeof(double);
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_patch_table(const ccz4_ctx *c, int32_t *ids, double *geom)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    for (size_t p = 0; p < c->leaf.size(); ++p) {
+        if (ids)
+            for (int j = 0; j < 4; ++j) ids[4 * p + j] = c->leaf[p][j];
+        if (geom)
+            for (int a = 0; a < 3; ++a) {
+                geom[6 * p + a] = c->geom[p].org[a];
+                geom[6 * p + 3 + a] = c->geom[p].dx[a];
+            }
+    }
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_init_patches(ccz4_ctx *c, double *Q, int32_t scen, const double *sp, int32_t nsp, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    ccz4_status st = check_ptr(Q, "Q");
+    if (st) return st;
+    const int need = scen == CCZ4_SCEN_GAUGE_WAVE ? 2 : (scen == CCZ4_SCEN_PUNCTURE ? 5 : (scen == CCZ4_SCEN_BL_BY ? 14 : -1));
+    if (need < 0) return fail(CCZ4_EINVAL, "unknown scenario");
+    if (nsp < need || !sp) return fail(CCZ4_EINVAL, "too few scenario parameters");
+    InitArgs a{};
+    for (int i = 0; i < need; ++i) a.sp[i] = sp[i];
+    HIP_TRY(launch_init(Q, c->d_geom.p, c->d_bmask.p, (int32_t)c->leaf.size(), scen, a, S(stream)));
+    HIP_TRY(launch_capture_bg(Q, c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(), S(stream)));
+    c->bg_valid = true;
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_set_background(ccz4_ctx *c, const double *Q, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    ccz4_status st = check_ptr(Q, "Q");
+    if (st) return st;
+    HIP_TRY(launch_capture_bg(Q, c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(), S(stream)));
+    c->bg_valid = true;
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_fill_halos(ccz4_ctx *c, double *Q, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    ccz4_status st = check_ptr(Q, "Q");
+    if (st) return st;
+    HIP_TRY(launch_fill(Q, c->d_ph1.p, (int32_t)c->phase1.size(), S(stream)));
+    HIP_TRY(launch_fill(Q, c->d_ph2.p, (int32_t)c->phase2.size(), S(stream)));
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_rhs(ccz4_ctx *c, const double *Q, double *k, int32_t precision, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    ccz4_status st = check_ptr(Q, "Q");
+    if (!st) st = check_ptr(k, "k");
+    if (st) return st;
+    if (Q == k) return fail(CCZ4_EINVAL, "Q and k must not alias");
+    if (precision != CCZ4_PREC_FP64 && precision != CCZ4_PREC_MIXED) return fail(CCZ4_EINVAL, "bad precision");
+    if (!c->bface.empty() && !c->bg_valid)
+        return fail(CCZ4_ESTATE, "Sommerfeld background not set (call ccz4_init_patches or ccz4_set_background)");
+    HIP_TRY(launch_rhs(Q, k, c->d_geom.p, (int32_t)c->leaf.size(), c->prm, precision, S(stream)));
+    HIP_TRY(launch_rhs_sommerfeld(Q, k, c->d_geom.p, c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(),
+                                  c->prm.shift == 0, S(stream)));
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_rk4_stage(ccz4_ctx *c, int32_t s, double dt, const double *Qn, const double *k, double *acc,
+                           double *Qnext, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    if (s < 0 || s > 3) return fail(CCZ4_EINVAL, "stage must be 0..3");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(CCZ4_EINVAL, "dt must be finite and > 0");
+    ccz4_status st = check_ptr(Qn, "Qn");
+    if (!st) st = check_ptr(k, "k");
+    if (!st) st = check_ptr(acc, "acc");
+    if (!st) st = check_ptr(Qnext, "Qnext");
+    if (st) return st;
+    if (s < 3 && Qnext == Qn) return fail(CCZ4_EINVAL, "Qnext may alias Qn only at s = 3");
+    HIP_TRY(launch_rk4(s, dt, Qn, k, acc, Qnext, (int32_t)c->leaf.size(), c->d_bf.p, (int32_t)c->bface.size(),
+                       S(stream)));
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_constraints(ccz4_ctx *c, const double *Q, double *HM, double r_excise, double *norms, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    ccz4_status st = check_ptr(Q, "Q");
+    if (st) return st;
+    HIP_TRY(launch_constraints(Q, HM, c->d_geom.p, (int32_t)c->leaf.size(), r_excise, c->d_part.p, c->d_out3.p,
+                               S(stream)));
+    if (!norms) return CCZ4_OK;
+    HIP_TRY(hipMemcpyAsync(c->h_out3, c->d_out3.p, 3 * sizeof(double), hipMemcpyDeviceToHost, S(stream)));
+    HIP_TRY(hipStreamSynchronize(S(stream)));
+    for (int j = 0; j < 3; ++j) norms[j] = c->h_out3[j];
+    if (norms[2] > 0) return fail(CCZ4_ENONFINITE, "non-finite values in the state or the constraints");
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_tag_refine(ccz4_ctx *c, const double *Q, double theta_r, double theta_c, int32_t max_level,
+                            int8_t *tags, double *indicator, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    ccz4_status st = check_ptr(Q, "Q");
+    if (st) return st;
+    if (!tags) return fail(CCZ4_EINVAL, "tags is NULL");
+    const size_t np = c->leaf.size();
+    if (c->d_hm.n < np * 4 * NCELL) HIP_TRY(c->d_hm.alloc(np * 4 * NCELL));
+    double *ind = indicator;
+    DevBuf<double> tmp;
+    if (!ind) {
+        HIP_TRY(tmp.alloc(np * 3));
+        ind = tmp.p;
+    }
+    HIP_TRY(launch_constraints(Q, c->d_hm.p, c->d_geom.p, (int32_t)np, 0.0, c->d_part.p, c->d_out3.p, S(stream)));
+    HIP_TRY(launch_tags(Q, c->d_hm.p, c->d_geom.p, c->d_sib.p, (int32_t)np, theta_r, theta_c, max_level, tags, ind,
+                        S(stream)));
+    if (tmp.p) {
+        HIP_TRY(hipStreamSynchronize(S(stream)));
+        tmp.release();
+    }
+    return CCZ4_OK;
+}
+
+}  // extern "C"

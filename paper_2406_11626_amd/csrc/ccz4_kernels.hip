@@ -1,0 +1,639 @@
+// HIP kernels of the CCZ4 FD4 hot path for gfx950 (MI355X).
+//
+// State layout: per leaf patch, slot-major boxes of 15 x 15 x 16 doubles (see ccz4.h).
+// Every kernel maps one thread to one cell (or one halo cell) so that consecutive lanes walk
+// the contiguous x rows of a box.
+#include <hip/hip_runtime.h>
+
+#include "ccz4_algebra.hpp"
+#include "ccz4_kernels.hpp"
+#include "ccz4_rhs_phased.hpp"
+
+namespace ccz4 {
+
+// ------------------------------------------------------------------ initial data
+// Closed forms of the three scenarios at a point; the first-order auxiliaries are the
+// analytic derivatives (A = d alpha, B = d beta, D = d gt / 2, P = d phi).
+__device__ void init_point(int scen, const double *sp, double x, double y, double z, double *q)
+{
+    for (int v = 0; v < NV; ++v) q[v] = 0.0;
+    if (scen == 0) {
+        const double A = sp[0], kk = sp[1];
+        const double w = kk * M_PI;
+        const double Hh = 1.0 - A * sin(w * x);
+        const double dH = -A * w * cos(w * x);
+        const double sq = sqrt(Hh);
+        const double Kxx = dH / (2.0 * sq);
+        const double Hm13 = pow(Hh, -1.0 / 3.0);
+        q[SG + 0] = Hh * Hm13;
+        q[SG + 3] = Hm13;
+        q[SG + 5] = Hm13;
+        q[SALPHA] = sq;
+        q[SPHI] = pow(Hh, -1.0 / 6.0);
+        q[SAT + 0] = (2.0 / 3.0) * Hm13 * Kxx;
+        q[SAT + 3] = -(1.0 / 3.0) * Hm13 / Hh * Kxx;
+        q[SAT + 5] = q[SAT + 3];
+        q[SK] = Kxx / Hh;
+        q[SGHAT + 0] = (2.0 / 3.0) * Hm13 * Hm13 / Hh * dH;
+        q[SA + 0] = Kxx;
+        q[SD + 0] = (1.0 / 3.0) * Hm13 * dH;
+        q[SD + 3] = -(1.0 / 6.0) * Hm13 / Hh * dH;
+        q[SD + 5] = q[SD + 3];
+        q[SP + 0] = -(1.0 / 6.0) * q[SPHI] / Hh * dH;
+        return;
+    }
+    q[SG + 0] = q[SG + 3] = q[SG + 5] = 1.0;
+    if (scen == 1) {
+        const double M = sp[0];
+        const double rx = x - sp[1], ry = y - sp[2], rz = z - sp[3];
+        const double r = sqrt(rx * rx + ry * ry + rz * rz);
+        const double psi = 1.0 + 0.5 * M / r;
+        const double ipsi = 1.0 / psi;
+        const double f = 0.5 * M / (r * r * r);  // -d_k psi = f x_k
+        const double phi = ipsi * ipsi;
+        q[SPHI] = phi;
+        const double pk = 2.0 * phi * ipsi * f;  // d_k phi = -2 psi^-3 d_k psi
+        q[SP + 0] = pk * rx;
+        q[SP + 1] = pk * ry;
+        q[SP + 2] = pk * rz;
+        const int lapse = (int)sp[4];
+        if (lapse == 0) {
+            q[SALPHA] = phi;
+            q[SA + 0] = q[SP + 0];
+            q[SA + 1] = q[SP + 1];
+            q[SA + 2] = q[SP + 2];
+        } else {
+            const double as = (2.0 - psi) * ipsi;   // (1 - M/2r)/(1 + M/2r)
+            const double wgt = lapse == 1 ? 0.5 : 1.0;
+            q[SALPHA] = lapse == 1 ? 0.5 * (as + 1.0) : as;
+            const double ak = wgt * 2.0 * phi * f;  // d_k alpha_s = -2 psi^-2 d_k psi
+            q[SA + 0] = ak * rx;
+            q[SA + 1] = ak * ry;
+            q[SA + 2] = ak * rz;
+        }
+        return;
+    }
+    // two Brill-Lindquist holes with Bowen-York curvature
+    double psi = 1.0, dpsi[3] = {0.0, 0.0, 0.0}, Ah[6] = {0, 0, 0, 0, 0, 0};
+    for (int h = 0; h < 2; ++h) {
+        const double *s = sp + 7 * h;
+        const double d[3] = {x - s[1], y - s[2], z - s[3]};
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        const double r = sqrt(r2);
+        const double n[3] = {d[0] / r, d[1] / r, d[2] / r};
+        psi += 0.5 * s[0] / r;
+        for (int i = 0; i < 3; ++i) dpsi[i] -= 0.5 * s[0] * d[i] / (r2 * r);
+        const double Pn = s[4] * n[0] + s[5] * n[1] + s[6] * n[2];
+        const double c = 1.5 / r2;
+        for (int i = 0; i < 3; ++i)
+            for (int j = i; j < 3; ++j)
+                Ah[sym(i, j)] += c * (s[4 + i] * n[j] + s[4 + j] * n[i] - ((i == j) - n[i] * n[j]) * Pn);
+    }
+    const double ipsi = 1.0 / psi;
+    const double phi = ipsi * ipsi;
+    const double ip6 = phi * phi * phi;
+    q[SPHI] = phi;
+    q[SALPHA] = phi;
+    for (int i = 0; i < 3; ++i) {
+        q[SP + i] = -2.0 * phi * ipsi * dpsi[i];
+        q[SA + i] = q[SP + i];
+    }
+    for (int s = 0; s < 6; ++s) q[SAT + s] = ip6 * Ah[s];
+}
+
+// det gt = 1 by rescaling, then remove the trace of At with the rescaled metric
+__device__ void project_cell(double *q)
+{
+    const double det = q[0] * (q[3] * q[5] - q[4] * q[4]) - q[1] * (q[1] * q[5] - q[4] * q[2]) +
+                       q[2] * (q[1] * q[4] - q[3] * q[2]);
+    const double s = 1.0 / cbrt(det);
+    double g[6];
+    for (int v = 0; v < 6; ++v) g[v] = q[v] * s;
+    const double c00 = g[3] * g[5] - g[4] * g[4], c01 = g[2] * g[4] - g[1] * g[5], c02 = g[1] * g[4] - g[2] * g[3];
+    const double c11 = g[0] * g[5] - g[2] * g[2], c12 = g[1] * g[2] - g[0] * g[4], c22 = g[0] * g[3] - g[1] * g[1];
+    const double dn = g[0] * c00 + g[1] * c01 + g[2] * c02;
+    const double tr = (c00 * q[11] + c11 * q[14] + c22 * q[16] + 2.0 * (c01 * q[12] + c02 * q[13] + c12 * q[15])) / dn;
+    for (int v = 0; v < 6; ++v) {
+        q[v] = g[v];
+        q[11 + v] -= g[v] * tr * (1.0 / 3.0);
+    }
+}
+
+__global__ void k_init(double *__restrict__ Q, const PatchGeom *__restrict__ geom,
+                       const uint8_t *__restrict__ bmask, int32_t npatch, int32_t scen, InitArgs a)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)npatch * 3375) return;
+    const int p = (int)(t / 3375);
+    const int c = (int)(t % 3375);
+    const int x = c % 15, y = (c / 15) % 15, z = c / 225;
+    const int inx = (x >= 3 && x < 12), iny = (y >= 3 && y < 12), inz = (z >= 3 && z < 12);
+    const int nin = inx + iny + inz;
+    bool active = nin == 3;
+    if (nin == 2) {
+        // face-slab ghost: which face?  bmask bit (2*axis + (side>0)) marks Sommerfeld faces
+        const int axis = !inx ? 0 : (!iny ? 1 : 2);
+        const int cc = axis == 0 ? x : (axis == 1 ? y : z);
+        const int bit = 2 * axis + (cc >= 12 ? 1 : 0);
+        active = (bmask[p] >> bit) & 1;
+    }
+    if (!active) return;
+    const PatchGeom g = geom[p];
+    double q[NV];
+    init_point(scen, a.sp, g.org[0] + (x - 2.5) * g.dx[0], g.org[1] + (y - 2.5) * g.dx[1],
+               g.org[2] + (z - 2.5) * g.dx[2], q);
+    if (nin == 3) project_cell(q);
+    double *Qp = Q + (int64_t)p * PS + boff(x, y, z);
+    for (int v = 0; v < NV; ++v) Qp[(int64_t)v * CS] = q[v];
+}
+
+// ------------------------------------------------------------------ halo fill
+// One block per face task, one thread per halo cell of the 3 x 9 x 9 slab, loop over slots.
+// Axis a face: ghost layer L (1..3) sits at box coordinate 11 + L (side +1) or 3 - L (side -1);
+// interior depth d (1..3) from the face at 12 - d (side +1) or 2 + d (side -1).
+__device__ __forceinline__ int ghost_c(int side, int L) { return side > 0 ? 11 + L : 3 - L; }
+__device__ __forceinline__ int depth_c(int side, int d) { return side > 0 ? 12 - d : 2 + d; }
+
+// slab thread -> (layer L in 1..3, tangential t1, t2 in 0..8) with the lowest box axis fastest
+__device__ __forceinline__ void slab_coords(int axis, int idx, int &L, int &t1, int &t2)
+{
+    if (axis == 0) {  // layer index is the contiguous x
+        L = idx % 3 + 1;
+        t1 = (idx / 3) % 9;   // y
+        t2 = idx / 27;        // z
+    } else {
+        t1 = idx % 9;         // x
+        t2 = (idx / 9) % 9;   // z (axis 1) or y (axis 2)
+        L = idx / 81 + 1;
+    }
+}
+
+__device__ __forceinline__ int slab_off(int axis, int coordA, int t1, int t2)
+{
+    // t1/t2 are the tangential axes in increasing order: axis0 -> (y, z); axis1 -> (x, z); axis2 -> (x, y)
+    if (axis == 0) return boff(coordA, t1 + 3, t2 + 3);
+    if (axis == 1) return boff(t1 + 3, coordA, t2 + 3);
+    return boff(t1 + 3, t2 + 3, coordA);
+}
+
+// P_parallel row F (0..26) -> (first coarse index, weights w0, w1)
+__device__ __forceinline__ void ppar(int F, int &l, double &w0, double &w1)
+{
+    // u = (F + 1/2)/3 - 1/2 = (2F - 2)/6 ; l = clamp(floor(u), 0, 7)
+    const int num = F - 1;  // u = num / 3
+    int lf = num >= 0 ? num / 3 : -1;
+    l = lf < 0 ? 0 : (lf > 7 ? 7 : lf);
+    const double u = (double)num / 3.0;
+    w1 = u - l;
+    w0 = 1.0 - w1;
+}
+
+__global__ void k_fill(double *__restrict__ Q, const FaceTask *__restrict__ tasks, int32_t ntask)
+{
+    const int ti = blockIdx.x;
+    if (ti >= ntask) return;
+    const FaceTask tk = tasks[ti];
+    const int idx = threadIdx.x;
+    if (idx >= NFACE) return;
+    int L, t1, t2;
+    slab_coords(tk.axis, idx, L, t1, t2);
+    double *dst = Q + (int64_t)tk.patch * PS + slab_off(tk.axis, ghost_c(tk.side, L), t1, t2);
+    if (tk.kind == FK_COPY) {
+        const double *src = Q + (int64_t)tk.src[0] * PS + slab_off(tk.axis, depth_c(-tk.side, L), t1, t2);
+        for (int v = 0; v < NV; ++v) dst[v * CS] = src[v * CS];
+    } else if (tk.kind == FK_NEUMANN) {
+        const double *src = Q + (int64_t)tk.patch * PS + slab_off(tk.axis, depth_c(tk.side, 1), t1, t2);
+        for (int v = 0; v < NV; ++v) dst[v * CS] = src[v * CS];
+    } else if (tk.kind == FK_RESTRICT) {
+        // coarse ghost c_{2+L}; fine interior layers f3..f5 = depth 1..3 from the kid's face -side;
+        // R_perp rows: (1/3,1/3,1/3), (0,-2,3), (0,-5,6) over (f3,f4,f5); R_avg over 3x3 fine cells.
+        double wf[3];
+        if (L == 1) { wf[0] = wf[1] = wf[2] = 1.0 / 3.0; }
+        else if (L == 2) { wf[0] = 0.0; wf[1] = -2.0; wf[2] = 3.0; }
+        else { wf[0] = 0.0; wf[1] = -5.0; wf[2] = 6.0; }
+        // fine cells (F1, F2) in 3*t1..3*t1+2, 3*t2..3*t2+2 span kid (F/9)
+        const int k1 = (3 * t1) / 9, k2 = (3 * t2) / 9;
+        const double *kid = Q + (int64_t)tk.src[k2 * 3 + k1] * PS;
+        const int f1 = (3 * t1) % 9, f2 = (3 * t2) % 9;
+        for (int v = 0; v < NV; ++v) {
+            double acc = 0.0;
+            for (int m = 0; m < 3; ++m) {
+                if (wf[m] == 0.0) continue;
+                const int cA = depth_c(-tk.side, m + 1);
+                double s = 0.0;
+                for (int b2 = 0; b2 < 3; ++b2)
+                    for (int b1 = 0; b1 < 3; ++b1) s += kid[v * CS + slab_off(tk.axis, cA, f1 + b1, f2 + b2)];
+                acc += wf[m] * (s * (1.0 / 9.0));
+            }
+            dst[v * CS] = acc;
+        }
+    } else {  // FK_PROLONG
+        // fine ghost L -> f_{3-L}; P_perp rows over coarse (c0..c5):
+        // f0 = c1/3 + 2c2/3, f1 = c2, f2 = 2c2/3 + c3/3.  c0..c2: coarse interior depth 3..1 from
+        // the coarse face -side; c3..c5: coarse ghost 1..3 of that face.
+        const double *cp = Q + (int64_t)tk.src[0] * PS;
+        int cA[2];
+        double wA[2];
+        if (L == 3) { cA[0] = depth_c(-tk.side, 2); wA[0] = 1.0 / 3.0; cA[1] = depth_c(-tk.side, 1); wA[1] = 2.0 / 3.0; }
+        else if (L == 2) { cA[0] = depth_c(-tk.side, 1); wA[0] = 1.0; cA[1] = cA[0]; wA[1] = 0.0; }
+        else { cA[0] = depth_c(-tk.side, 1); wA[0] = 2.0 / 3.0; cA[1] = ghost_c(-tk.side, 1); wA[1] = 1.0 / 3.0; }
+        int l1, l2;
+        double a0, a1, b0, b1;
+        ppar(9 * tk.o1 + t1, l1, a0, a1);
+        ppar(9 * tk.o2 + t2, l2, b0, b1);
+        for (int v = 0; v < NV; ++v) {
+            double acc = 0.0;
+            for (int m = 0; m < 2; ++m) {
+                if (wA[m] == 0.0) continue;
+                const double *s = cp + v * CS;
+                const double r0 = a0 * s[slab_off(tk.axis, cA[m], l1, l2)] + a1 * s[slab_off(tk.axis, cA[m], l1 + 1, l2)];
+                const double r1 = a0 * s[slab_off(tk.axis, cA[m], l1, l2 + 1)] + a1 * s[slab_off(tk.axis, cA[m], l1 + 1, l2 + 1)];
+                acc += wA[m] * (b0 * r0 + b1 * r1);
+            }
+            dst[v * CS] = acc;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ right-hand side
+__device__ __forceinline__ bool frozen_slot(int v)
+{
+    return (v >= SBETA && v < SBETA + 3) || (v >= SBB && v < SBB + 3) || (v >= SB && v < SB + 9);
+}
+
+// Work-group -> (patch, z-slab of 3 planes) with the three slabs of a patch on one XCD:
+// consecutive block ids are dealt to the 8 XCDs in turn, so logical block L runs at physical
+// id (L % per) * 8 + L / per with per = grid / 8 (the grid is padded to a multiple of 8).
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk)
+{
+    const int64_t per = nblk / 8;
+    return (b % 8) * per + b / 8;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_rhs(const double *__restrict__ Q, double *__restrict__ K,
+                                             const PatchGeom *__restrict__ geom, int32_t npatch,
+                                             RhsParams prm)
+{
+    const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int p = (int)(lb / 3);
+    if (p >= npatch || threadIdx.x >= 243) return;
+    const int c = (int)(lb % 3) * 243 + threadIdx.x;
+    const PatchGeom g = geom[p];
+    CellRef cr;
+    cr.qb = Q + (int64_t)p * PS;
+    cr.kb = K + (int64_t)p * PS;
+    cr.o = boff(c % 9 + 3, (c / 9) % 9 + 3, c / 81 + 3);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cr.i12[a] = 1.0 / (12.0 * g.dx[a]);
+        cr.koc[a] = prm.ko_eps / (64.0 * g.dx[a]);
+    }
+    rhs_cell_phased<T>(cr, prm);
+}
+
+// Sommerfeld ghosts: one block per boundary face, one thread per ghost cell
+__global__ void k_rhs_sommerfeld(const double *__restrict__ Q, double *__restrict__ K,
+                                 const PatchGeom *__restrict__ geom, const BoundaryFace *__restrict__ bf,
+                                 const double *__restrict__ bg, int32_t nbf, int32_t frozen)
+{
+    const int fi = blockIdx.x;
+    if (fi >= nbf) return;
+    const int idx = threadIdx.x;
+    if (idx >= NFACE) return;
+    const BoundaryFace f = bf[fi];
+    int L, t1, t2;
+    slab_coords(f.axis, idx, L, t1, t2);
+    const int cg = ghost_c(f.side, L);
+    const int ci = L == 1 ? depth_c(f.side, 1) : ghost_c(f.side, L - 1);
+    const int og = slab_off(f.axis, cg, t1, t2), oi = slab_off(f.axis, ci, t1, t2);
+    const PatchGeom g = geom[f.patch];
+    int cx, cy, cz;
+    if (f.axis == 0) { cx = cg; cy = t1 + 3; cz = t2 + 3; }
+    else if (f.axis == 1) { cx = t1 + 3; cy = cg; cz = t2 + 3; }
+    else { cx = t1 + 3; cy = t2 + 3; cz = cg; }
+    const double X = g.org[0] + (cx - 2.5) * g.dx[0];
+    const double Y = g.org[1] + (cy - 2.5) * g.dx[1];
+    const double Z = g.org[2] + (cz - 2.5) * g.dx[2];
+    const double r = sqrt(X * X + Y * Y + Z * Z);
+    const double xn = f.axis == 0 ? X : (f.axis == 1 ? Y : Z);
+    const double cadv = r / (fabs(xn) * g.dx[f.axis]);
+    const double cdmp = 1.0 / r;
+    const double *Qp = Q + (int64_t)f.patch * PS;
+    double *Kp = K + (int64_t)f.patch * PS;
+    const double *B = bg + (int64_t)f.bg * NV * NFACE + idx;
+    for (int v = 0; v < NEVOL; ++v) {
+        if (frozen && frozen_slot(v)) { Kp[v * CS + og] = 0.0; continue; }
+        const double qL = Qp[v * CS + og];
+        Kp[v * CS + og] = -cadv * (qL - Qp[v * CS + oi]) - cdmp * (qL - B[v * NFACE]);
+    }
+    Kp[SK0 * CS + og] = 0.0;
+}
+
+__global__ void k_capture_bg(const double *__restrict__ Q, const BoundaryFace *__restrict__ bf,
+                             double *__restrict__ bg, int32_t nbf)
+{
+    const int fi = blockIdx.x;
+    if (fi >= nbf) return;
+    const int idx = threadIdx.x;
+    if (idx >= NFACE) return;
+    const BoundaryFace f = bf[fi];
+    int L, t1, t2;
+    slab_coords(f.axis, idx, L, t1, t2);
+    const int og = slab_off(f.axis, ghost_c(f.side, L), t1, t2);
+    const double *Qp = Q + (int64_t)f.patch * PS;
+    for (int v = 0; v < NV; ++v) bg[(int64_t)f.bg * NV * NFACE + v * NFACE + idx] = Qp[v * CS + og];
+}
+
+// ------------------------------------------------------------------ RK4 stage
+__device__ __forceinline__ void rk_combine(int s, double dt, const double *__restrict__ qn,
+                                           const double *__restrict__ kk, double *__restrict__ acc,
+                                           double *__restrict__ qx, int o, double *keep)
+{
+    // two-register classical RK4
+    constexpr double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    constexpr double aw[3] = {0.5, 0.5, 1.0};
+    for (int v = 0; v < NV; ++v) {
+        const int e = v * CS + o;
+        const double kv = kk[e];
+        if (s == 0) {
+            const double q0 = qn[e];
+            acc[e] = q0 + bw[0] * dt * kv;
+            qx[e] = q0 + aw[0] * dt * kv;
+        } else if (s < 3) {
+            acc[e] = acc[e] + bw[s] * dt * kv;
+            qx[e] = qn[e] + aw[s] * dt * kv;
+        } else {
+            const double r = acc[e] + bw[3] * dt * kv;
+            if (keep) keep[v] = r;
+            else qx[e] = r;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rk4(int32_t s, double dt, const double *__restrict__ Qn,
+                                             const double *__restrict__ Kk, double *__restrict__ acc,
+                                             double *__restrict__ Qx, int64_t ncell)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ncell) return;
+    const int p = (int)(t / NCELL);
+    const int c = (int)(t % NCELL);
+    const int o = boff(c % 9 + 3, (c / 9) % 9 + 3, c / 81 + 3);
+    const int64_t base = (int64_t)p * PS;
+    if (s < 3) {
+        rk_combine(s, dt, Qn + base, Kk + base, acc + base, Qx + base, o, nullptr);
+        return;
+    }
+    double q[NV];
+    rk_combine(s, dt, Qn + base, Kk + base, acc + base, Qx + base, o, q);
+    project_cell(q);
+    for (int v = 0; v < NV; ++v) Qx[base + v * CS + o] = q[v];
+}
+
+__global__ void k_rk4_ghost(int32_t s, double dt, const double *__restrict__ Qn, const double *__restrict__ Kk,
+                            double *__restrict__ acc, double *__restrict__ Qx, const BoundaryFace *__restrict__ bf,
+                            int32_t nbf)
+{
+    const int fi = blockIdx.x;
+    if (fi >= nbf) return;
+    const int idx = threadIdx.x;
+    if (idx >= NFACE) return;
+    const BoundaryFace f = bf[fi];
+    int L, t1, t2;
+    slab_coords(f.axis, idx, L, t1, t2);
+    const int og = slab_off(f.axis, ghost_c(f.side, L), t1, t2);
+    const int64_t base = (int64_t)f.patch * PS;
+    rk_combine(s, dt, Qn + base, Kk + base, acc + base, Qx + base, og, nullptr);
+}
+
+// ------------------------------------------------------------------ constraints
+// H = R + 2/3 K^2 - At_ij At^ij with R = phi^2 gt^ij R_ij;
+// M_i = gt^kl (d_k At_li - Gt^m_li At_km - Gt^m_lk At_im - 3 At_ik P_l/phi) - 2/3 d_i K.
+__global__ __launch_bounds__(128) void k_constraints(const double *__restrict__ Q, double *__restrict__ HM,
+                                                     const PatchGeom *__restrict__ geom, int64_t ncell,
+                                                     double r_excise, double *__restrict__ part)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double h2 = 0.0, m2 = 0.0, cnt = 0.0, bad = 0.0;
+    if (t < ncell) {
+        const int p = (int)(t / NCELL);
+        const int c = (int)(t % NCELL);
+        const int x = c % 9 + 3, y = (c / 9) % 9 + 3, z = c / 81 + 3;
+        const int o = boff(x, y, z);
+        const double *Qp = Q + (int64_t)p * PS + o;
+        const PatchGeom g = geom[p];
+        const int st[3] = {1, YS, ZS};
+        double q[NV];
+        bool fin = true;
+        for (int v = 0; v < NV; ++v) {
+            q[v] = Qp[v * CS];
+            fin = fin && isfinite(q[v]);
+        }
+        double dq[3][NDIFF];
+        for (int a = 0; a < 3; ++a) {
+            const double i12 = 1.0 / (12.0 * g.dx[a]);
+            const int s = st[a];
+            for (int v = DOFF; v < DOFF + NDIFF; ++v) {
+                const double *f = Qp + v * CS;
+                dq[a][v - DOFF] = (8.0 * (f[s] - f[-s]) - (f[2 * s] - f[-2 * s])) * i12;
+            }
+        }
+        double hm[4];
+        constraints_algebra(q, dq, hm);
+        for (int j = 0; j < 4; ++j) fin = fin && isfinite(hm[j]);
+        if (HM)
+            for (int j = 0; j < 4; ++j) HM[((int64_t)p * 4 + j) * NCELL + c] = hm[j];
+        const double X = g.org[0] + (x - 2.5) * g.dx[0], Y = g.org[1] + (y - 2.5) * g.dx[1],
+                     Z = g.org[2] + (z - 2.5) * g.dx[2];
+        const double r = sqrt(X * X + Y * Y + Z * Z);
+        if (!fin) bad = 1.0;
+        else if (r >= r_excise) {
+            h2 = hm[0] * hm[0];
+            m2 = hm[1] * hm[1] + hm[2] * hm[2] + hm[3] * hm[3];
+            cnt = 1.0;
+        }
+    }
+    // block reduction (deterministic order)
+    __shared__ double red[4][128];
+    red[0][threadIdx.x] = h2;
+    red[1][threadIdx.x] = m2;
+    red[2][threadIdx.x] = cnt;
+    red[3][threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = 64; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int j = 0; j < 4; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int j = 0; j < 4; ++j) part[(int64_t)blockIdx.x * 4 + j] = red[j][0];
+}
+
+__global__ void k_reduce_parts(const double *__restrict__ part, int64_t nblk, double *__restrict__ out)
+{
+    // one block of 256 threads: strided partial sums, then a tree
+    __shared__ double red[4][256];
+    double s[4] = {0, 0, 0, 0};
+    for (int64_t b = threadIdx.x; b < nblk; b += 256)
+        for (int j = 0; j < 4; ++j) s[j] += part[b * 4 + j];
+    for (int j = 0; j < 4; ++j) red[j][threadIdx.x] = s[j];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int j = 0; j < 4; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double n = red[2][0];
+        out[0] = n > 0 ? sqrt(red[0][0] / n) : 0.0;
+        out[1] = n > 0 ? sqrt(red[1][0] / n) : 0.0;
+        out[2] = red[3][0];
+    }
+}
+
+// ------------------------------------------------------------------ refinement tags
+// one block (256 threads) per leaf; HM must hold this leaf's H
+__global__ void k_tag_indicator(const double *__restrict__ Q, const double *__restrict__ HM,
+                                const PatchGeom *__restrict__ geom, double *__restrict__ ind)
+{
+    const int p = blockIdx.x;
+    const double *Qp = Q + (int64_t)p * PS;
+    double gc = 0.0, ga = 0.0, hm = 0.0;
+    for (int c = threadIdx.x; c < NCELL; c += blockDim.x) {
+        const int x = c % 9 + 3, y = (c / 9) % 9 + 3, z = c / 81 + 3;
+        const int o = boff(x, y, z);
+        const double ph = Qp[SPHI * CS + o], al = Qp[SALPHA * CS + o];
+        const double chi = ph * ph;
+        const int st[3] = {1, YS, ZS};
+        const int cc[3] = {x, y, z};
+        for (int a = 0; a < 3; ++a) {
+            if (cc[a] + 1 >= 12) continue;
+            const double ph2 = Qp[SPHI * CS + o + st[a]];
+            gc = fmax(gc, fabs(ph2 * ph2 - chi));
+            ga = fmax(ga, fabs(Qp[SALPHA * CS + o + st[a]] - al));
+        }
+        hm = fmax(hm, fabs(HM[(int64_t)p * 4 * NCELL + c]));
+    }
+    __shared__ double red[3][256];
+    red[0][threadIdx.x] = gc;
+    red[1][threadIdx.x] = ga;
+    red[2][threadIdx.x] = hm;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int j = 0; j < 3; ++j) red[j][threadIdx.x] = fmax(red[j][threadIdx.x], red[j][threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double dx = geom[p].dx[0];
+        ind[3 * p] = red[0][0];
+        ind[3 * p + 1] = red[1][0];
+        ind[3 * p + 2] = dx * dx * red[2][0];
+    }
+}
+
+// sib[p*27 + n]: the 27 sibling leaves of leaf p (-1 if a sibling is not a leaf); level-0 leaves
+// have no siblings (sib[p*27] = -2)
+__global__ void k_tag_decide(const double *__restrict__ ind, const int32_t *__restrict__ sib,
+                             const PatchGeom *__restrict__ geom, int32_t npatch, double theta_r,
+                             double theta_c, int32_t max_level, int8_t *__restrict__ tags)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npatch) return;
+    auto e_of = [&](int q) { return fmax(fmax(ind[3 * q], ind[3 * q + 1]), ind[3 * q + 2]); };
+    const double e = e_of(p);
+    const int lev = geom[p].level;
+    int8_t tg = 0;
+    if (e >= theta_r) tg = lev < max_level ? 1 : 0;
+    else if (lev > 0 && e < theta_c) {
+        bool ok = true;
+        for (int n = 0; n < 27 && ok; ++n) {
+            const int s = sib[(int64_t)p * 27 + n];
+            if (s < 0 || !(e_of(s) < theta_c)) ok = false;
+        }
+        tg = ok ? -1 : 0;
+    }
+    tags[p] = tg;
+}
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_init(double *Q, const PatchGeom *geom, const uint8_t *bmask, int32_t npatch, int32_t scen,
+                       const InitArgs &a, hipStream_t st)
+{
+    const int64_t n = (int64_t)npatch * 3375;
+    hipLaunchKernelGGL(k_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Q, geom, bmask, npatch, scen, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *Q, const FaceTask *tasks, int32_t ntask, hipStream_t st)
+{
+    if (ntask <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(ntask), dim3(256), 0, st, Q, tasks, ntask);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t npatch, const RhsParams &p,
+                      int32_t precision, hipStream_t st)
+{
+    const int64_t nb = ((int64_t)npatch * 3 + 7) / 8 * 8;
+    if (precision == 1)
+        hipLaunchKernelGGL(k_rhs<float>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p);
+    else
+        hipLaunchKernelGGL(k_rhs<double>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_sommerfeld(const double *Q, double *K, const PatchGeom *geom, const BoundaryFace *bf,
+                                 const double *bg, int32_t nbf, int32_t frozen, hipStream_t st)
+{
+    if (nbf <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rhs_sommerfeld, dim3(nbf), dim3(256), 0, st, Q, K, geom, bf, bg, nbf, frozen);
+    return hipGetLastError();
+}
+
+hipError_t launch_capture_bg(const double *Q, const BoundaryFace *bf, double *bg, int32_t nbf, hipStream_t st)
+{
+    if (nbf <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_capture_bg, dim3(nbf), dim3(256), 0, st, Q, bf, bg, nbf);
+    return hipGetLastError();
+}
+
+hipError_t launch_rk4(int32_t s, double dt, const double *Qn, const double *K, double *acc, double *Qx,
+                      int32_t npatch, const BoundaryFace *bf, int32_t nbf, hipStream_t st)
+{
+    const int64_t n = (int64_t)npatch * NCELL;
+    hipLaunchKernelGGL(k_rk4, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, dt, Qn, K, acc, Qx, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nbf <= 0) return e;
+    hipLaunchKernelGGL(k_rk4_ghost, dim3(nbf), dim3(256), 0, st, s, dt, Qn, K, acc, Qx, bf, nbf);
+    return hipGetLastError();
+}
+
+int64_t constraints_blocks(int32_t npatch) { return ((int64_t)npatch * NCELL + 127) / 128; }
+
+hipError_t launch_constraints(const double *Q, double *HM, const PatchGeom *geom, int32_t npatch,
+                              double r_excise, double *part, double *out3, hipStream_t st)
+{
+    const int64_t n = (int64_t)npatch * NCELL;
+    const int64_t nb = constraints_blocks(npatch);
+    hipLaunchKernelGGL(k_constraints, dim3((unsigned)nb), dim3(128), 0, st, Q, HM, geom, n, r_excise, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, part, nb, out3);
+    return hipGetLastError();
+}
+
+hipError_t launch_tags(const double *Q, const double *HM, const PatchGeom *geom, const int32_t *sib,
+                       int32_t npatch, double theta_r, double theta_c, int32_t max_level, int8_t *tags,
+                       double *ind, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tag_indicator, dim3(npatch), dim3(256), 0, st, Q, HM, geom, ind);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tag_decide, dim3((npatch + 127) / 128), dim3(128), 0, st, ind, sib, geom, npatch,
+                       theta_r, theta_c, max_level, tags);
+    return hipGetLastError();
+}
+
+}  // namespace ccz4

@@ -1,0 +1,31 @@
+// Launchers of the device kernels (implemented in ccz4_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ccz4_algebra.hpp"
+#include "ccz4_layout.hpp"
+
+namespace ccz4 {
+
+struct InitArgs {
+    double sp[16];
+};
+
+hipError_t launch_init(double *Q, const PatchGeom *geom, const uint8_t *bmask, int32_t npatch, int32_t scen,
+                       const InitArgs &a, hipStream_t st);
+hipError_t launch_fill(double *Q, const FaceTask *tasks, int32_t ntask, hipStream_t st);
+hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t npatch, const RhsParams &p,
+                      int32_t precision, hipStream_t st);
+hipError_t launch_rhs_sommerfeld(const double *Q, double *K, const PatchGeom *geom, const BoundaryFace *bf,
+                                 const double *bg, int32_t nbf, int32_t frozen, hipStream_t st);
+hipError_t launch_capture_bg(const double *Q, const BoundaryFace *bf, double *bg, int32_t nbf, hipStream_t st);
+hipError_t launch_rk4(int32_t s, double dt, const double *Qn, const double *K, double *acc, double *Qx,
+                      int32_t npatch, const BoundaryFace *bf, int32_t nbf, hipStream_t st);
+int64_t constraints_blocks(int32_t npatch);
+hipError_t launch_constraints(const double *Q, double *HM, const PatchGeom *geom, int32_t npatch,
+                              double r_excise, double *part, double *out3, hipStream_t st);
+hipError_t launch_tags(const double *Q, const double *HM, const PatchGeom *geom, const int32_t *sib,
+                       int32_t npatch, double theta_r, double theta_c, int32_t max_level, int8_t *tags,
+                       double *ind, hipStream_t st);
+
+}  // namespace ccz4

@@ -1,0 +1,53 @@
+// Layout constants and small helpers shared by the host planner and the device kernels.
+#pragma once
+#include <cstdint>
+
+namespace ccz4 {
+
+constexpr int NV = 59;          // 58 first-order variables + K_0
+constexpr int NEVOL = 58;       // evolved slots
+constexpr int PN = 9;           // interior cells per axis
+constexpr int HL = 3;           // halo layers per face
+constexpr int NBX = 15;         // box cells per axis
+constexpr int XS = 16;          // padded row length (doubles)
+constexpr int YS = XS;          // y stride
+constexpr int ZS = NBX * XS;    // z stride (240)
+constexpr int CS = NBX * ZS;    // slot stride (3600)
+constexpr int64_t PS = (int64_t)NV * CS; // patch stride (212400 doubles)
+constexpr int NCELL = PN * PN * PN;      // 729 interior cells
+constexpr int NFACE = 3 * PN * PN;       // 243 cells per face slab
+
+// slot map of the first-order variables
+__host__ __device__ constexpr int sym(int i, int j)
+{
+    return i <= j ? (i == 0 ? j : (i == 1 ? 2 + j : 5)) : (j == 0 ? i : (j == 1 ? 2 + i : 5));
+}
+constexpr int SG = 0, SALPHA = 6, SBETA = 7, SPHI = 10, SAT = 11, SK = 17, STHETA = 18,
+              SGHAT = 19, SBB = 22, SA = 25, SB = 28, SD = 37, SP = 55, SK0 = 58;
+
+// box offset of cell (x, y, z) inside one slot of a patch
+__host__ __device__ constexpr int boff(int x, int y, int z) { return z * ZS + y * YS + x; }
+
+// face-task kinds of the halo fill
+enum FaceKind : int32_t { FK_COPY = 0, FK_NEUMANN = 1, FK_RESTRICT = 2, FK_PROLONG = 3 };
+
+struct FaceTask {
+    int32_t kind;
+    int32_t patch;     // destination leaf
+    int32_t axis;      // 0, 1, 2
+    int32_t side;      // -1 or +1
+    int32_t src[9];    // COPY: src[0]; RESTRICT: 9 fine leaves [u2*3+u1]; PROLONG: src[0] coarse leaf
+    int32_t o1, o2;    // PROLONG: position of the fine patch inside the coarse face
+};
+
+struct BoundaryFace {  // a Sommerfeld face of a leaf and its background slab
+    int32_t patch, axis, side, bg;
+};
+
+struct PatchGeom {
+    double org[3];     // lower corner of the interior
+    double dx[3];
+    int32_t level, pad;
+};
+
+}  // namespace ccz4

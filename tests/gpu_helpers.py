@@ -1,0 +1,50 @@
+"""Helpers of the GPU parity tests: moving states between the oracle and the device layout,
+and the per-component error measure of the parity bar."""
+import numpy as np
+
+from seeded_inputs import from_device_layout, to_device_layout
+
+FACE_MASK = None
+
+
+def face_slab_mask():
+    m = np.zeros((15, 15, 15), bool)
+    inner = slice(3, 12)
+    for a in range(3):
+        for sl in (slice(0, 3), slice(12, 15)):
+            idx = [inner, inner, inner]
+            idx[2 - a] = sl
+            m[tuple(idx)] = True
+    return m
+
+
+SLABS = face_slab_mask()
+INTERIOR = np.zeros((15, 15, 15), bool)
+INTERIOR[3:12, 3:12, 3:12] = True
+
+
+def to_gpu(Qo):
+    import torch
+    return torch.from_numpy(to_device_layout(Qo)).cuda()
+
+
+def to_host(Qd, patches=None):
+    t = Qd if patches is None else Qd[patches]
+    return from_device_layout(t.cpu().numpy())
+
+
+FLOOR = 1e-3
+
+
+def parity_error(gpu, ref, mask=INTERIOR, nslots=59):
+    """Per-slot error of the parity bar over the masked cells:
+        e_c = max|gpu_c - ref_c| / max(max|ref_c|, FLOOR * max_c' max|ref_c'|).
+    Slots within three orders of magnitude of the largest one are measured relative to their
+    own size; smaller slots (cancellation residuals such as Theta of the gauge wave, whose
+    terms are 1e5 times larger than their sum) relative to FLOOR times the largest slot."""
+    g = gpu[:, mask][..., :nslots]
+    r = ref[:, mask][..., :nslots]
+    diff = np.abs(g - r).reshape(-1, nslots).max(0)
+    scale = np.abs(r).reshape(-1, nslots).max(0)
+    top = scale.max()
+    return diff / np.maximum(np.maximum(scale, FLOOR * top), 1e-300)
