@@ -97,7 +97,7 @@ ccz4_status ccz4_layout(const ccz4_ctx *ctx, int64_t *n_patches, int64_t *patch_
    the patch interior (x, y, z) and cell spacing (dx, dy, dz).  Either may be NULL. */
 ccz4_status ccz4_patch_table(const ccz4_ctx *ctx, int32_t *ids, double *geom);
 
-/* a1.  Pointwise initial data on every interior cell and, with the Sommerfeld condition, on
+/* Initial data.  Pointwise initial data on every interior cell and, with the Sommerfeld condition, on
    the ghost layers of domain-boundary faces (which are evolved, not filled).  Interior cells
    are then projected (det gt = 1, tr At = 0).  Also records the Sommerfeld background Q_ini.
    scenario / scen (host array of n_scen doubles):
@@ -113,14 +113,14 @@ ccz4_status ccz4_init_patches(ccz4_ctx *ctx, double *Q, int32_t scenario, const 
 /* Records the Sommerfeld ghost values of Q as the background Q_ini (no-op for other bcs). */
 ccz4_status ccz4_set_background(ccz4_ctx *ctx, const double *Q, void *stream);
 
-/* a2.  Fills the six face halos of every leaf from the current values of Q: same-level copy
+/* Halo fill.  Fills the six face halos of every leaf from the current values of Q: same-level copy
    (periodic wrap included), homogeneous Neumann copied layer by layer outwards, restriction
    of fine interiors into coarse halos (R_avg x R_avg x R_perp of App. E), then prolongation
    of coarse interiors and restricted halos into fine halos (P_par x P_par x P_perp).
    Sommerfeld ghosts are left untouched. */
 ccz4_status ccz4_fill_halos(ccz4_ctx *ctx, double *Q, void *stream);
 
-/* a3-a5 (+a9).  k = RHS(Q) on every interior cell: FD4 central derivatives of slots 11..57,
+/* Right-hand side.  k = RHS(Q) on every interior cell: FD4 central derivatives of slots 11..57,
    the pointwise first-order CCZ4 algebra of App. B, plus the Kreiss-Oliger sum over the axes
    on the 58 evolved slots (frozen-shift slots get 0; slot 58 gets 0).  On Sommerfeld faces
    the ghost slots receive G_L = -(r/|x_n|)(Q_L - Q_{L-1})/dx - (Q_L - Q_ini)/r.  Requires
@@ -129,7 +129,7 @@ ccz4_status ccz4_fill_halos(ccz4_ctx *ctx, double *Q, void *stream);
    metric, det gt and every factor of 1/phi in FP64, result promoted to FP64). */
 ccz4_status ccz4_rhs(ccz4_ctx *ctx, const double *Q, double *k, int32_t precision, void *stream);
 
-/* a6.  Stage s (0..3) of classical RK4 in two-register form, on interior cells and
+/* RK4 stage.  Stage s (0..3) of classical RK4 in two-register form, on interior cells and
    Sommerfeld ghosts:  s=0: acc = Qn + dt/6 k, Qnext = Qn + dt/2 k;  s=1: acc += dt/3 k,
    Qnext = Qn + dt/2 k;  s=2: acc += dt/3 k, Qnext = Qn + dt k;  s=3: Qnext = acc + dt/6 k,
    then gt <- gt/det(gt)^(1/3) and At <- At - gt tr(At)/3 on interior cells.  dt > 0.
@@ -137,7 +137,16 @@ ccz4_status ccz4_rhs(ccz4_ctx *ctx, const double *Q, double *k, int32_t precisio
 ccz4_status ccz4_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double *Qn,
                            const double *k, double *acc, double *Qnext, void *stream);
 
-/* a7.  Hamiltonian H = R + 2/3 K^2 - At_ij At^ij and momentum M_i (App. B) on every interior
+/* Fused stage.  One launch over every leaf of every level: the right-hand
+   side of Qs exactly as ccz4_rhs computes it, folded slot by slot into stage s of RK4 exactly as
+   ccz4_rk4_stage combines it (interior cells and Sommerfeld ghosts; projection at s = 3), without
+   storing the right-hand side.  Qs needs filled halos.  Qnext must not alias Qs (other cells
+   still read it), may alias Qn only at s = 3; acc aliases none of them.  A step is
+   s = 0: (Qn -> Q1), 1: (Q1 -> Q2), 2: (Q2 -> Q1), 3: (Q1 -> Qn), each after a halo fill. */
+ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double *Qs, const double *Qn,
+                               double *acc, double *Qnext, int32_t precision, void *stream);
+
+/* Constraint monitor.  Hamiltonian H = R + 2/3 K^2 - At_ij At^ij and momentum M_i (App. B) on every interior
    cell (FD4 derivatives; requires filled halos).  HM (device, may be NULL) receives
    HM[(p*4 + q)*729 + c] for q = H, Mx, My, Mz and interior cell c = (z*9 + y)*9 + x.
    norms_host (host, may be NULL): {sqrt(sum H^2/n), sqrt(sum |M|^2/n), count of cells with a
@@ -146,7 +155,7 @@ ccz4_status ccz4_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double *Qn
 ccz4_status ccz4_constraints(ccz4_ctx *ctx, const double *Q, double *HM, double r_excise,
                              double *norms_host, void *stream);
 
-/* a8.  Plain refinement criterion per leaf (requires filled halos): indicator[p] =
+/* Refinement tags.  Plain refinement criterion per leaf (requires filled halos): indicator[p] =
    (max |chi_a - chi_b|, max |alpha_a - alpha_b| over face-adjacent interior cells a, b with
    chi = phi^2, dx^2 max |H|) and e = the largest of the three.  tags[p] = +1 (refine) if
    e >= theta_r and level < max_level; -1 (coarsen) if level > 0, e < theta_c and all 27

@@ -13,23 +13,24 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
 
-def build(verbose=False):
+def build(verbose=False, out=OUT, defines=()):
     objs = []
     for src in SOURCES:
-        obj = os.path.join(CSRC, "_build", src + ".o")
+        tag = "".join(d.replace("=", "") for d in defines)
+        obj = os.path.join(CSRC, "_build", tag + src + ".o")
         os.makedirs(os.path.dirname(obj), exist_ok=True)
-        cmd = [HIPCC, "-x", "hip", *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, "-x", "hip", *FLAGS, *["-D" + d for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = OUT + ".tmp"
+    tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -73,6 +73,7 @@ def lib():
             "ccz4_fill_halos": (i32, [P, P, P]),
             "ccz4_rhs": (i32, [P, P, P, i32, P]),
             "ccz4_rk4_stage": (i32, [P, i32, f64, P, P, P, P, P]),
+            "ccz4_rhs_rk4_stage": (i32, [P, i32, f64, P, P, P, P, i32, P]),
             "ccz4_constraints": (i32, [P, P, P, f64, P, P]),
             "ccz4_tag_refine": (i32, [P, P, f64, f64, i32, P, P, P]),
             "ccz4_last_error": (ctypes.c_char_p, []),
@@ -177,6 +178,11 @@ def ccz4_rk4_stage(h, s, dt, Qn, k, acc, Qnext, stream=None):
                                        _stream(stream)))
 
 
+def ccz4_rhs_rk4_stage(h, s, dt, Qs, Qn, acc, Qnext, precision=PREC_FP64, stream=None):
+    return _check(lib().ccz4_rhs_rk4_stage(h, int(s), float(dt), _ptr(Qs), _ptr(Qn), _ptr(acc), _ptr(Qnext),
+                                           int(precision), _stream(stream)))
+
+
 def ccz4_constraints(h, Q, HM=None, r_excise=0.0, want_norms=True, stream=None):
     norms = (ctypes.c_double * 3)()
     st = lib().ccz4_constraints(h, _ptr(Q), _ptr(HM), float(r_excise),
@@ -246,6 +252,17 @@ class Context:
 
     def tag_refine(self, Q, theta_r, theta_c, max_level, tags, indicator=None, stream=None):
         ccz4_tag_refine(self.h, Q, theta_r, theta_c, max_level, tags, indicator, stream)
+
+    def rhs_rk4_stage(self, s, dt, Qs, Qn, acc, Qnext, precision=PREC_FP64, stream=None):
+        ccz4_rhs_rk4_stage(self.h, s, dt, Qs, Qn, acc, Qnext, precision, stream)
+
+    def rk4_step_fused(self, Qn, dt, bufs, precision=PREC_FP64, stream=None):
+        """One RK4 step in place on Qn with the fused stage kernel; bufs = (Q1, Q2, acc)."""
+        Q1, Q2, acc = bufs
+        order = ((Qn, Q1), (Q1, Q2), (Q2, Q1), (Q1, Qn))
+        for s, (src, dst) in enumerate(order):
+            self.fill_halos(src, stream)
+            self.rhs_rk4_stage(s, dt, src, Qn, acc, dst, precision, stream)
 
     def rk4_step(self, Qn, dt, bufs, precision=PREC_FP64, stream=None):
         """One RK4 step in place on Qn; bufs = (Qs, k, acc) work tensors of the state shape."""

@@ -460,6 +460,28 @@ ccz4_status ccz4_rk4_stage(ccz4_ctx *c, int32_t s, double dt, const double *Qn, 
     return CCZ4_OK;
 }
 
+ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *c, int32_t s, double dt, const double *Qs, const double *Qn, double *acc,
+                               double *Qnext, int32_t precision, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    if (s < 0 || s > 3) return fail(CCZ4_EINVAL, "stage must be 0..3");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(CCZ4_EINVAL, "dt must be finite and > 0");
+    ccz4_status st = check_ptr(Qs, "Qs");
+    if (!st) st = check_ptr(Qn, "Qn");
+    if (!st) st = check_ptr(acc, "acc");
+    if (!st) st = check_ptr(Qnext, "Qnext");
+    if (st) return st;
+    if (precision != CCZ4_PREC_FP64 && precision != CCZ4_PREC_MIXED) return fail(CCZ4_EINVAL, "bad precision");
+    if (Qnext == Qs) return fail(CCZ4_EINVAL, "Qnext must not alias Qs");
+    if (s < 3 && Qnext == Qn) return fail(CCZ4_EINVAL, "Qnext may alias Qn only at s = 3");
+    if (acc == Qs || acc == Qn || acc == Qnext) return fail(CCZ4_EINVAL, "acc must not alias the states");
+    if (!c->bface.empty() && !c->bg_valid)
+        return fail(CCZ4_ESTATE, "Sommerfeld background not set (call ccz4_init_patches or ccz4_set_background)");
+    HIP_TRY(launch_stage(s, dt, Qs, Qn, acc, Qnext, c->d_geom.p, (int32_t)c->leaf.size(), c->prm, precision,
+                         c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(), S(stream)));
+    return CCZ4_OK;
+}
+
 ccz4_status ccz4_constraints(ccz4_ctx *c, const double *Q, double *HM, double r_excise, double *norms, void *stream)
 {
     if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");

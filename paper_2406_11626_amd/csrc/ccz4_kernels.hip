@@ -188,49 +188,63 @@ __device__ __forceinline__ void ppar(int F, int &l, double &w0, double &w1)
     w0 = 1.0 - w1;
 }
 
-__global__ void k_fill(double *__restrict__ Q, const FaceTask *__restrict__ tasks, int32_t ntask)
+// One block per face task, one thread per slab cell; the 59 slots are handled in batches of
+// eight (all loads of a batch issued before its stores, since source and destination share
+// the state array).
+constexpr int SB8 = 8;
+
+__global__ __launch_bounds__(256) void k_fill(double *__restrict__ Q, const FaceTask *__restrict__ tasks,
+                                              int32_t ntask)
 {
     const int ti = blockIdx.x;
-    if (ti >= ntask) return;
-    const FaceTask tk = tasks[ti];
     const int idx = threadIdx.x;
-    if (idx >= NFACE) return;
+    if (ti >= ntask || idx >= NFACE) return;
+    const FaceTask tk = tasks[ti];
     int L, t1, t2;
     slab_coords(tk.axis, idx, L, t1, t2);
     double *dst = Q + (int64_t)tk.patch * PS + slab_off(tk.axis, ghost_c(tk.side, L), t1, t2);
-    if (tk.kind == FK_COPY) {
-        const double *src = Q + (int64_t)tk.src[0] * PS + slab_off(tk.axis, depth_c(-tk.side, L), t1, t2);
-        for (int v = 0; v < NV; ++v) dst[v * CS] = src[v * CS];
-    } else if (tk.kind == FK_NEUMANN) {
-        const double *src = Q + (int64_t)tk.patch * PS + slab_off(tk.axis, depth_c(tk.side, 1), t1, t2);
-        for (int v = 0; v < NV; ++v) dst[v * CS] = src[v * CS];
+    if (tk.kind == FK_COPY || tk.kind == FK_NEUMANN) {
+        const double *src = tk.kind == FK_COPY
+                                ? Q + (int64_t)tk.src[0] * PS + slab_off(tk.axis, depth_c(-tk.side, L), t1, t2)
+                                : Q + (int64_t)tk.patch * PS + slab_off(tk.axis, depth_c(tk.side, 1), t1, t2);
+        for (int v0 = 0; v0 < NV; v0 += SB8) {
+            double r[SB8];
+#pragma unroll
+            for (int j = 0; j < SB8; ++j) r[j] = (v0 + j < NV) ? src[(v0 + j) * CS] : 0.0;
+#pragma unroll
+            for (int j = 0; j < SB8; ++j)
+                if (v0 + j < NV) dst[(v0 + j) * CS] = r[j];
+        }
     } else if (tk.kind == FK_RESTRICT) {
         // coarse ghost c_{2+L}; fine interior layers f3..f5 = depth 1..3 from the kid's face -side;
-        // R_perp rows: (1/3,1/3,1/3), (0,-2,3), (0,-5,6) over (f3,f4,f5); R_avg over 3x3 fine cells.
+        // R_perp rows (1/3,1/3,1/3), (0,-2,3), (0,-5,6) over (f3,f4,f5); R_avg over 3x3 fine cells
         double wf[3];
         if (L == 1) { wf[0] = wf[1] = wf[2] = 1.0 / 3.0; }
         else if (L == 2) { wf[0] = 0.0; wf[1] = -2.0; wf[2] = 3.0; }
         else { wf[0] = 0.0; wf[1] = -5.0; wf[2] = 6.0; }
-        // fine cells (F1, F2) in 3*t1..3*t1+2, 3*t2..3*t2+2 span kid (F/9)
         const int k1 = (3 * t1) / 9, k2 = (3 * t2) / 9;
         const double *kid = Q + (int64_t)tk.src[k2 * 3 + k1] * PS;
         const int f1 = (3 * t1) % 9, f2 = (3 * t2) % 9;
+        int off[3][9];
+        for (int m = 0; m < 3; ++m)
+            for (int b2 = 0; b2 < 3; ++b2)
+                for (int b1 = 0; b1 < 3; ++b1)
+                    off[m][b2 * 3 + b1] = slab_off(tk.axis, depth_c(-tk.side, m + 1), f1 + b1, f2 + b2);
         for (int v = 0; v < NV; ++v) {
             double acc = 0.0;
             for (int m = 0; m < 3; ++m) {
                 if (wf[m] == 0.0) continue;
-                const int cA = depth_c(-tk.side, m + 1);
-                double s = 0.0;
-                for (int b2 = 0; b2 < 3; ++b2)
-                    for (int b1 = 0; b1 < 3; ++b1) s += kid[v * CS + slab_off(tk.axis, cA, f1 + b1, f2 + b2)];
-                acc += wf[m] * (s * (1.0 / 9.0));
+                double sum = 0.0;
+#pragma unroll
+                for (int n = 0; n < 9; ++n) sum += kid[v * CS + off[m][n]];
+                acc += wf[m] * (sum * (1.0 / 9.0));
             }
             dst[v * CS] = acc;
         }
     } else {  // FK_PROLONG
-        // fine ghost L -> f_{3-L}; P_perp rows over coarse (c0..c5):
-        // f0 = c1/3 + 2c2/3, f1 = c2, f2 = 2c2/3 + c3/3.  c0..c2: coarse interior depth 3..1 from
-        // the coarse face -side; c3..c5: coarse ghost 1..3 of that face.
+        // fine ghost L -> f_{3-L}; P_perp rows over coarse (c0..c5): f0 = c1/3 + 2c2/3, f1 = c2,
+        // f2 = 2c2/3 + c3/3; c0..c2 coarse interior depth 3..1 from the coarse face -side, c3..c5
+        // its ghosts 1..3
         const double *cp = Q + (int64_t)tk.src[0] * PS;
         int cA[2];
         double wA[2];
@@ -241,13 +255,20 @@ __global__ void k_fill(double *__restrict__ Q, const FaceTask *__restrict__ task
         double a0, a1, b0, b1;
         ppar(9 * tk.o1 + t1, l1, a0, a1);
         ppar(9 * tk.o2 + t2, l2, b0, b1);
+        int off[2][4];
+        for (int m = 0; m < 2; ++m) {
+            off[m][0] = slab_off(tk.axis, cA[m], l1, l2);
+            off[m][1] = slab_off(tk.axis, cA[m], l1 + 1, l2);
+            off[m][2] = slab_off(tk.axis, cA[m], l1, l2 + 1);
+            off[m][3] = slab_off(tk.axis, cA[m], l1 + 1, l2 + 1);
+        }
         for (int v = 0; v < NV; ++v) {
+            const double *c = cp + v * CS;
             double acc = 0.0;
             for (int m = 0; m < 2; ++m) {
                 if (wA[m] == 0.0) continue;
-                const double *s = cp + v * CS;
-                const double r0 = a0 * s[slab_off(tk.axis, cA[m], l1, l2)] + a1 * s[slab_off(tk.axis, cA[m], l1 + 1, l2)];
-                const double r1 = a0 * s[slab_off(tk.axis, cA[m], l1, l2 + 1)] + a1 * s[slab_off(tk.axis, cA[m], l1 + 1, l2 + 1)];
+                const double r0 = a0 * c[off[m][0]] + a1 * c[off[m][1]];
+                const double r1 = a0 * c[off[m][2]] + a1 * c[off[m][3]];
                 acc += wA[m] * (b0 * r0 + b1 * r1);
             }
             dst[v * CS] = acc;
@@ -270,8 +291,12 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk)
     return (b % 8) * per + b / 8;
 }
 
+#ifndef CCZ4_RHS_WPE
+#define CCZ4_RHS_WPE 1
+#endif
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_rhs(const double *__restrict__ Q, double *__restrict__ K,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WPE))) void k_rhs(const double *__restrict__ Q, double *__restrict__ K,
                                              const PatchGeom *__restrict__ geom, int32_t npatch,
                                              RhsParams prm)
 {
@@ -289,24 +314,110 @@ __global__ __launch_bounds__(256) void k_rhs(const double *__restrict__ Q, doubl
         cr.i12[a] = 1.0 / (12.0 * g.dx[a]);
         cr.koc[a] = prm.ko_eps / (64.0 * g.dx[a]);
     }
-    rhs_cell_phased<T>(cr, prm);
+    RhsSink snk;
+    rhs_cell_phased<T>(cr, prm, snk);
 }
 
-// Sommerfeld ghosts: one block per boundary face, one thread per ghost cell
-__global__ void k_rhs_sommerfeld(const double *__restrict__ Q, double *__restrict__ K,
-                                 const PatchGeom *__restrict__ geom, const BoundaryFace *__restrict__ bf,
-                                 const double *__restrict__ bg, int32_t nbf, int32_t frozen)
+// Fused stage: the right-hand side of Qs folded slot by slot into stage s of RK4 (two-register
+// form) on the interior cells, with the projection of Q^{n+1} at s = 3.  Qs is read through the
+// stencils, Qn and acc pointwise; Qnext must differ from Qs (other cells still read Qs).
+struct StageSink {
+    const double *__restrict__ qn;
+    double *__restrict__ acc;
+    double *__restrict__ qx;
+    int s;
+    double dt;
+    double carry[12];  // s = 3: gt_ij and At_ij of Q^{n+1}, projected in finish()
+
+    __device__ __forceinline__ void combine(const CellRef &c, int v, double r)
+    {
+        const int e = v * CS + c.o;
+        if (s == 0) {
+            const double q0 = qn[e];
+            acc[e] = q0 + (1.0 / 6.0) * dt * r;
+            qx[e] = q0 + 0.5 * dt * r;
+        } else if (s < 3) {
+            acc[e] = acc[e] + (1.0 / 3.0) * dt * r;
+            qx[e] = qn[e] + (s == 1 ? 0.5 : 1.0) * dt * r;
+        } else {
+            const double val = acc[e] + (1.0 / 6.0) * dt * r;
+            if (v < 6) carry[v] = val;
+            else if (v >= SAT && v < SAT + 6) carry[v - SAT + 6] = val;
+            else qx[e] = val;
+        }
+    }
+    __device__ __forceinline__ void put(const CellRef &c, int v, double alg) { combine(c, v, alg + ko(c, v)); }
+    __device__ __forceinline__ void zero(const CellRef &c, int v) { combine(c, v, 0.0); }
+    __device__ __forceinline__ void finish(const CellRef &c)
+    {
+        if (s != 3) return;
+        double q[SAT + 6];
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+            q[v] = carry[v];
+            q[SAT + v] = carry[6 + v];
+        }
+        project_cell(q);
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+            qx[v * CS + c.o] = q[v];
+            qx[(SAT + v) * CS + c.o] = q[SAT + v];
+        }
+    }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WPE))) void k_stage(
+    const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
+    const PatchGeom *__restrict__ geom, int32_t npatch, RhsParams prm, int32_t s, double dt)
 {
-    const int fi = blockIdx.x;
-    if (fi >= nbf) return;
-    const int idx = threadIdx.x;
-    if (idx >= NFACE) return;
+    const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int p = (int)(lb / 3);
+    if (p >= npatch || threadIdx.x >= 243) return;
+    const int c = (int)(lb % 3) * 243 + threadIdx.x;
+    const PatchGeom g = geom[p];
+    CellRef cr;
+    cr.qb = Qs + (int64_t)p * PS;
+    cr.kb = nullptr;
+    cr.o = boff(c % 9 + 3, (c / 9) % 9 + 3, c / 81 + 3);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cr.i12[a] = 1.0 / (12.0 * g.dx[a]);
+        cr.koc[a] = prm.ko_eps / (64.0 * g.dx[a]);
+    }
+    StageSink snk;
+    snk.qn = Qn + (int64_t)p * PS;
+    snk.acc = acc + (int64_t)p * PS;
+    snk.qx = Qx + (int64_t)p * PS;
+    snk.s = s;
+    snk.dt = dt;
+    rhs_cell_phased<T>(cr, prm, snk);
+}
+
+// Sommerfeld ghosts: one thread per (boundary face, slot, ghost cell)
+__global__ __launch_bounds__(256) void k_rhs_sommerfeld(const double *__restrict__ Q, double *__restrict__ K,
+                                                        const PatchGeom *__restrict__ geom,
+                                                        const BoundaryFace *__restrict__ bf,
+                                                        const double *__restrict__ bg, int32_t nbf, int32_t frozen)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nbf * NV * NFACE) return;
+    const int fi = (int)(t / (NV * NFACE));
+    const int r = (int)(t % (NV * NFACE));
+    const int v = r / NFACE;
+    const int idx = r % NFACE;
     const BoundaryFace f = bf[fi];
     int L, t1, t2;
     slab_coords(f.axis, idx, L, t1, t2);
     const int cg = ghost_c(f.side, L);
+    const int og = slab_off(f.axis, cg, t1, t2);
+    double *Kp = K + (int64_t)f.patch * PS + v * CS + og;
+    if (v == SK0 || (frozen && frozen_slot(v))) {
+        *Kp = 0.0;
+        return;
+    }
     const int ci = L == 1 ? depth_c(f.side, 1) : ghost_c(f.side, L - 1);
-    const int og = slab_off(f.axis, cg, t1, t2), oi = slab_off(f.axis, ci, t1, t2);
+    const int oi = slab_off(f.axis, ci, t1, t2);
     const PatchGeom g = geom[f.patch];
     int cx, cy, cz;
     if (f.axis == 0) { cx = cg; cy = t1 + 3; cz = t2 + 3; }
@@ -315,19 +426,11 @@ __global__ void k_rhs_sommerfeld(const double *__restrict__ Q, double *__restric
     const double X = g.org[0] + (cx - 2.5) * g.dx[0];
     const double Y = g.org[1] + (cy - 2.5) * g.dx[1];
     const double Z = g.org[2] + (cz - 2.5) * g.dx[2];
-    const double r = sqrt(X * X + Y * Y + Z * Z);
+    const double rr = sqrt(X * X + Y * Y + Z * Z);
     const double xn = f.axis == 0 ? X : (f.axis == 1 ? Y : Z);
-    const double cadv = r / (fabs(xn) * g.dx[f.axis]);
-    const double cdmp = 1.0 / r;
-    const double *Qp = Q + (int64_t)f.patch * PS;
-    double *Kp = K + (int64_t)f.patch * PS;
-    const double *B = bg + (int64_t)f.bg * NV * NFACE + idx;
-    for (int v = 0; v < NEVOL; ++v) {
-        if (frozen && frozen_slot(v)) { Kp[v * CS + og] = 0.0; continue; }
-        const double qL = Qp[v * CS + og];
-        Kp[v * CS + og] = -cadv * (qL - Qp[v * CS + oi]) - cdmp * (qL - B[v * NFACE]);
-    }
-    Kp[SK0 * CS + og] = 0.0;
+    const double *Qp = Q + (int64_t)f.patch * PS + v * CS;
+    const double qL = Qp[og];
+    *Kp = -(rr / (fabs(xn) * g.dx[f.axis])) * (qL - Qp[oi]) - (1.0 / rr) * (qL - bg[(int64_t)f.bg * NV * NFACE + v * NFACE + idx]);
 }
 
 __global__ void k_capture_bg(const double *__restrict__ Q, const BoundaryFace *__restrict__ bf,
@@ -346,65 +449,123 @@ __global__ void k_capture_bg(const double *__restrict__ Q, const BoundaryFace *_
 }
 
 // ------------------------------------------------------------------ RK4 stage
-__device__ __forceinline__ void rk_combine(int s, double dt, const double *__restrict__ qn,
-                                           const double *__restrict__ kk, double *__restrict__ acc,
-                                           double *__restrict__ qx, int o, double *keep)
+// classical RK4 in two-register form: weights of acc (b) and of the stage state (a)
+__device__ __forceinline__ void rk_one(int s, double dt, const double *__restrict__ qn, const double *__restrict__ kk,
+                                       double *__restrict__ acc, double *__restrict__ qx, int64_t e)
 {
-    // two-register classical RK4
-    constexpr double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
-    constexpr double aw[3] = {0.5, 0.5, 1.0};
-    for (int v = 0; v < NV; ++v) {
-        const int e = v * CS + o;
-        const double kv = kk[e];
-        if (s == 0) {
-            const double q0 = qn[e];
-            acc[e] = q0 + bw[0] * dt * kv;
-            qx[e] = q0 + aw[0] * dt * kv;
-        } else if (s < 3) {
-            acc[e] = acc[e] + bw[s] * dt * kv;
-            qx[e] = qn[e] + aw[s] * dt * kv;
-        } else {
-            const double r = acc[e] + bw[3] * dt * kv;
-            if (keep) keep[v] = r;
-            else qx[e] = r;
-        }
+    const double kv = kk[e];
+    if (s == 0) {
+        const double q0 = qn[e];
+        acc[e] = q0 + (1.0 / 6.0) * dt * kv;
+        qx[e] = q0 + 0.5 * dt * kv;
+    } else if (s == 1) {
+        acc[e] = acc[e] + (1.0 / 3.0) * dt * kv;
+        qx[e] = qn[e] + 0.5 * dt * kv;
+    } else if (s == 2) {
+        acc[e] = acc[e] + (1.0 / 3.0) * dt * kv;
+        qx[e] = qn[e] + dt * kv;
+    } else {
+        qx[e] = acc[e] + (1.0 / 6.0) * dt * kv;
     }
 }
 
+// one thread per interior cell; slots in batches of eight; at s = 3 the cell is projected
 __global__ __launch_bounds__(256) void k_rk4(int32_t s, double dt, const double *__restrict__ Qn,
                                              const double *__restrict__ Kk, double *__restrict__ acc,
-                                             double *__restrict__ Qx, int64_t ncell)
+                                             double *__restrict__ Qx, int32_t npatch)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ncell) return;
+    if (t >= (int64_t)npatch * NCELL) return;
     const int p = (int)(t / NCELL);
     const int c = (int)(t % NCELL);
-    const int o = boff(c % 9 + 3, (c / 9) % 9 + 3, c / 81 + 3);
-    const int64_t base = (int64_t)p * PS;
+    const int64_t base = (int64_t)p * PS + boff(c % 9 + 3, (c / 9) % 9 + 3, c / 81 + 3);
     if (s < 3) {
-        rk_combine(s, dt, Qn + base, Kk + base, acc + base, Qx + base, o, nullptr);
+        for (int v0 = 0; v0 < NV; v0 += SB8) {
+#pragma unroll
+            for (int j = 0; j < SB8; ++j)
+                if (v0 + j < NV) rk_one(s, dt, Qn, Kk, acc, Qx, base + (int64_t)(v0 + j) * CS);
+        }
         return;
     }
     double q[NV];
-    rk_combine(s, dt, Qn + base, Kk + base, acc + base, Qx + base, o, q);
+    for (int v0 = 0; v0 < NV; v0 += SB8) {
+#pragma unroll
+        for (int j = 0; j < SB8; ++j)
+            if (v0 + j < NV) {
+                const int64_t e = base + (int64_t)(v0 + j) * CS;
+                q[v0 + j] = acc[e] + (1.0 / 6.0) * dt * Kk[e];
+            }
+    }
     project_cell(q);
-    for (int v = 0; v < NV; ++v) Qx[base + v * CS + o] = q[v];
+    for (int v = 0; v < NV; ++v) Qx[base + (int64_t)v * CS] = q[v];
 }
 
-__global__ void k_rk4_ghost(int32_t s, double dt, const double *__restrict__ Qn, const double *__restrict__ Kk,
-                            double *__restrict__ acc, double *__restrict__ Qx, const BoundaryFace *__restrict__ bf,
-                            int32_t nbf)
+// Sommerfeld ghosts: one thread per (boundary face, slot, ghost cell); no projection
+__global__ __launch_bounds__(256) void k_rk4_ghost(int32_t s, double dt, const double *__restrict__ Qn,
+                                                   const double *__restrict__ Kk, double *__restrict__ acc,
+                                                   double *__restrict__ Qx, const BoundaryFace *__restrict__ bf,
+                                                   int32_t nbf)
 {
-    const int fi = blockIdx.x;
-    if (fi >= nbf) return;
-    const int idx = threadIdx.x;
-    if (idx >= NFACE) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nbf * NV * NFACE) return;
+    const int fi = (int)(t / (NV * NFACE));
+    const int r = (int)(t % (NV * NFACE));
+    const int v = r / NFACE;
+    const int idx = r % NFACE;
     const BoundaryFace f = bf[fi];
     int L, t1, t2;
     slab_coords(f.axis, idx, L, t1, t2);
-    const int og = slab_off(f.axis, ghost_c(f.side, L), t1, t2);
+    const int64_t e = (int64_t)f.patch * PS + v * CS + slab_off(f.axis, ghost_c(f.side, L), t1, t2);
+    rk_one(s, dt, Qn, Kk, acc, Qx, e);
+}
+
+// Fused stage on Sommerfeld ghosts: G_L of Qs combined at once into stage s
+__global__ void k_stage_sommerfeld(int32_t s, double dt, const double *__restrict__ Qs,
+                                   const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
+                                   const PatchGeom *__restrict__ geom, const BoundaryFace *__restrict__ bf,
+                                   const double *__restrict__ bg, int32_t nbf, int32_t frozen)
+{
+    const int fi = blockIdx.x;
+    const int idx = threadIdx.x;
+    if (fi >= nbf || idx >= NFACE) return;
+    const BoundaryFace f = bf[fi];
+    int L, t1, t2;
+    slab_coords(f.axis, idx, L, t1, t2);
+    const int cg = ghost_c(f.side, L);
+    const int og = slab_off(f.axis, cg, t1, t2);
+    const int ci = L == 1 ? depth_c(f.side, 1) : ghost_c(f.side, L - 1);
+    const int oi = slab_off(f.axis, ci, t1, t2);
+    const PatchGeom g = geom[f.patch];
+    int cx, cy, cz;
+    if (f.axis == 0) { cx = cg; cy = t1 + 3; cz = t2 + 3; }
+    else if (f.axis == 1) { cx = t1 + 3; cy = cg; cz = t2 + 3; }
+    else { cx = t1 + 3; cy = t2 + 3; cz = cg; }
+    const double X = g.org[0] + (cx - 2.5) * g.dx[0];
+    const double Y = g.org[1] + (cy - 2.5) * g.dx[1];
+    const double Z = g.org[2] + (cz - 2.5) * g.dx[2];
+    const double rr = sqrt(X * X + Y * Y + Z * Z);
+    const double xn = f.axis == 0 ? X : (f.axis == 1 ? Y : Z);
+    const double cadv = rr / (fabs(xn) * g.dx[f.axis]), cdmp = 1.0 / rr;
     const int64_t base = (int64_t)f.patch * PS;
-    rk_combine(s, dt, Qn + base, Kk + base, acc + base, Qx + base, og, nullptr);
+    const double *B = bg + (int64_t)f.bg * NV * NFACE + idx;
+    for (int v = 0; v < NV; ++v) {
+        double r = 0.0;
+        if (v != SK0 && !(frozen && frozen_slot(v))) {
+            const double qL = Qs[base + v * CS + og];
+            r = -cadv * (qL - Qs[base + v * CS + oi]) - cdmp * (qL - B[v * NFACE]);
+        }
+        const int64_t e = base + v * CS + og;
+        if (s == 0) {
+            const double q0 = Qn[e];
+            acc[e] = q0 + (1.0 / 6.0) * dt * r;
+            Qx[e] = q0 + 0.5 * dt * r;
+        } else if (s < 3) {
+            acc[e] = acc[e] + (1.0 / 3.0) * dt * r;
+            Qx[e] = Qn[e] + (s == 1 ? 0.5 : 1.0) * dt * r;
+        } else {
+            Qx[e] = acc[e] + (1.0 / 6.0) * dt * r;
+        }
+    }
 }
 
 // ------------------------------------------------------------------ constraints
@@ -584,11 +745,29 @@ hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t
     return hipGetLastError();
 }
 
+hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn, double *acc, double *Qx,
+                        const PatchGeom *geom, int32_t npatch, const RhsParams &p, int32_t precision,
+                        const BoundaryFace *bf, const double *bg, int32_t nbf, hipStream_t st)
+{
+    const int64_t nb = ((int64_t)npatch * 3 + 7) / 8 * 8;
+    if (precision == 1)
+        hipLaunchKernelGGL(k_stage<float>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch, p, s, dt);
+    else
+        hipLaunchKernelGGL(k_stage<double>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch, p, s, dt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nbf <= 0) return e;
+    hipLaunchKernelGGL(k_stage_sommerfeld, dim3(nbf), dim3(256), 0, st, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, nbf,
+                       p.shift == 0);
+    return hipGetLastError();
+}
+
 hipError_t launch_rhs_sommerfeld(const double *Q, double *K, const PatchGeom *geom, const BoundaryFace *bf,
                                  const double *bg, int32_t nbf, int32_t frozen, hipStream_t st)
 {
     if (nbf <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rhs_sommerfeld, dim3(nbf), dim3(256), 0, st, Q, K, geom, bf, bg, nbf, frozen);
+    const int64_t n = (int64_t)nbf * NV * NFACE;
+    hipLaunchKernelGGL(k_rhs_sommerfeld, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Q, K, geom, bf, bg,
+                       nbf, frozen);
     return hipGetLastError();
 }
 
@@ -603,10 +782,13 @@ hipError_t launch_rk4(int32_t s, double dt, const double *Qn, const double *K, d
                       int32_t npatch, const BoundaryFace *bf, int32_t nbf, hipStream_t st)
 {
     const int64_t n = (int64_t)npatch * NCELL;
-    hipLaunchKernelGGL(k_rk4, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, dt, Qn, K, acc, Qx, n);
+    hipLaunchKernelGGL(k_rk4, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, s, dt, Qn, K, acc, Qx, npatch);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || nbf <= 0) return e;
-    hipLaunchKernelGGL(k_rk4_ghost, dim3(nbf), dim3(256), 0, st, s, dt, Qn, K, acc, Qx, bf, nbf);
+    if (e != hipSuccess) return e;
+    if (nbf <= 0) return hipSuccess;
+    const int64_t ng = (int64_t)nbf * NV * NFACE;
+    hipLaunchKernelGGL(k_rk4_ghost, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, st, s, dt, Qn, K, acc, Qx, bf,
+                       nbf);
     return hipGetLastError();
 }
 

@@ -42,10 +42,20 @@ __device__ __forceinline__ double fd(const CellRef &c, int v, int a)
     return (8.0 * (f[s] - f[-s]) - (f[2 * s] - f[-2 * s])) * c.i12[a];
 }
 
+#ifndef CCZ4_KO_PRINTED_ORDER
+#define CCZ4_KO_PRINTED_ORDER 1
+#endif
+
 __device__ __forceinline__ double ko_axis(const double *__restrict__ f, int s)
 {
+#if CCZ4_KO_PRINTED_ORDER
 #pragma clang fp contract(off)
     return f[-3 * s] - 6.0 * f[-2 * s] + 15.0 * f[-s] - 20.0 * f[0] + 15.0 * f[s] - 6.0 * f[2 * s] + f[3 * s];
+#else
+    // symmetric pairs, three fused multiply-adds
+    const double p3 = f[-3 * s] + f[3 * s], p2 = f[-2 * s] + f[2 * s], p1 = f[-s] + f[s];
+    return fma(-20.0, f[0], fma(15.0, p1, fma(-6.0, p2, p3)));
+#endif
 }
 
 // Kreiss-Oliger sum over the axes of slot v (printed stencil order, no contraction)
@@ -62,8 +72,13 @@ __device__ __forceinline__ double adv(const CellRef &c, int v, const double be[3
     return be[0] * fd(c, v, 0) + be[1] * fd(c, v, 1) + be[2] * fd(c, v, 2);
 }
 
-__device__ __forceinline__ void store(const CellRef &c, int v, double alg) { c.kb[v * CS + c.o] = alg + ko(c, v); }
-__device__ __forceinline__ void store_zero(const CellRef &c, int v) { c.kb[v * CS + c.o] = 0.0; }
+// Output sinks: the plain right-hand side writes k = algebra + KO; the fused stage folds each
+// finished slot at once into the RK4 stage combine (see StageSink).
+struct RhsSink {
+    __device__ __forceinline__ void put(const CellRef &c, int v, double alg) { c.kb[v * CS + c.o] = alg + ko(c, v); }
+    __device__ __forceinline__ void zero(const CellRef &c, int v) { c.kb[v * CS + c.o] = 0.0; }
+    __device__ __forceinline__ void finish(const CellRef &) {}
+};
 
 __device__ __forceinline__ void metric_inverse(const double g[6], double ig[6], double &det)
 {
@@ -124,8 +139,8 @@ __device__ __forceinline__ void christoffel(const T ig[6], const T D[3][6], T Gl
 // ---------------------------------------------------------------------------------------
 // phase 1: At_ij, K, Theta (Ricci tensor, nabla nabla alpha, Z4 terms).  Returns the curl
 // contraction H - G1 of d D that the B equation needs.
-template <typename T>
-__device__ __forceinline__ void phase_ricci(const CellRef &c, const RhsParams &p, T CmG[3][3])
+template <typename T, typename Sink>
+__device__ __forceinline__ void phase_ricci(Sink &snk, const CellRef &c, const RhsParams &p, T CmG[3][3])
 {
     double gd[6], igd[6], detg;
 #pragma unroll
@@ -349,27 +364,27 @@ __device__ __forceinline__ void phase_ricci(const CellRef &c, const RhsParams &p
             t += al * At[ij] * (Kt - T(2) * Th * cc);
             t += T(-2) * al * (At[sym(i, 0)] * Am[0][j] + At[sym(i, 1)] * Am[1][j] + At[sym(i, 2)] * Am[2][j]);
             const T tf = X[ij] - T(1.0 / 3.0) * g[ij] * trX;
-            store(c, SAT + ij, adv(c, SAT + ij, be) + static_cast<double>(t) + phid * phid * static_cast<double>(tf));
+            snk.put(c, SAT + ij, adv(c, SAT + ij, be) + static_cast<double>(t) + phid * phid * static_cast<double>(tf));
         }
     const T kap1 = cvt<T>(p.kappa1), kap2 = cvt<T>(p.kappa2);
-    store(c, SK, adv(c, SK, be) + static_cast<double>(-lapal + al * RpZ + al * Kt * (Kt - T(2) * Th * cc) -
+    snk.put(c, SK, adv(c, SK, be) + static_cast<double>(-lapal + al * RpZ + al * Kt * (Kt - T(2) * Th * cc) -
                                                         T(3) * al * kap1 * (T(1) + kap2) * Th));
     const T ee2 = cvt<T>(p.e * p.e);
     const T half_phi2 = T(0.5) * phi2;
     const T ZA = half_phi2 * (dG[0] * A[0] + dG[1] * A[1] + dG[2] * A[2]);
-    store(c, STHETA, adv(c, STHETA, be) + static_cast<double>(T(0.5) * al * ee2 * (RpZ + T(2.0 / 3.0) * Kt * Kt - AA) -
+    snk.put(c, STHETA, adv(c, STHETA, be) + static_cast<double>(T(0.5) * al * ee2 * (RpZ + T(2.0 / 3.0) * Kt * Kt - AA) -
                                                               al * Th * Kt * cc - ZA - al * kap1 * (T(2) + kap2) * Th));
     (void)bet;
 }
 
 // ---------------------------------------------------------------------------------------
 // phase 2: B_k^i (Gamma-driver only; zero with the frozen shift)
-template <typename T>
-__device__ __forceinline__ void phase_B(const CellRef &c, const RhsParams &p, const T CmG[3][3])
+template <typename T, typename Sink>
+__device__ __forceinline__ void phase_B(Sink &snk, const CellRef &c, const RhsParams &p, const T CmG[3][3])
 {
     if (p.shift == 0) {
 #pragma unroll
-        for (int s = 0; s < 9; ++s) store_zero(c, SB + s);
+        for (int s = 0; s < 9; ++s) snk.zero(c, SB + s);
         return;
     }
     double gd[6], igd[6], detg;
@@ -413,14 +428,14 @@ __device__ __forceinline__ void phase_B(const CellRef &c, const RhsParams &p, co
 #pragma unroll
             for (int j = 0; j < 3; ++j) curl += ig[sym(i, j)] * (CmG[k][j] - cP[k][j]);
             t += a2mu * curl;
-            store(c, SB + 3 * k + i, adv(c, SB + 3 * k + i, be) + static_cast<double>(t));
+            snk.put(c, SB + 3 * k + i, adv(c, SB + 3 * k + i, be) + static_cast<double>(t));
         }
 }
 
 // ---------------------------------------------------------------------------------------
 // phase 3: Ghat^i and b^i
-template <typename T>
-__device__ __forceinline__ void phase_gamma(const CellRef &c, const RhsParams &p)
+template <typename T, typename Sink>
+__device__ __forceinline__ void phase_gamma(Sink &snk, const CellRef &c, const RhsParams &p)
 {
     double gd[6], igd[6], detg;
 #pragma unroll
@@ -531,16 +546,16 @@ __device__ __forceinline__ void phase_gamma(const CellRef &c, const RhsParams &p
         t += T(2) * kap3 * (T(2.0 / 3.0) * u * trB - zb);
         const double advG = adv(c, SGHAT + i, be);
         const double rG = advG + static_cast<double>(t);
-        store(c, SGHAT + i, rG);
-        if (p.shift) store(c, SBB + i, rG - advG + adv(c, SBB + i, be) - p.eta * ld(c, SBB + i));
-        else store_zero(c, SBB + i);
+        snk.put(c, SGHAT + i, rG);
+        if (p.shift) snk.put(c, SBB + i, rG - advG + adv(c, SBB + i, be) - p.eta * ld(c, SBB + i));
+        else snk.zero(c, SBB + i);
     }
 }
 
 // ---------------------------------------------------------------------------------------
 // phase 4: A_k and P_k
-template <typename T>
-__device__ __forceinline__ void phase_AP(const CellRef &c, const RhsParams &p)
+template <typename T, typename Sink>
+__device__ __forceinline__ void phase_AP(Sink &snk, const CellRef &c, const RhsParams &p)
 {
     double gd[6], igd[6], detg;
 #pragma unroll
@@ -600,17 +615,17 @@ __device__ __forceinline__ void phase_AP(const CellRef &c, const RhsParams &p)
         T t = -al * al * ga * (dK - T(2) * cc * dTh) - al * ga * dtrA[k];
         t += Bm[k][0] * A[0] + Bm[k][1] * A[1] + Bm[k][2] * A[2];
         t += -ga_lin * theta_term * A[k];
-        store(c, SA + k, adv(c, SA + k, be) + static_cast<double>(t));
+        snk.put(c, SA + k, adv(c, SA + k, be) + static_cast<double>(t));
         T u = Bm[k][0] * P[0] + Bm[k][1] * P[1] + Bm[k][2] * P[2] + T(1.0 / 3.0) * (al * Kt - trB) * P[k];
         const T phipart = T(1.0 / 3.0) * (al * dK - sdBtr[k]) + T(1.0 / 3.0) * al * dtrA[k] + T(1.0 / 3.0) * Kt * A[k];
-        store(c, SP + k, adv(c, SP + k, be) + static_cast<double>(u) + phid * static_cast<double>(phipart));
+        snk.put(c, SP + k, adv(c, SP + k, be) + static_cast<double>(u) + phid * static_cast<double>(phipart));
     }
 }
 
 // ---------------------------------------------------------------------------------------
 // phase 5: D_kij
-template <typename T>
-__device__ __forceinline__ void phase_D(const CellRef &c0, const RhsParams &p)
+template <typename T, typename Sink>
+__device__ __forceinline__ void phase_D(Sink &snk, const CellRef &c0, const RhsParams &p)
 {
     const CellRef &c = c0;
     double gd[6], igd[6], detg;
@@ -683,7 +698,7 @@ __device__ __forceinline__ void phase_D(const CellRef &c0, const RhsParams &p)
                 for (int l = 0; l < 3; ++l) t += Bm[k][l] * D[l][ij] + Bm[j][l] * D[k][sym(l, i)] + Bm[i][l] * D[k][sym(l, j)];
                 t += T(-2.0 / 3.0) * trB * D[k][ij];
                 t += -A[k] * (At[ij] - T(1.0 / 3.0) * g[ij] * trAt);
-                store(c, SD + 6 * k + ij, adv(c, SD + 6 * k + ij, be) + static_cast<double>(t));
+                snk.put(c, SD + 6 * k + ij, adv(c, SD + 6 * k + ij, be) + static_cast<double>(t));
             }
         CCZ4_PHASE_BARRIER();
     }
@@ -691,8 +706,8 @@ __device__ __forceinline__ void phase_D(const CellRef &c0, const RhsParams &p)
 
 // ---------------------------------------------------------------------------------------
 // phase 6: gt_ij, alpha, beta^i, phi and K_0
-template <typename T>
-__device__ __forceinline__ void phase_point(const CellRef &c, const RhsParams &p)
+template <typename T, typename Sink>
+__device__ __forceinline__ void phase_point(Sink &snk, const CellRef &c, const RhsParams &p)
 {
     double gd[6], igd[6], detg;
 #pragma unroll
@@ -729,24 +744,24 @@ __device__ __forceinline__ void phase_point(const CellRef &c, const RhsParams &p
             for (int k = 0; k < 3; ++k) t += g[sym(k, i)] * Bm[j][k] + g[sym(k, j)] * Bm[i][k];
             t += T(-2.0 / 3.0) * g[ij] * trB;
             t += T(-2) * al * (At[ij] - T(1.0 / 3.0) * g[ij] * trAt);
-            store(c, SG + ij, static_cast<double>(t) - (detg - 1.0) / p.tau * gd[ij]);
+            snk.put(c, SG + ij, static_cast<double>(t) - (detg - 1.0) / p.tau * gd[ij]);
         }
     const T Kt = cvt<T>(ld(c, SK)), K0 = cvt<T>(ld(c, SK0)), Th = cvt<T>(ld(c, STHETA));
     const T ga = p.slicing == 1 ? T(2) / al : T(1);
-    store(c, SALPHA, static_cast<double>(bet[0] * A[0] + bet[1] * A[1] + bet[2] * A[2] -
+    snk.put(c, SALPHA, static_cast<double>(bet[0] * A[0] + bet[1] * A[1] + bet[2] * A[2] -
                                          al * al * ga * (Kt - K0 - T(2) * cvt<T>(p.c) * Th)));
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         if (p.shift)
-            store(c, SBETA + i, static_cast<double>(bet[0] * Bm[0][i] + bet[1] * Bm[1][i] + bet[2] * Bm[2][i] +
+            snk.put(c, SBETA + i, static_cast<double>(bet[0] * Bm[0][i] + bet[1] * Bm[1][i] + bet[2] * Bm[2][i] +
                                                     cvt<T>(p.f) * cvt<T>(ld(c, SBB + i))));
         else
-            store_zero(c, SBETA + i);
+            snk.zero(c, SBETA + i);
     }
     const double phid = ld(c, SPHI);
-    store(c, SPHI, be[0] * ld(c, SP) + be[1] * ld(c, SP + 1) + be[2] * ld(c, SP + 2) +
+    snk.put(c, SPHI, be[0] * ld(c, SP) + be[1] * ld(c, SP + 1) + be[2] * ld(c, SP + 2) +
                        phid * static_cast<double>((al * Kt - trB) * T(1.0 / 3.0)));
-    store_zero(c, SK0);
+    snk.zero(c, SK0);
 }
 
 // Pass the cell offset through an opaque register move so that the compiler can neither
@@ -760,16 +775,17 @@ __device__ __forceinline__ CellRef fresh(const CellRef &c)
     return r;
 }
 
-template <typename T>
-__device__ __forceinline__ void rhs_cell_phased(const CellRef &c0, const RhsParams &p)
+template <typename T, typename Sink>
+__device__ __forceinline__ void rhs_cell_phased(const CellRef &c0, const RhsParams &p, Sink &snk)
 {
     T CmG[3][3];
-    phase_ricci<T>(fresh(c0), p, CmG);
-    phase_B<T>(fresh(c0), p, CmG);
-    phase_gamma<T>(fresh(c0), p);
-    phase_AP<T>(fresh(c0), p);
-    phase_D<T>(fresh(c0), p);
-    phase_point<T>(fresh(c0), p);
+    phase_ricci<T>(snk, fresh(c0), p, CmG);
+    phase_B<T>(snk, fresh(c0), p, CmG);
+    phase_gamma<T>(snk, fresh(c0), p);
+    phase_AP<T>(snk, fresh(c0), p);
+    phase_D<T>(snk, fresh(c0), p);
+    phase_point<T>(snk, fresh(c0), p);
+    snk.finish(fresh(c0));
 }
 
 }  // namespace ccz4
