@@ -2,9 +2,14 @@
 
 A step is one classical RK4 step of the whole hot path over the single-puncture workload of
 16^3 patches of 9^3 cells (144^3 = 2,985,984 cells on [-9,9]^3, Sommerfeld boundaries, 1+log
-slicing, Gamma-driver): four times (halo fill, RHS = FD4 + CCZ4 algebra + KO, RK4 stage
-combine), the last stage with the algebraic projection.  The metric is cell-updates per second
-per RK4 stage: cells x 4 stages x steps / wall time, inputs resident in HBM.
+slicing, Gamma-driver): four times (halo fill; fused stage = FD4 derivatives + CCZ4 algebra +
+Kreiss-Oliger + RK4 stage combine, the last stage with the algebraic projection).  The metric
+is cell-updates per second per RK4 stage: cells x 4 stages x steps / wall time, with the state
+resident in HBM.
+
+The roofline object is the fused stage kernel's: algorithmic bytes per launch (per cell: every
+evolved slot with its three-cell face halos read once, the step state and accumulator streamed
+as the stage requires) over its average launch time, taken with events on the launch stream.
 
 Prints one JSON line.  --gpus N > 1 is not supported (the path runs on one GPU).
 """
@@ -18,9 +23,51 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-RHS_BYTES_PER_CELL = 1888   # 2187 cell-vectors read (interior + face halos) / 729 + 1 written, 59 x 8 B each
-STAGE_BYTES_PER_CELL = 2360  # RK4 stage: read Qn, k, acc; write acc, Q_next
-FILL_BYTES_PER_CELL = 1888   # face halos: 1458 read + 1458 written per 729 cells
+NV = 59
+# Fused stage, bytes per interior cell.  Q_s: the 58 evolved slots with interior + face halos
+# (2187 cell-vectors per 729 cells) and K_0 pointwise.  Streamed, per stage s:
+#   s = 0: read Q_n, write acc, write Q_next;  s = 1, 2: read/write acc, read Q_n, write Q_next;
+#   s = 3: read acc, write Q_next.
+QS_BYTES_PER_CELL = 8 * (58 * 3 + 1)
+STREAM_BYTES_PER_CELL = {0: 3 * 8 * NV, 1: 4 * 8 * NV, 2: 4 * 8 * NV, 3: 2 * 8 * NV}
+
+
+def stage_bytes_per_cell(s):
+    return QS_BYTES_PER_CELL + STREAM_BYTES_PER_CELL[s]
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_puncture16_hbm_traffic.md")
+
+
+def kernel_source_digest():
+    """sha256 over the HIP sources of the library (the traffic figure is void once they change)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2406_11626_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fused stage kernel from the committed counter summary, or None
+    when there is none or the kernel sources have changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    with open(TRAFFIC_FILE) as f:
+        for ln in f:
+            if ln.startswith("- ") and ":" in ln:
+                k, v = ln[2:].split(":", 1)
+                rec[k.strip()] = v.strip().strip("`")
+    if rec.get("source_sha256") != kernel_source_digest():
+        return None
+    try:
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def run_gpu(args, w, precision):
@@ -29,26 +76,23 @@ def run_gpu(args, w, precision):
     ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, w.params(), w.refined)
     Q = ctx.new_state(0.0)
     ctx.init_patches(Q, w.scenario, w.scen)
-    Qs, k, acc = ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0)
+    Q1, Q2, acc = ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0)
     dt = w.dt()
     stream = torch.cuda.current_stream()
-    ev = {}
+    order = ((Q, Q1), (Q1, Q2), (Q2, Q1), (Q1, Q))
+    events = []
 
     def step(timed):
-        cur = Q
-        for s in range(4):
-            ctx.fill_halos(cur)
+        for s, (src, dst) in enumerate(order):
+            ctx.fill_halos(src, stream)
             if timed:
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-            ctx.rhs(cur, k, precision)
+            ctx.rhs_rk4_stage(s, dt, src, Q, acc, dst, precision, stream)
             if timed:
                 e1.record(stream)
-                ev.setdefault("rhs", []).append((e0, e1))
-            nxt = Q if s == 3 else Qs
-            ctx.rk4_stage(s, dt, Q, k, acc, nxt)
-            cur = nxt
+                events.append((s, e0, e1))
 
     for _ in range(args.warmup):
         step(False)
@@ -60,11 +104,14 @@ def run_gpu(args, w, precision):
             print(f"# step {i + 1}/{args.steps}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    rhs_ms = sum(a.elapsed_time(b) for a, b in ev["rhs"]) / len(ev["rhs"])
-    norms, st = ctx.constraints(Q, r_excise=1.0)
     cells = ctx.n_patches * 729
-    out = dict(wall=wall, cells=cells, patches=ctx.n_patches, rhs_ms=rhs_ms, norms=norms, status=st)
-    del Q, Qs, k, acc
+    stage_ms = [a.elapsed_time(b) for _, a, b in events]
+    stage_bytes = [stage_bytes_per_cell(s) * cells for s, _, _ in events]
+    norms, st = ctx.constraints(Q, r_excise=1.0)
+    out = dict(wall=wall, cells=cells, patches=ctx.n_patches, stage_ms=sum(stage_ms) / len(stage_ms),
+               stage_bytes=sum(stage_bytes) / len(stage_bytes),
+               stage_gbs=sum(stage_bytes) / (sum(stage_ms) * 1e-3) / 1e9, norms=norms, status=st)
+    del Q, Q1, Q2, acc
     ctx.close()
     torch.cuda.empty_cache()
     return out
@@ -72,8 +119,8 @@ def run_gpu(args, w, precision):
 
 def cpu_baseline(w, target_s):
     """The oracle (single-threaded C, as it stands) on a bounded sample of the same workload:
-    the full mesh is initialised and filled once (untimed), then one RK4 stage is timed on a
-    sample of patches -- fill of the whole mesh and stage combine pro-rated to the sample."""
+    the full mesh is initialised and filled once, then one RK4 stage's RHS is timed on a sample
+    of patches; the fill of the whole mesh and the stage combine are pro-rated to the sample."""
     import numpy as np
     import oracle as orc
     from paper_2406_11626_amd import ccz4
@@ -84,7 +131,6 @@ def cpu_baseline(w, target_s):
     t = time.perf_counter()
     m.fill_halos(Q)
     t_fill = time.perf_counter() - t
-    # probe the RHS cost on 8 patches, then size the sample to ~target_s of work
     rng = np.random.default_rng(0)
     probe = sorted(rng.choice(m.np, 8, replace=False).tolist())
     k = np.zeros_like(Q)
@@ -104,8 +150,8 @@ def cpu_baseline(w, target_s):
     t_total = t_rhs + (t_fill + t_stage) * frac
     cells = n * 729
     return dict(value=cells / t_total, unit="cell-updates/s", cores=1, kind="oracle",
-                sample=f"one RK4 stage (fill + RHS + stage) on {n} of {m.np} patches ({cells} cells) "
-                       f"of the same workload; fill and stage pro-rated; {t_total:.1f} s of CPU work")
+                sample=f"one RK4 stage (fill + RHS + stage combine) on {n} of {m.np} patches ({cells} cells) "
+                       f"of the same workload; fill and combine pro-rated; {t_total:.1f} s of CPU work")
 
 
 def main():
@@ -117,6 +163,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision run")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference kernel for the HBM byte counters)")
     ap.add_argument("--progress", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -126,10 +174,17 @@ def main():
     from paper_2406_11626_amd import scenarios
     assert torch.cuda.is_available(), "no GPU"
     w = scenarios.config(args.config)
+    if args.copy_calibration:
+        a = torch.ones(2**27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
     r64 = run_gpu(args, w, 0)
     stages = 4 * args.steps
     value = r64["cells"] * stages / r64["wall"]
-    achieved = RHS_BYTES_PER_CELL * r64["cells"] / (r64["rhs_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic()
     line = {
         "metric": "CCZ4 cell-updates/s per RK4 stage (FP64 vs mixed), % of FP64/HBM roofline",
         "value": value,
@@ -145,15 +200,16 @@ def main():
         "data": "synthetic (analytic puncture initial data)",
         "config": {"workload": w.name, "patches": r64["patches"], "cells": r64["cells"],
                    "stages_per_step": 4, "dt": w.dt(), "precision": "fp64"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_rhs<double>",
-                     "avg_ms": r64["rhs_ms"], "algorithmic_bytes_per_cell": RHS_BYTES_PER_CELL},
+        "roofline": {"bound": "hbm", "achieved": r64["stage_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": r64["stage_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_stage<double>", "avg_ms": r64["stage_ms"],
+                     "algorithmic_bytes_per_launch": r64["stage_bytes"]},
         "constraints_after": {"L2_H": r64["norms"][0], "L2_M": r64["norms"][1], "nonfinite": r64["norms"][2]},
     }
     if not args.no_mixed:
         rm = run_gpu(args, w, 1)
-        line["mixed"] = {"value": rm["cells"] * stages / rm["wall"], "rhs_avg_ms": rm["rhs_ms"],
-                         "speedup_vs_fp64": (rm["cells"] * stages / rm["wall"]) / value,
+        vm = rm["cells"] * stages / rm["wall"]
+        line["mixed"] = {"value": vm, "stage_avg_ms": rm["stage_ms"], "speedup_vs_fp64": vm / value,
                          "L2_H": rm["norms"][0], "L2_M": rm["norms"][1]}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
