@@ -146,6 +146,17 @@ ccz4_status ccz4_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double *Qn
 ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double *Qs, const double *Qn,
                                double *acc, double *Qnext, int32_t precision, void *stream);
 
+/* Kernel choice for ccz4_rhs and ccz4_rhs_rk4_stage, per precision (CCZ4_PREC_FP64 or
+   CCZ4_PREC_MIXED).  Both kernels evaluate the same right-hand side (App. B algebra, App. D FD4
+   and KO stencils) and agree up to floating-point rounding order; they differ only in how the
+   stencil footprints reach the registers.  CCZ4_KERNEL_PHASED reads every stencil point from the
+   state in six phases; CCZ4_KERNEL_LDS copies each slot's slab footprint once into LDS per
+   evaluation, in four rounds.  Default after ccz4_create: CCZ4_KERNEL_LDS for both precisions.
+   EINVAL on an unknown precision or kernel, or a NULL out pointer. */
+typedef enum { CCZ4_KERNEL_PHASED = 0, CCZ4_KERNEL_LDS = 1 } ccz4_kernel;
+ccz4_status ccz4_set_kernel(ccz4_ctx *ctx, int32_t precision, int32_t kernel);
+ccz4_status ccz4_get_kernel(const ccz4_ctx *ctx, int32_t precision, int32_t *kernel);
+
 /* Constraint monitor.  Hamiltonian H = R + 2/3 K^2 - At_ij At^ij and momentum M_i (App. B) on every interior
    cell (FD4 derivatives; requires filled halos).  HM (device, may be NULL) receives
    HM[(p*4 + q)*729 + c] for q = H, Mx, My, Mz and interior cell c = (z*9 + y)*9 + x.

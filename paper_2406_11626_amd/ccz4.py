@@ -16,6 +16,7 @@ NV = 59
 CCZ4_OK, CCZ4_EINVAL, CCZ4_ENOMEM, CCZ4_ELAYOUT, CCZ4_EHIP, CCZ4_ENONFINITE, CCZ4_ESTATE = range(7)
 BC_PERIODIC, BC_NEUMANN, BC_SOMMERFELD = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
+KERNEL_PHASED, KERNEL_LDS = 0, 1
 SCEN_GAUGE_WAVE, SCEN_PUNCTURE, SCEN_BL_BY = 0, 1, 2
 
 
@@ -76,6 +77,8 @@ def lib():
             "ccz4_rhs_rk4_stage": (i32, [P, i32, f64, P, P, P, P, i32, P]),
             "ccz4_constraints": (i32, [P, P, P, f64, P, P]),
             "ccz4_tag_refine": (i32, [P, P, f64, f64, i32, P, P, P]),
+            "ccz4_set_kernel": (i32, [P, i32, i32]),
+            "ccz4_get_kernel": (i32, [P, i32, ctypes.POINTER(i32)]),
             "ccz4_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -183,6 +186,16 @@ def ccz4_rhs_rk4_stage(h, s, dt, Qs, Qn, acc, Qnext, precision=PREC_FP64, stream
                                            int(precision), _stream(stream)))
 
 
+def ccz4_set_kernel(h, precision, kernel):
+    return _check(lib().ccz4_set_kernel(h, int(precision), int(kernel)))
+
+
+def ccz4_get_kernel(h, precision):
+    out = ctypes.c_int32(-1)
+    _check(lib().ccz4_get_kernel(h, int(precision), ctypes.byref(out)))
+    return out.value
+
+
 def ccz4_constraints(h, Q, HM=None, r_excise=0.0, want_norms=True, stream=None):
     norms = (ctypes.c_double * 3)()
     st = lib().ccz4_constraints(h, _ptr(Q), _ptr(HM), float(r_excise),
@@ -255,6 +268,12 @@ class Context:
 
     def rhs_rk4_stage(self, s, dt, Qs, Qn, acc, Qnext, precision=PREC_FP64, stream=None):
         ccz4_rhs_rk4_stage(self.h, s, dt, Qs, Qn, acc, Qnext, precision, stream)
+
+    def set_kernel(self, precision, kernel):
+        ccz4_set_kernel(self.h, precision, kernel)
+
+    def get_kernel(self, precision):
+        return ccz4_get_kernel(self.h, precision)
 
     def rk4_step_fused(self, Qn, dt, bufs, precision=PREC_FP64, stream=None):
         """One RK4 step in place on Qn with the fused stage kernel; bufs = (Q1, Q2, acc)."""

@@ -92,6 +92,7 @@ struct ccz4_ctx {
     DevBuf<double> d_bg, d_part, d_out3, d_hm;
     double *h_out3 = nullptr;  // pinned
     bool bg_valid = false;
+    int32_t kernel[2] = {KV_LDS, KV_LDS};  // per precision
 };
 
 namespace {
@@ -437,7 +438,8 @@ ccz4_status ccz4_rhs(ccz4_ctx *c, const double *Q, double *k, int32_t precision,
     if (precision != CCZ4_PREC_FP64 && precision != CCZ4_PREC_MIXED) return fail(CCZ4_EINVAL, "bad precision");
     if (!c->bface.empty() && !c->bg_valid)
         return fail(CCZ4_ESTATE, "Sommerfeld background not set (call ccz4_init_patches or ccz4_set_background)");
-    HIP_TRY(launch_rhs(Q, k, c->d_geom.p, (int32_t)c->leaf.size(), c->prm, precision, S(stream)));
+    HIP_TRY(launch_rhs(Q, k, c->d_geom.p, (int32_t)c->leaf.size(), c->prm, precision, c->kernel[precision],
+                       S(stream)));
     HIP_TRY(launch_rhs_sommerfeld(Q, k, c->d_geom.p, c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(),
                                   c->prm.shift == 0, S(stream)));
     return CCZ4_OK;
@@ -478,7 +480,24 @@ ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *c, int32_t s, double dt, const double *
     if (!c->bface.empty() && !c->bg_valid)
         return fail(CCZ4_ESTATE, "Sommerfeld background not set (call ccz4_init_patches or ccz4_set_background)");
     HIP_TRY(launch_stage(s, dt, Qs, Qn, acc, Qnext, c->d_geom.p, (int32_t)c->leaf.size(), c->prm, precision,
-                         c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(), S(stream)));
+                         c->kernel[precision], c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(), S(stream)));
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_set_kernel(ccz4_ctx *c, int32_t precision, int32_t kernel)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    if (precision != CCZ4_PREC_FP64 && precision != CCZ4_PREC_MIXED) return fail(CCZ4_EINVAL, "bad precision");
+    if (kernel != CCZ4_KERNEL_PHASED && kernel != CCZ4_KERNEL_LDS) return fail(CCZ4_EINVAL, "unknown kernel");
+    c->kernel[precision] = kernel == CCZ4_KERNEL_LDS ? KV_LDS : KV_PHASED;
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_get_kernel(const ccz4_ctx *c, int32_t precision, int32_t *kernel)
+{
+    if (!c || !kernel) return fail(CCZ4_EINVAL, "ctx or kernel is NULL");
+    if (precision != CCZ4_PREC_FP64 && precision != CCZ4_PREC_MIXED) return fail(CCZ4_EINVAL, "bad precision");
+    *kernel = c->kernel[precision] == KV_LDS ? CCZ4_KERNEL_LDS : CCZ4_KERNEL_PHASED;
     return CCZ4_OK;
 }
 

@@ -7,6 +7,7 @@
 
 #include "ccz4_algebra.hpp"
 #include "ccz4_kernels.hpp"
+#include "ccz4_rhs_lds.hpp"
 #include "ccz4_rhs_phased.hpp"
 
 namespace ccz4 {
@@ -329,9 +330,9 @@ struct StageSink {
     double dt;
     double carry[12];  // s = 3: gt_ij and At_ij of Q^{n+1}, projected in finish()
 
-    __device__ __forceinline__ void combine(const CellRef &c, int v, double r)
+    __device__ __forceinline__ void combine_at(int o, int v, double r)
     {
-        const int e = v * CS + c.o;
+        const int e = v * CS + o;
         if (s == 0) {
             const double q0 = qn[e];
             acc[e] = q0 + (1.0 / 6.0) * dt * r;
@@ -346,9 +347,10 @@ struct StageSink {
             else qx[e] = val;
         }
     }
-    __device__ __forceinline__ void put(const CellRef &c, int v, double alg) { combine(c, v, alg + ko(c, v)); }
-    __device__ __forceinline__ void zero(const CellRef &c, int v) { combine(c, v, 0.0); }
-    __device__ __forceinline__ void finish(const CellRef &c)
+    __device__ __forceinline__ void put(const CellRef &c, int v, double alg) { combine_at(c.o, v, alg + ko(c, v)); }
+    __device__ __forceinline__ void zero(const CellRef &c, int v) { combine_at(c.o, v, 0.0); }
+    __device__ __forceinline__ void finish(const CellRef &c) { finish_at(c.o); }
+    __device__ __forceinline__ void finish_at(int o)
     {
         if (s != 3) return;
         double q[SAT + 6];
@@ -360,18 +362,73 @@ struct StageSink {
         project_cell(q);
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
-            qx[v * CS + c.o] = q[v];
-            qx[(SAT + v) * CS + c.o] = q[SAT + v];
+            qx[v * CS + o] = q[v];
+            qx[(SAT + v) * CS + o] = q[SAT + v];
         }
     }
 };
 
+// Fused stage on the Sommerfeld ghosts of boundary face fi: G_L of Qs combined at once into
+// stage s (one thread per ghost cell, all slots).
+__device__ __forceinline__ void stage_ghost_face(int fi, int idx, int32_t s, double dt, const double *__restrict__ Qs,
+                                                 const double *__restrict__ Qn, double *__restrict__ acc,
+                                                 double *__restrict__ Qx, const PatchGeom *__restrict__ geom,
+                                                 const BoundaryFace *__restrict__ bf, const double *__restrict__ bg,
+                                                 int32_t frozen)
+{
+    if (idx >= NFACE) return;
+    const BoundaryFace f = bf[fi];
+    int L, t1, t2;
+    slab_coords(f.axis, idx, L, t1, t2);
+    const int cg = ghost_c(f.side, L);
+    const int og = slab_off(f.axis, cg, t1, t2);
+    const int ci = L == 1 ? depth_c(f.side, 1) : ghost_c(f.side, L - 1);
+    const int oi = slab_off(f.axis, ci, t1, t2);
+    const PatchGeom g = geom[f.patch];
+    int cx, cy, cz;
+    if (f.axis == 0) { cx = cg; cy = t1 + 3; cz = t2 + 3; }
+    else if (f.axis == 1) { cx = t1 + 3; cy = cg; cz = t2 + 3; }
+    else { cx = t1 + 3; cy = t2 + 3; cz = cg; }
+    const double X = g.org[0] + (cx - 2.5) * g.dx[0];
+    const double Y = g.org[1] + (cy - 2.5) * g.dx[1];
+    const double Z = g.org[2] + (cz - 2.5) * g.dx[2];
+    const double rr = sqrt(X * X + Y * Y + Z * Z);
+    const double xn = f.axis == 0 ? X : (f.axis == 1 ? Y : Z);
+    const double cadv = rr / (fabs(xn) * g.dx[f.axis]), cdmp = 1.0 / rr;
+    const int64_t base = (int64_t)f.patch * PS;
+    const double *B = bg + (int64_t)f.bg * NV * NFACE + idx;
+    for (int v = 0; v < NV; ++v) {
+        double r = 0.0;
+        if (v != SK0 && !(frozen && frozen_slot(v))) {
+            const double qL = Qs[base + v * CS + og];
+            r = -cadv * (qL - Qs[base + v * CS + oi]) - cdmp * (qL - B[v * NFACE]);
+        }
+        const int64_t e = base + v * CS + og;
+        if (s == 0) {
+            const double q0 = Qn[e];
+            acc[e] = q0 + (1.0 / 6.0) * dt * r;
+            Qx[e] = q0 + 0.5 * dt * r;
+        } else if (s < 3) {
+            acc[e] = acc[e] + (1.0 / 3.0) * dt * r;
+            Qx[e] = Qn[e] + (s == 1 ? 0.5 : 1.0) * dt * r;
+        } else {
+            Qx[e] = acc[e] + (1.0 / 6.0) * dt * r;
+        }
+    }
+}
+
+
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WPE))) void k_stage(
     const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
-    const PatchGeom *__restrict__ geom, int32_t npatch, RhsParams prm, int32_t s, double dt)
+    const PatchGeom *__restrict__ geom, int32_t npatch, int32_t nb_slab, RhsParams prm, int32_t s, double dt,
+    const BoundaryFace *__restrict__ bf, const double *__restrict__ bg)
 {
-    const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    if ((int32_t)blockIdx.x >= nb_slab) {
+        stage_ghost_face((int)blockIdx.x - nb_slab, threadIdx.x, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, prm.shift == 0);
+        return;
+    }
+    const int64_t lb = xcd_logical_block(blockIdx.x, nb_slab);
     const int p = (int)(lb / 3);
     if (p >= npatch || threadIdx.x >= 243) return;
     const int c = (int)(lb % 3) * 243 + threadIdx.x;
@@ -392,6 +449,89 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WP
     snk.s = s;
     snk.dt = dt;
     rhs_cell_phased<T>(cr, prm, snk);
+}
+
+// LDS-staged variants: one work-group per (patch, z-slab), every lane takes part in staging;
+// the 151 KB of LDS leave one work-group per CU, so the waves may use the whole register file.
+__device__ __forceinline__ void lds_cell_setup(double *lds, int sl, const PatchGeom &g, const RhsParams &prm,
+                                               LdsCell &C, int &o, bool &act)
+{
+    const int tid = threadIdx.x;
+    act = tid < 243;
+    const int cc = act ? tid : 242;
+    const int x = cc % 9 + 3, y = (cc / 9) % 9 + 3, zl = cc / 81;
+    C.s = lds;
+    C.c = zl * ZS + y * YS + x;
+#pragma unroll
+    for (int k = -3; k <= 3; ++k) {
+        const int z2 = zl + k;
+        C.zo[k + 3] = (z2 >= 0 && z2 <= 2) ? z2 * ZS + y * YS + x
+                                            : LDS_OWN + (z2 < 0 ? z2 + 3 : z2) * 90 + (y - 3) * LDS_HROW + (x - 2);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        C.i12[a] = 1.0 / (12.0 * g.dx[a]);
+        C.koc[a] = prm.ko_eps / (64.0 * g.dx[a]);
+    }
+    o = boff(x, y, zl + 3 + 3 * sl);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rhs_lds(
+    const double *__restrict__ Q, double *__restrict__ K, const PatchGeom *__restrict__ geom, int32_t npatch,
+    RhsParams prm)
+{
+    __shared__ double lds[LDS_DOUBLES];
+    const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int p = (int)(lb / 3);
+    if (p >= npatch) return;  // uniform over the work-group
+    const int sl = (int)(lb % 3);
+    const PatchGeom g = geom[p];
+    LdsCell C;
+    int o;
+    bool act;
+    lds_cell_setup(lds, sl, g, prm, C, o, act);
+    LdsRhsSink snk;
+    snk.kb = K + (int64_t)p * PS;
+    snk.o = o;
+    rhs_slab_lds<T>(Q + (int64_t)p * PS, lds, sl, act, o, C, prm, snk);
+}
+
+struct LdsStageSink {
+    StageSink *st;
+    int o;
+    __device__ __forceinline__ void put(int v, double r) { st->combine_at(o, v, r); }
+    __device__ __forceinline__ void finish() { st->finish_at(o); }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_stage_lds(
+    const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
+    const PatchGeom *__restrict__ geom, int32_t npatch, int32_t nb_slab, RhsParams prm, int32_t s, double dt,
+    const BoundaryFace *__restrict__ bf, const double *__restrict__ bg)
+{
+    __shared__ double lds[LDS_DOUBLES];
+    if ((int32_t)blockIdx.x >= nb_slab) {
+        stage_ghost_face((int)blockIdx.x - nb_slab, threadIdx.x, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, prm.shift == 0);
+        return;
+    }
+    const int64_t lb = xcd_logical_block(blockIdx.x, nb_slab);
+    const int p = (int)(lb / 3);
+    if (p >= npatch) return;  // uniform over the work-group
+    const int sl = (int)(lb % 3);
+    const PatchGeom g = geom[p];
+    LdsCell C;
+    int o;
+    bool act;
+    lds_cell_setup(lds, sl, g, prm, C, o, act);
+    StageSink ss;
+    ss.qn = Qn + (int64_t)p * PS;
+    ss.acc = acc + (int64_t)p * PS;
+    ss.qx = Qx + (int64_t)p * PS;
+    ss.s = s;
+    ss.dt = dt;
+    LdsStageSink snk{&ss, o};
+    rhs_slab_lds<T>(Qs + (int64_t)p * PS, lds, sl, act, o, C, prm, snk);
 }
 
 // Sommerfeld ghosts: one thread per (boundary face, slot, ghost cell)
@@ -517,55 +657,6 @@ __global__ __launch_bounds__(256) void k_rk4_ghost(int32_t s, double dt, const d
     slab_coords(f.axis, idx, L, t1, t2);
     const int64_t e = (int64_t)f.patch * PS + v * CS + slab_off(f.axis, ghost_c(f.side, L), t1, t2);
     rk_one(s, dt, Qn, Kk, acc, Qx, e);
-}
-
-// Fused stage on Sommerfeld ghosts: G_L of Qs combined at once into stage s
-__global__ void k_stage_sommerfeld(int32_t s, double dt, const double *__restrict__ Qs,
-                                   const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
-                                   const PatchGeom *__restrict__ geom, const BoundaryFace *__restrict__ bf,
-                                   const double *__restrict__ bg, int32_t nbf, int32_t frozen)
-{
-    const int fi = blockIdx.x;
-    const int idx = threadIdx.x;
-    if (fi >= nbf || idx >= NFACE) return;
-    const BoundaryFace f = bf[fi];
-    int L, t1, t2;
-    slab_coords(f.axis, idx, L, t1, t2);
-    const int cg = ghost_c(f.side, L);
-    const int og = slab_off(f.axis, cg, t1, t2);
-    const int ci = L == 1 ? depth_c(f.side, 1) : ghost_c(f.side, L - 1);
-    const int oi = slab_off(f.axis, ci, t1, t2);
-    const PatchGeom g = geom[f.patch];
-    int cx, cy, cz;
-    if (f.axis == 0) { cx = cg; cy = t1 + 3; cz = t2 + 3; }
-    else if (f.axis == 1) { cx = t1 + 3; cy = cg; cz = t2 + 3; }
-    else { cx = t1 + 3; cy = t2 + 3; cz = cg; }
-    const double X = g.org[0] + (cx - 2.5) * g.dx[0];
-    const double Y = g.org[1] + (cy - 2.5) * g.dx[1];
-    const double Z = g.org[2] + (cz - 2.5) * g.dx[2];
-    const double rr = sqrt(X * X + Y * Y + Z * Z);
-    const double xn = f.axis == 0 ? X : (f.axis == 1 ? Y : Z);
-    const double cadv = rr / (fabs(xn) * g.dx[f.axis]), cdmp = 1.0 / rr;
-    const int64_t base = (int64_t)f.patch * PS;
-    const double *B = bg + (int64_t)f.bg * NV * NFACE + idx;
-    for (int v = 0; v < NV; ++v) {
-        double r = 0.0;
-        if (v != SK0 && !(frozen && frozen_slot(v))) {
-            const double qL = Qs[base + v * CS + og];
-            r = -cadv * (qL - Qs[base + v * CS + oi]) - cdmp * (qL - B[v * NFACE]);
-        }
-        const int64_t e = base + v * CS + og;
-        if (s == 0) {
-            const double q0 = Qn[e];
-            acc[e] = q0 + (1.0 / 6.0) * dt * r;
-            Qx[e] = q0 + 0.5 * dt * r;
-        } else if (s < 3) {
-            acc[e] = acc[e] + (1.0 / 3.0) * dt * r;
-            Qx[e] = Qn[e] + (s == 1 ? 0.5 : 1.0) * dt * r;
-        } else {
-            Qx[e] = acc[e] + (1.0 / 6.0) * dt * r;
-        }
-    }
 }
 
 // ------------------------------------------------------------------ constraints
@@ -735,29 +826,47 @@ hipError_t launch_fill(double *Q, const FaceTask *tasks, int32_t ntask, hipStrea
 }
 
 hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t npatch, const RhsParams &p,
-                      int32_t precision, hipStream_t st)
+                      int32_t precision, int32_t variant, hipStream_t st)
 {
     const int64_t nb = ((int64_t)npatch * 3 + 7) / 8 * 8;
-    if (precision == 1)
-        hipLaunchKernelGGL(k_rhs<float>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p);
-    else
-        hipLaunchKernelGGL(k_rhs<double>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p);
+    if (variant == KV_LDS) {
+        if (precision == 1)
+            hipLaunchKernelGGL(k_rhs_lds<float>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p);
+        else
+            hipLaunchKernelGGL(k_rhs_lds<double>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p);
+    } else {
+        if (precision == 1)
+            hipLaunchKernelGGL(k_rhs<float>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p);
+        else
+            hipLaunchKernelGGL(k_rhs<double>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p);
+    }
     return hipGetLastError();
 }
 
+// One launch: 3 work-groups per patch (grid padded to a multiple of 8 for the XCD mapping),
+// then one work-group per Sommerfeld boundary face.
 hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn, double *acc, double *Qx,
                         const PatchGeom *geom, int32_t npatch, const RhsParams &p, int32_t precision,
-                        const BoundaryFace *bf, const double *bg, int32_t nbf, hipStream_t st)
+                        int32_t variant, const BoundaryFace *bf, const double *bg, int32_t nbf, hipStream_t st)
 {
-    const int64_t nb = ((int64_t)npatch * 3 + 7) / 8 * 8;
-    if (precision == 1)
-        hipLaunchKernelGGL(k_stage<float>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch, p, s, dt);
-    else
-        hipLaunchKernelGGL(k_stage<double>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch, p, s, dt);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || nbf <= 0) return e;
-    hipLaunchKernelGGL(k_stage_sommerfeld, dim3(nbf), dim3(256), 0, st, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, nbf,
-                       p.shift == 0);
+    const int64_t nb_slab = ((int64_t)npatch * 3 + 7) / 8 * 8;
+    const int64_t nb = nb_slab + (nbf > 0 ? nbf : 0);
+    const int32_t ns = (int32_t)nb_slab;
+    if (variant == KV_LDS) {
+        if (precision == 1)
+            hipLaunchKernelGGL(k_stage_lds<float>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch,
+                               ns, p, s, dt, bf, bg);
+        else
+            hipLaunchKernelGGL(k_stage_lds<double>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom,
+                               npatch, ns, p, s, dt, bf, bg);
+    } else {
+        if (precision == 1)
+            hipLaunchKernelGGL(k_stage<float>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
+                               p, s, dt, bf, bg);
+        else
+            hipLaunchKernelGGL(k_stage<double>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch,
+                               ns, p, s, dt, bf, bg);
+    }
     return hipGetLastError();
 }
 

@@ -14,11 +14,14 @@ struct InitArgs {
 hipError_t launch_init(double *Q, const PatchGeom *geom, const uint8_t *bmask, int32_t npatch, int32_t scen,
                        const InitArgs &a, hipStream_t st);
 hipError_t launch_fill(double *Q, const FaceTask *tasks, int32_t ntask, hipStream_t st);
+// right-hand side / fused stage kernel variants
+enum KernelVariant : int32_t { KV_PHASED = 0, KV_LDS = 1, KV_COUNT = 2 };
+
 hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t npatch, const RhsParams &p,
-                      int32_t precision, hipStream_t st);
+                      int32_t precision, int32_t variant, hipStream_t st);
 hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn, double *acc, double *Qx,
                         const PatchGeom *geom, int32_t npatch, const RhsParams &p, int32_t precision,
-                        const BoundaryFace *bf, const double *bg, int32_t nbf, hipStream_t st);
+                        int32_t variant, const BoundaryFace *bf, const double *bg, int32_t nbf, hipStream_t st);
 hipError_t launch_rhs_sommerfeld(const double *Q, double *K, const PatchGeom *geom, const BoundaryFace *bf,
                                  const double *bg, int32_t nbf, int32_t frozen, hipStream_t st);
 hipError_t launch_capture_bg(const double *Q, const BoundaryFace *bf, double *bg, int32_t nbf, hipStream_t st);

@@ -38,7 +38,8 @@ def test_argument_errors_without_gpu():
     assert b"NULL" in L.ccz4_last_error()
     for fn, args in (("ccz4_fill_halos", (None, None, None)), ("ccz4_rhs", (None, None, None, 0, None)),
                      ("ccz4_rk4_stage", (None, 0, 0.1, None, None, None, None, None)),
-                     ("ccz4_constraints", (None, None, None, 0.0, None, None))):
+                     ("ccz4_constraints", (None, None, None, 0.0, None, None)),
+                     ("ccz4_set_kernel", (None, 0, 1)), ("ccz4_get_kernel", (None, 0, None))):
         assert getattr(L, fn)(*args) == ccz4.CCZ4_EINVAL
     g = ccz4.GridDesc()
     g.n0[:] = [0, 1, 1]

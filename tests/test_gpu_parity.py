@@ -14,6 +14,7 @@ from paper_2406_11626_amd import ccz4, scenarios  # noqa: E402
 from seeded_inputs import box_centers, smooth_state  # noqa: E402
 
 TOL = 1e-12
+KERNELS = [ccz4.KERNEL_PHASED, ccz4.KERNEL_LDS]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -27,8 +28,11 @@ def oparams(prm):
     return orc.Params(**{f: getattr(prm, f) for f, _ in ccz4.Params._fields_})
 
 
-def make_pair(n0, origin, extent, bc, prm, refined=()):
+def make_pair(n0, origin, extent, bc, prm, refined=(), kernel=ccz4.KERNEL_LDS):
     ctx = ccz4.Context(n0, origin, extent, bc, prm, refined)
+    for prec in (ccz4.PREC_FP64, ccz4.PREC_MIXED):
+        ctx.set_kernel(prec, kernel)
+        assert ctx.get_kernel(prec) == kernel
     m = orc.Mesh(n0, origin, extent, bc, refined)
     assert ctx.n_patches == m.np
     assert np.array_equal(ctx.ids, m.ids)
@@ -117,10 +121,11 @@ PARAM_SETS = [
 ]
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("ps", range(len(PARAM_SETS)))
-def test_rhs_parity_random_states(ps):
+def test_rhs_parity_random_states(ps, kernel):
     prm = ccz4.params(**PARAM_SETS[ps])
-    ctx, m = make_pair((2, 2, 1), (-0.4, 0.1, 0.2), (1.6, 1.6, 0.8), ccz4.BC_PERIODIC, prm)
+    ctx, m = make_pair((2, 2, 1), (-0.4, 0.1, 0.2), (1.6, 1.6, 0.8), ccz4.BC_PERIODIC, prm, kernel=kernel)
     Qo = random_state(m, 20 + ps, frozen=PARAM_SETS[ps]["shift"] == 0)
     m.fill_halos(Qo)
     Qd = to_gpu(Qo)
@@ -132,9 +137,10 @@ def test_rhs_parity_random_states(ps):
     assert np.array_equal(to_host(Qd), Qo)  # Q untouched
 
 
-def test_rhs_parity_gauge_wave_config1():
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_rhs_parity_gauge_wave_config1(kernel):
     w = scenarios.config(1)
-    ctx, m = make_pair(w.n0, w.origin, w.extent, w.bc, w.params())
+    ctx, m = make_pair(w.n0, w.origin, w.extent, w.bc, w.params(), kernel=kernel)
     Qo = m.zeros()
     m.init(Qo, w.scenario, w.scen)
     m.fill_halos(Qo)
@@ -145,10 +151,11 @@ def test_rhs_parity_gauge_wave_config1():
     assert e.max() <= TOL, (e.argmax(), e.max())
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("cfg", [2, 5])
-def test_rhs_parity_punctures_with_sommerfeld_ghosts(cfg):
+def test_rhs_parity_punctures_with_sommerfeld_ghosts(cfg, kernel):
     w = scenarios.config(cfg)
-    ctx, m = make_pair((2, 2, 2), w.origin, w.extent, w.bc, w.params())
+    ctx, m = make_pair((2, 2, 2), w.origin, w.extent, w.bc, w.params(), kernel=kernel)
     Qo = m.zeros()
     m.init(Qo, w.scenario, w.scen)
     m.fill_halos(Qo)
@@ -305,6 +312,12 @@ def test_full_size_sampled(cfg):
     if w.bc == ccz4.BC_SOMMERFELD:
         e = parity_error(to_host(kd, sel), ko, SLABS)
         assert e.max() <= TOL, ("rhs ghosts", e.argmax(), e.max())
+    # the other kernel on the same full mesh
+    ctx.set_kernel(ccz4.PREC_FP64, ccz4.KERNEL_PHASED)
+    ctx.rhs(Qd, kd)
+    e = parity_error(to_host(kd, sel), ko, INTERIOR)
+    assert e.max() <= TOL, ("rhs phased", e.argmax(), e.max())
+    ctx.set_kernel(ccz4.PREC_FP64, ccz4.KERNEL_LDS)
     del kd
     # (c) fill: the same interiors with every non-Sommerfeld halo poisoned
     Qp = Qo.copy()
@@ -334,8 +347,8 @@ def test_full_size_sampled(cfg):
 
 # ------------------------------------------------------------------ fused stage
 
-def _fused_vs_oracle(w, n0, refined=(), steps=2, perturb=False):
-    ctx, m = make_pair(n0, w.origin, w.extent, w.bc, w.params(), refined)
+def _fused_vs_oracle(w, n0, refined=(), steps=2, perturb=False, kernel=ccz4.KERNEL_LDS):
+    ctx, m = make_pair(n0, w.origin, w.extent, w.bc, w.params(), refined, kernel=kernel)
     Qo = m.zeros()
     m.init(Qo, w.scenario, w.scen)
     if perturb:
@@ -372,25 +385,29 @@ def boundary_ghost_mask(m, n0):
     return out
 
 
-def test_fused_stage_config1_matches_oracle():
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_fused_stage_config1_matches_oracle(kernel):
     w = scenarios.config(1)
-    e, _, _, _ = _fused_vs_oracle(w, w.n0, steps=10)
+    e, _, _, _ = _fused_vs_oracle(w, w.n0, steps=10, kernel=kernel)
     assert e.max() <= 1e-11, (e.argmax(), e.max())
 
 
-def test_fused_stage_puncture_sommerfeld_matches_oracle():
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_fused_stage_puncture_sommerfeld_matches_oracle(kernel):
     w = scenarios.config(2)
-    e, eg, _, _ = _fused_vs_oracle(w, (2, 2, 2), steps=2, perturb=True)
+    e, eg, _, _ = _fused_vs_oracle(w, (2, 2, 2), steps=2, perturb=True, kernel=kernel)
     assert e.max() <= 1e-11, (e.argmax(), e.max())
     assert eg.max() <= 1e-11, (eg.argmax(), eg.max())
 
 
-def test_fused_stage_amr_matches_unfused_gpu_path():
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_fused_stage_amr_matches_unfused_gpu_path(kernel):
     """Fused and unfused GPU steps on a mesh with coarse-fine faces agree (the oracle's own AMR
     step is checked by the sampled tests); differences come from summation order only."""
     w = scenarios.config(2)
     refined = [(0, 1, 1, 1)]
     ctx = ccz4.Context((3, 3, 3), (-9.0,) * 3, (18.0,) * 3, w.bc, w.params(), refined)
+    ctx.set_kernel(ccz4.PREC_FP64, kernel)
     Q = ctx.new_state(0.0)
     ctx.init_patches(Q, w.scenario, w.scen)
     Q2 = Q.clone()
@@ -412,11 +429,14 @@ def test_fused_stage_rejects_aliasing():
             ctx.rhs_rk4_stage(*args)
 
 
-def test_mixed_precision_stage_error_bound():
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_mixed_precision_stage_error_bound(kernel):
     """FP32 nonlinear algebra with FP64 state: after two fused RK4 steps of the perturbed
     puncture, the state differs from the FP64 path by a small relative amount per slot."""
     w = scenarios.config(2)
     ctx = ccz4.Context((2, 2, 2), w.origin, w.extent, w.bc, w.params())
+    for prec in (ccz4.PREC_FP64, ccz4.PREC_MIXED):
+        ctx.set_kernel(prec, kernel)
     Q = ctx.new_state(0.0)
     ctx.init_patches(Q, w.scenario, w.scen)
     Qm = Q.clone()
@@ -427,3 +447,42 @@ def test_mixed_precision_stage_error_bound():
         ctx.rk4_step_fused(Qm, w.dt(), b2, ccz4.PREC_MIXED)
     e = parity_error(to_host(Qm), to_host(Q), INTERIOR)
     assert e.max() <= 1e-6, (e.argmax(), e.max())
+
+
+def test_kernels_agree_on_a_static_amr_mesh():
+    """Both right-hand-side kernels on every leaf of a two-level mesh with Sommerfeld faces,
+    random smooth state: they agree with each other to rounding, and the LDS kernel with the
+    oracle, for both the plain RHS and one fused stage."""
+    w = scenarios.config(2)
+    refined = [(0, 1, 1, 1), (0, 2, 1, 1)]
+    ctx, m = make_pair((4, 3, 3), (-9.0, -6.75, -6.75), (18.0, 13.5, 13.5), w.bc, w.params(), refined)
+    Qo = random_state(m, 61)
+    m.fill_halos(Qo)
+    Qd = to_gpu(Qo)
+    ctx.set_background(Qd)
+    k_ph, k_lds = ctx.new_state(0.0), ctx.new_state(0.0)
+    ctx.set_kernel(ccz4.PREC_FP64, ccz4.KERNEL_PHASED)
+    ctx.rhs(Qd, k_ph)
+    ctx.set_kernel(ccz4.PREC_FP64, ccz4.KERNEL_LDS)
+    ctx.rhs(Qd, k_lds)
+    e = parity_error(to_host(k_lds), to_host(k_ph), INTERIOR)
+    assert e.max() <= 1e-13, (e.argmax(), e.max())
+    e = parity_error(to_host(k_lds), m.rhs(oparams(w.params()), Qo), INTERIOR)
+    assert e.max() <= TOL, (e.argmax(), e.max())
+    outs = []
+    for kern in KERNELS:
+        ctx.set_kernel(ccz4.PREC_FP64, kern)
+        acc, Qx = ctx.new_state(0.0), ctx.new_state(0.0)
+        ctx.rhs_rk4_stage(1, 0.01, Qd, Qd.clone(), acc, Qx)
+        outs.append((to_host(acc), to_host(Qx)))
+    for a, b in zip(outs[0], outs[1]):
+        e = parity_error(b, a, INTERIOR)
+        assert e.max() <= 1e-13, (e.argmax(), e.max())
+
+
+def test_kernel_selection_rejects_bad_arguments():
+    ctx = ccz4.Context((1, 1, 1), (0, 0, 0), (1.0, 1.0, 1.0), ccz4.BC_PERIODIC, ccz4.params())
+    for args in ((2, 0), (0, 2), (-1, 1), (0, -1)):
+        with pytest.raises(ccz4.CCZ4Error):
+            ctx.set_kernel(*args)
+    assert ctx.get_kernel(ccz4.PREC_FP64) == ccz4.KERNEL_LDS
