@@ -2,14 +2,16 @@
 
 A step is one classical RK4 step of the whole hot path over the single-puncture workload of
 16^3 patches of 9^3 cells (144^3 = 2,985,984 cells on [-9,9]^3, Sommerfeld boundaries, 1+log
-slicing, Gamma-driver): four times (halo fill; fused stage = FD4 derivatives + CCZ4 algebra +
-Kreiss-Oliger + RK4 stage combine, the last stage with the algebraic projection).  The metric
-is cell-updates per second per RK4 stage: cells x 4 stages x steps / wall time, with the state
-resident in HBM.
+slicing, Gamma-driver): four fused stages (FD4 derivatives + CCZ4 algebra + Kreiss-Oliger + RK4
+stage combine, the last stage with the algebraic projection), each of which also writes the
+same-level face halos of its output; the Neumann and coarse-fine halo fill between stages has
+no faces on this uniform mesh.  The metric is cell-updates per second per RK4 stage: cells x 4
+stages x steps / wall time, with the state resident in HBM.
 
 The roofline object is the fused stage kernel's: algorithmic bytes per launch (per cell: every
 evolved slot with its three-cell face halos read once, the step state and accumulator streamed
-as the stage requires) over its average launch time, taken with events on the launch stream.
+as the stage requires; plus the same-level halo cells written) over its average launch time,
+taken with events on the launch stream.
 
 Prints one JSON line.  --gpus N > 1 is not supported (the path runs on one GPU).
 """
@@ -32,8 +34,15 @@ QS_BYTES_PER_CELL = 8 * (58 * 3 + 1)
 STREAM_BYTES_PER_CELL = {0: 3 * 8 * NV, 1: 4 * 8 * NV, 2: 4 * 8 * NV, 3: 2 * 8 * NV}
 
 
+HALO_BYTES_PER_FACE = 243 * NV * 8   # a same-level face halo written by the stage
+
+
 def stage_bytes_per_cell(s):
     return QS_BYTES_PER_CELL + STREAM_BYTES_PER_CELL[s]
+
+
+def stage_bytes(s, cells, same_level_faces):
+    return stage_bytes_per_cell(s) * cells + HALO_BYTES_PER_FACE * same_level_faces
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_puncture16_hbm_traffic.md")
@@ -80,19 +89,23 @@ def run_gpu(args, w, precision):
     dt = w.dt()
     stream = torch.cuda.current_stream()
     order = ((Q, Q1), (Q1, Q2), (Q2, Q1), (Q1, Q))
+    rest = ccz4.FILL_NEUMANN | ccz4.FILL_LEVELS
     events = []
+    ctx.fill_halos(Q, stream)
 
     def step(timed):
         for s, (src, dst) in enumerate(order):
-            ctx.fill_halos(src, stream)
+            if s > 0:
+                ctx.fill_halos_kinds(src, rest, stream)
             if timed:
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-            ctx.rhs_rk4_stage(s, dt, src, Q, acc, dst, precision, stream)
+            ctx.rhs_rk4_stage(s, dt, src, Q, acc, dst, precision, ccz4.STAGE_FILL_SAME_LEVEL, stream)
             if timed:
                 e1.record(stream)
                 events.append((s, e0, e1))
+        ctx.fill_halos_kinds(Q, rest, stream)
 
     for _ in range(args.warmup):
         step(False)
@@ -105,12 +118,15 @@ def run_gpu(args, w, precision):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     cells = ctx.n_patches * 729
+    nsame = ctx.plan_counts()["same_level"]
     stage_ms = [a.elapsed_time(b) for _, a, b in events]
-    stage_bytes = [stage_bytes_per_cell(s) * cells for s, _, _ in events]
+    launch_bytes = [stage_bytes(s, cells, nsame) for s, _, _ in events]
     norms, st = ctx.constraints(Q, r_excise=1.0)
+    kname = {ccz4.KERNEL_LDS: "k_stage_lds", ccz4.KERNEL_PHASED: "k_stage"}[ctx.get_kernel(precision)]
     out = dict(wall=wall, cells=cells, patches=ctx.n_patches, stage_ms=sum(stage_ms) / len(stage_ms),
-               stage_bytes=sum(stage_bytes) / len(stage_bytes),
-               stage_gbs=sum(stage_bytes) / (sum(stage_ms) * 1e-3) / 1e9, norms=norms, status=st)
+               stage_bytes=sum(launch_bytes) / len(launch_bytes),
+               stage_gbs=sum(launch_bytes) / (sum(stage_ms) * 1e-3) / 1e9, norms=norms, status=st,
+               kernel=kname + ("<double>" if precision == ccz4.PREC_FP64 else "<float>"))
     del Q, Q1, Q2, acc
     ctx.close()
     torch.cuda.empty_cache()
@@ -202,7 +218,7 @@ def main():
                    "stages_per_step": 4, "dt": w.dt(), "precision": "fp64"},
         "roofline": {"bound": "hbm", "achieved": r64["stage_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r64["stage_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_stage<double>", "avg_ms": r64["stage_ms"],
+                     "kernel": r64["kernel"], "avg_ms": r64["stage_ms"],
                      "algorithmic_bytes_per_launch": r64["stage_bytes"]},
         "constraints_after": {"L2_H": r64["norms"][0], "L2_M": r64["norms"][1], "nonfinite": r64["norms"][2]},
     }

@@ -120,6 +120,18 @@ ccz4_status ccz4_set_background(ccz4_ctx *ctx, const double *Q, void *stream);
    Sommerfeld ghosts are left untouched. */
 ccz4_status ccz4_fill_halos(ccz4_ctx *ctx, double *Q, void *stream);
 
+/* Halo fill restricted to some kinds of face (same semantics per face as ccz4_fill_halos):
+   CCZ4_FILL_SAME_LEVEL (copy from a same-level leaf, periodic wrap included), CCZ4_FILL_NEUMANN,
+   CCZ4_FILL_LEVELS (all restrictions, then all prolongations).  kinds = CCZ4_FILL_ALL is
+   ccz4_fill_halos.  EINVAL on unknown bits.  Pairs with CCZ4_STAGE_FILL_SAME_LEVEL below, which
+   leaves only the Neumann and coarse-fine faces to fill between stages. */
+enum { CCZ4_FILL_SAME_LEVEL = 1, CCZ4_FILL_NEUMANN = 2, CCZ4_FILL_LEVELS = 4, CCZ4_FILL_ALL = 7 };
+ccz4_status ccz4_fill_halos_kinds(ccz4_ctx *ctx, double *Q, int32_t kinds, void *stream);
+
+/* Face counts of the fill plan: counts[0..4] = same-level faces, Neumann faces, restriction
+   faces (coarse side), prolongation faces (fine side), Sommerfeld faces.  Host call. */
+ccz4_status ccz4_plan_counts(const ccz4_ctx *ctx, int64_t *counts);
+
 /* Right-hand side.  k = RHS(Q) on every interior cell: FD4 central derivatives of slots 11..57,
    the pointwise first-order CCZ4 algebra of App. B, plus the Kreiss-Oliger sum over the axes
    on the 58 evolved slots (frozen-shift slots get 0; slot 58 gets 0).  On Sommerfeld faces
@@ -142,9 +154,15 @@ ccz4_status ccz4_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double *Qn
    ccz4_rk4_stage combines it (interior cells and Sommerfeld ghosts; projection at s = 3), without
    storing the right-hand side.  Qs needs filled halos.  Qnext must not alias Qs (other cells
    still read it), may alias Qn only at s = 3; acc aliases none of them.  A step is
-   s = 0: (Qn -> Q1), 1: (Q1 -> Q2), 2: (Q2 -> Q1), 3: (Q1 -> Qn), each after a halo fill. */
+   s = 0: (Qn -> Q1), 1: (Q1 -> Q2), 2: (Q2 -> Q1), 3: (Q1 -> Qn), each after a halo fill.
+   flags: 0, or CCZ4_STAGE_FILL_SAME_LEVEL: the stage also writes every new interior value that
+   lies within three layers of a face shared with a same-level leaf into that leaf's face halo
+   of Qnext (what CCZ4_FILL_SAME_LEVEL would copy there afterwards), so that before the next
+   stage only ccz4_fill_halos_kinds(NEUMANN | LEVELS) remains; Qnext's halos are then complete
+   once that runs.  EINVAL on unknown flags. */
+enum { CCZ4_STAGE_FILL_SAME_LEVEL = 1 };
 ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double *Qs, const double *Qn,
-                               double *acc, double *Qnext, int32_t precision, void *stream);
+                               double *acc, double *Qnext, int32_t precision, int32_t flags, void *stream);
 
 /* Kernel choice for ccz4_rhs and ccz4_rhs_rk4_stage, per precision (CCZ4_PREC_FP64 or
    CCZ4_PREC_MIXED).  Both kernels evaluate the same right-hand side (App. B algebra, App. D FD4

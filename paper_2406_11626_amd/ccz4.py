@@ -17,6 +17,8 @@ CCZ4_OK, CCZ4_EINVAL, CCZ4_ENOMEM, CCZ4_ELAYOUT, CCZ4_EHIP, CCZ4_ENONFINITE, CCZ
 BC_PERIODIC, BC_NEUMANN, BC_SOMMERFELD = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 KERNEL_PHASED, KERNEL_LDS = 0, 1
+FILL_SAME_LEVEL, FILL_NEUMANN, FILL_LEVELS, FILL_ALL = 1, 2, 4, 7
+STAGE_FILL_SAME_LEVEL = 1
 SCEN_GAUGE_WAVE, SCEN_PUNCTURE, SCEN_BL_BY = 0, 1, 2
 
 
@@ -74,7 +76,9 @@ def lib():
             "ccz4_fill_halos": (i32, [P, P, P]),
             "ccz4_rhs": (i32, [P, P, P, i32, P]),
             "ccz4_rk4_stage": (i32, [P, i32, f64, P, P, P, P, P]),
-            "ccz4_rhs_rk4_stage": (i32, [P, i32, f64, P, P, P, P, i32, P]),
+            "ccz4_rhs_rk4_stage": (i32, [P, i32, f64, P, P, P, P, i32, i32, P]),
+            "ccz4_fill_halos_kinds": (i32, [P, P, i32, P]),
+            "ccz4_plan_counts": (i32, [P, ctypes.POINTER(i64)]),
             "ccz4_constraints": (i32, [P, P, P, f64, P, P]),
             "ccz4_tag_refine": (i32, [P, P, f64, f64, i32, P, P, P]),
             "ccz4_set_kernel": (i32, [P, i32, i32]),
@@ -172,6 +176,16 @@ def ccz4_fill_halos(h, Q, stream=None):
     return _check(lib().ccz4_fill_halos(h, _ptr(Q), _stream(stream)))
 
 
+def ccz4_fill_halos_kinds(h, Q, kinds, stream=None):
+    return _check(lib().ccz4_fill_halos_kinds(h, _ptr(Q), int(kinds), _stream(stream)))
+
+
+def ccz4_plan_counts(h):
+    out = (ctypes.c_int64 * 5)()
+    _check(lib().ccz4_plan_counts(h, out))
+    return dict(zip(("same_level", "neumann", "restrict", "prolong", "sommerfeld"), list(out)))
+
+
 def ccz4_rhs(h, Q, k, precision=PREC_FP64, stream=None):
     return _check(lib().ccz4_rhs(h, _ptr(Q), _ptr(k), int(precision), _stream(stream)))
 
@@ -181,9 +195,9 @@ def ccz4_rk4_stage(h, s, dt, Qn, k, acc, Qnext, stream=None):
                                        _stream(stream)))
 
 
-def ccz4_rhs_rk4_stage(h, s, dt, Qs, Qn, acc, Qnext, precision=PREC_FP64, stream=None):
+def ccz4_rhs_rk4_stage(h, s, dt, Qs, Qn, acc, Qnext, precision=PREC_FP64, flags=0, stream=None):
     return _check(lib().ccz4_rhs_rk4_stage(h, int(s), float(dt), _ptr(Qs), _ptr(Qn), _ptr(acc), _ptr(Qnext),
-                                           int(precision), _stream(stream)))
+                                           int(precision), int(flags), _stream(stream)))
 
 
 def ccz4_set_kernel(h, precision, kernel):
@@ -266,8 +280,14 @@ class Context:
     def tag_refine(self, Q, theta_r, theta_c, max_level, tags, indicator=None, stream=None):
         ccz4_tag_refine(self.h, Q, theta_r, theta_c, max_level, tags, indicator, stream)
 
-    def rhs_rk4_stage(self, s, dt, Qs, Qn, acc, Qnext, precision=PREC_FP64, stream=None):
-        ccz4_rhs_rk4_stage(self.h, s, dt, Qs, Qn, acc, Qnext, precision, stream)
+    def rhs_rk4_stage(self, s, dt, Qs, Qn, acc, Qnext, precision=PREC_FP64, flags=0, stream=None):
+        ccz4_rhs_rk4_stage(self.h, s, dt, Qs, Qn, acc, Qnext, precision, flags, stream)
+
+    def fill_halos_kinds(self, Q, kinds, stream=None):
+        ccz4_fill_halos_kinds(self.h, Q, kinds, stream)
+
+    def plan_counts(self):
+        return ccz4_plan_counts(self.h)
 
     def set_kernel(self, precision, kernel):
         ccz4_set_kernel(self.h, precision, kernel)
@@ -275,13 +295,24 @@ class Context:
     def get_kernel(self, precision):
         return ccz4_get_kernel(self.h, precision)
 
-    def rk4_step_fused(self, Qn, dt, bufs, precision=PREC_FP64, stream=None):
-        """One RK4 step in place on Qn with the fused stage kernel; bufs = (Q1, Q2, acc)."""
+    def rk4_step_fused(self, Qn, dt, bufs, precision=PREC_FP64, stream=None, push=True):
+        """One RK4 step in place on Qn with the fused stage kernel; bufs = (Q1, Q2, acc).
+        With push (default) every stage writes the same-level face halos of its output, so only
+        Neumann and coarse-fine faces are filled between stages; Qn must enter with all halos
+        filled (ccz4_fill_halos once after the initial data) and leaves with them filled."""
         Q1, Q2, acc = bufs
         order = ((Qn, Q1), (Q1, Q2), (Q2, Q1), (Q1, Qn))
+        rest = FILL_NEUMANN | FILL_LEVELS
         for s, (src, dst) in enumerate(order):
-            self.fill_halos(src, stream)
-            self.rhs_rk4_stage(s, dt, src, Qn, acc, dst, precision, stream)
+            if push:
+                if s > 0:
+                    self.fill_halos_kinds(src, rest, stream)
+                self.rhs_rk4_stage(s, dt, src, Qn, acc, dst, precision, STAGE_FILL_SAME_LEVEL, stream)
+            else:
+                self.fill_halos(src, stream)
+                self.rhs_rk4_stage(s, dt, src, Qn, acc, dst, precision, 0, stream)
+        if push:
+            self.fill_halos_kinds(Qn, rest, stream)
 
     def rk4_step(self, Qn, dt, bufs, precision=PREC_FP64, stream=None):
         """One RK4 step in place on Qn; bufs = (Qs, k, acc) work tensors of the state shape."""

@@ -80,12 +80,14 @@ struct ccz4_ctx {
     RhsParams prm;
     std::vector<std::array<int, 4>> leaf;     // lev, i, j, k
     std::vector<PatchGeom> geom;
-    std::vector<FaceTask> phase1, phase2;     // copy/neumann/restrict, then prolong
+    std::vector<FaceTask> ph_copy, ph_neu, ph_res, ph_pro;  // fill tasks by kind (restrict before prolong)
+    std::vector<int32_t> nbr;                 // [leaf][6] same-level face neighbour or -1
     std::vector<BoundaryFace> bface;
     std::vector<uint8_t> bmask;
     std::vector<int32_t> sib;
     DevBuf<PatchGeom> d_geom;
-    DevBuf<FaceTask> d_ph1, d_ph2;
+    DevBuf<FaceTask> d_phc, d_phn, d_phr, d_php;
+    DevBuf<int32_t> d_nbr;
     DevBuf<BoundaryFace> d_bf;
     DevBuf<uint8_t> d_bmask;
     DevBuf<int32_t> d_sib;
@@ -161,9 +163,12 @@ ccz4_status build_plan(ccz4_ctx *c, const ccz4_grid_desc *g)
         }
     }
     // face tasks
-    c->phase1.clear();
-    c->phase2.clear();
+    c->ph_copy.clear();
+    c->ph_neu.clear();
+    c->ph_res.clear();
+    c->ph_pro.clear();
     c->bface.clear();
+    c->nbr.assign(leaves.size() * 6, -1);
     c->bmask.assign(leaves.size(), 0);
     for (size_t p = 0; p < leaves.size(); ++p) {
         const int lev = leaves[p][0];
@@ -182,7 +187,7 @@ ccz4_status build_plan(ccz4_ctx *c, const ccz4_grid_desc *g)
                         n[a] = (n[a] + na) % na;
                     } else if (c->bc == CCZ4_BC_NEUMANN) {
                         t.kind = FK_NEUMANN;
-                        c->phase1.push_back(t);
+                        c->ph_neu.push_back(t);
                         continue;
                     } else {
                         BoundaryFace b{(int)p, a, side, (int)c->bface.size()};
@@ -195,7 +200,8 @@ ccz4_status build_plan(ccz4_ctx *c, const ccz4_grid_desc *g)
                 if (nb >= 0) {
                     t.kind = FK_COPY;
                     t.src[0] = nb;
-                    c->phase1.push_back(t);
+                    c->ph_copy.push_back(t);
+                    c->nbr[p * 6 + 2 * a + (side > 0 ? 1 : 0)] = nb;
                     continue;
                 }
                 // tangential axes in increasing order
@@ -214,7 +220,7 @@ ccz4_status build_plan(ccz4_ctx *c, const ccz4_grid_desc *g)
                                 return fail(CCZ4_ELAYOUT, "level jump of more than one across a face");
                             t.src[u2 * 3 + u1] = kid;
                         }
-                    c->phase1.push_back(t);
+                    c->ph_res.push_back(t);
                     continue;
                 }
                 if (lev == 0) return fail(CCZ4_ELAYOUT, "face neighbour missing at level 0");
@@ -224,7 +230,7 @@ ccz4_status build_plan(ccz4_ctx *c, const ccz4_grid_desc *g)
                 t.src[0] = cp;
                 t.o1 = n[b1] - 3 * (n[b1] / 3);
                 t.o2 = n[b2] - 3 * (n[b2] / 3);
-                c->phase2.push_back(t);
+                c->ph_pro.push_back(t);
             }
     }
     // siblings
@@ -323,8 +329,11 @@ ccz4_status ccz4_create(ccz4_ctx **out, const ccz4_grid_desc *g, const ccz4_para
     const int64_t nblk = constraints_blocks((int32_t)c->leaf.size());
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = c->d_geom.upload(c->geom);
-    if (e == hipSuccess) e = c->d_ph1.upload(c->phase1);
-    if (e == hipSuccess) e = c->d_ph2.upload(c->phase2);
+    if (e == hipSuccess) e = c->d_phc.upload(c->ph_copy);
+    if (e == hipSuccess) e = c->d_phn.upload(c->ph_neu);
+    if (e == hipSuccess) e = c->d_phr.upload(c->ph_res);
+    if (e == hipSuccess) e = c->d_php.upload(c->ph_pro);
+    if (e == hipSuccess) e = c->d_nbr.upload(c->nbr);
     if (e == hipSuccess) e = c->d_bf.upload(c->bface);
     if (e == hipSuccess) e = c->d_bmask.upload(c->bmask);
     if (e == hipSuccess) e = c->d_sib.upload(c->sib);
@@ -346,8 +355,11 @@ void ccz4_destroy(ccz4_ctx *c)
     if (!c) return;
     (void)hipDeviceSynchronize();
     c->d_geom.release();
-    c->d_ph1.release();
-    c->d_ph2.release();
+    c->d_phc.release();
+    c->d_phn.release();
+    c->d_phr.release();
+    c->d_php.release();
+    c->d_nbr.release();
     c->d_bf.release();
     c->d_bmask.release();
     c->d_sib.release();
@@ -423,8 +435,32 @@ ccz4_status ccz4_fill_halos(ccz4_ctx *c, double *Q, void *stream)
     if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
     ccz4_status st = check_ptr(Q, "Q");
     if (st) return st;
-    HIP_TRY(launch_fill(Q, c->d_ph1.p, (int32_t)c->phase1.size(), S(stream)));
-    HIP_TRY(launch_fill(Q, c->d_ph2.p, (int32_t)c->phase2.size(), S(stream)));
+    return ccz4_fill_halos_kinds(c, Q, CCZ4_FILL_ALL, stream);
+}
+
+ccz4_status ccz4_fill_halos_kinds(ccz4_ctx *c, double *Q, int32_t kinds, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    ccz4_status st = check_ptr(Q, "Q");
+    if (st) return st;
+    if (kinds & ~CCZ4_FILL_ALL) return fail(CCZ4_EINVAL, "unknown fill kinds");
+    if (kinds & CCZ4_FILL_SAME_LEVEL) HIP_TRY(launch_fill(Q, c->d_phc.p, (int32_t)c->ph_copy.size(), S(stream)));
+    if (kinds & CCZ4_FILL_NEUMANN) HIP_TRY(launch_fill(Q, c->d_phn.p, (int32_t)c->ph_neu.size(), S(stream)));
+    if (kinds & CCZ4_FILL_LEVELS) {
+        HIP_TRY(launch_fill(Q, c->d_phr.p, (int32_t)c->ph_res.size(), S(stream)));
+        HIP_TRY(launch_fill(Q, c->d_php.p, (int32_t)c->ph_pro.size(), S(stream)));
+    }
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_plan_counts(const ccz4_ctx *c, int64_t *counts)
+{
+    if (!c || !counts) return fail(CCZ4_EINVAL, "ctx or counts is NULL");
+    counts[0] = (int64_t)c->ph_copy.size();
+    counts[1] = (int64_t)c->ph_neu.size();
+    counts[2] = (int64_t)c->ph_res.size();
+    counts[3] = (int64_t)c->ph_pro.size();
+    counts[4] = (int64_t)c->bface.size();
     return CCZ4_OK;
 }
 
@@ -463,7 +499,7 @@ ccz4_status ccz4_rk4_stage(ccz4_ctx *c, int32_t s, double dt, const double *Qn, 
 }
 
 ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *c, int32_t s, double dt, const double *Qs, const double *Qn, double *acc,
-                               double *Qnext, int32_t precision, void *stream)
+                               double *Qnext, int32_t precision, int32_t flags, void *stream)
 {
     if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
     if (s < 0 || s > 3) return fail(CCZ4_EINVAL, "stage must be 0..3");
@@ -474,13 +510,15 @@ ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *c, int32_t s, double dt, const double *
     if (!st) st = check_ptr(Qnext, "Qnext");
     if (st) return st;
     if (precision != CCZ4_PREC_FP64 && precision != CCZ4_PREC_MIXED) return fail(CCZ4_EINVAL, "bad precision");
+    if (flags & ~CCZ4_STAGE_FILL_SAME_LEVEL) return fail(CCZ4_EINVAL, "unknown stage flags");
     if (Qnext == Qs) return fail(CCZ4_EINVAL, "Qnext must not alias Qs");
     if (s < 3 && Qnext == Qn) return fail(CCZ4_EINVAL, "Qnext may alias Qn only at s = 3");
     if (acc == Qs || acc == Qn || acc == Qnext) return fail(CCZ4_EINVAL, "acc must not alias the states");
     if (!c->bface.empty() && !c->bg_valid)
         return fail(CCZ4_ESTATE, "Sommerfeld background not set (call ccz4_init_patches or ccz4_set_background)");
     HIP_TRY(launch_stage(s, dt, Qs, Qn, acc, Qnext, c->d_geom.p, (int32_t)c->leaf.size(), c->prm, precision,
-                         c->kernel[precision], c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(), S(stream)));
+                         c->kernel[precision], c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(),
+                         (flags & CCZ4_STAGE_FILL_SAME_LEVEL) ? c->d_nbr.p : nullptr, S(stream)));
     return CCZ4_OK;
 }
 

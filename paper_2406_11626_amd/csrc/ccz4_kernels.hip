@@ -329,6 +329,17 @@ struct StageSink {
     int s;
     double dt;
     double carry[12];  // s = 3: gt_ij and At_ij of Q^{n+1}, projected in finish()
+    int64_t pd[3];     // offsets (doubles, from this cell) of its copies in same-level neighbours'
+                       // face halos of Q_next along each axis, 0 for none
+
+    // Q_next at element e, and its copies in the neighbours' halos
+    __device__ __forceinline__ void out(int64_t e, double val)
+    {
+        qx[e] = val;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            if (pd[a] != 0) qx[e + pd[a]] = val;
+    }
 
     __device__ __forceinline__ void combine_at(int o, int v, double r)
     {
@@ -336,15 +347,15 @@ struct StageSink {
         if (s == 0) {
             const double q0 = qn[e];
             acc[e] = q0 + (1.0 / 6.0) * dt * r;
-            qx[e] = q0 + 0.5 * dt * r;
+            out(e, q0 + 0.5 * dt * r);
         } else if (s < 3) {
             acc[e] = acc[e] + (1.0 / 3.0) * dt * r;
-            qx[e] = qn[e] + (s == 1 ? 0.5 : 1.0) * dt * r;
+            out(e, qn[e] + (s == 1 ? 0.5 : 1.0) * dt * r);
         } else {
             const double val = acc[e] + (1.0 / 6.0) * dt * r;
             if (v < 6) carry[v] = val;
             else if (v >= SAT && v < SAT + 6) carry[v - SAT + 6] = val;
-            else qx[e] = val;
+            else out(e, val);
         }
     }
     __device__ __forceinline__ void put(const CellRef &c, int v, double alg) { combine_at(c.o, v, alg + ko(c, v)); }
@@ -362,11 +373,33 @@ struct StageSink {
         project_cell(q);
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
-            qx[v * CS + o] = q[v];
-            qx[(SAT + v) * CS + o] = q[SAT + v];
+            out(v * CS + o, q[v]);
+            out((SAT + v) * CS + o, q[SAT + v]);
         }
     }
 };
+
+// Offsets (in doubles, relative to the cell's own element) of the copies of interior cell
+// (x, y, z) of patch p in the face halos of its same-level neighbours: a cell within three layers
+// of a face whose neighbour nbr[6p + 2a + (side > 0)] is a leaf of the same level appears in that
+// neighbour's ghost layer at box coordinate c_a - 9 (side +1) or c_a + 9 (side -1).  0: no copy.
+__device__ __forceinline__ void push_offsets(const int32_t *__restrict__ nbr, int p, int x, int y, int z, int o,
+                                             int64_t pd[3])
+{
+    const int c[3] = {x, y, z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        pd[a] = 0;
+        if (!nbr) continue;
+        const int side = c[a] >= 9 ? 1 : (c[a] <= 5 ? -1 : 0);
+        if (side == 0) continue;
+        const int np = nbr[p * 6 + 2 * a + (side > 0 ? 1 : 0)];
+        if (np < 0) continue;
+        int m[3] = {x, y, z};
+        m[a] = side > 0 ? c[a] - 9 : c[a] + 9;
+        pd[a] = (int64_t)(np - p) * PS + (boff(m[0], m[1], m[2]) - o);
+    }
+}
 
 // Fused stage on the Sommerfeld ghosts of boundary face fi: G_L of Qs combined at once into
 // stage s (one thread per ghost cell, all slots).
@@ -422,7 +455,7 @@ template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WPE))) void k_stage(
     const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
     const PatchGeom *__restrict__ geom, int32_t npatch, int32_t nb_slab, RhsParams prm, int32_t s, double dt,
-    const BoundaryFace *__restrict__ bf, const double *__restrict__ bg)
+    const BoundaryFace *__restrict__ bf, const double *__restrict__ bg, const int32_t *__restrict__ nbr)
 {
     if ((int32_t)blockIdx.x >= nb_slab) {
         stage_ghost_face((int)blockIdx.x - nb_slab, threadIdx.x, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, prm.shift == 0);
@@ -448,6 +481,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WP
     snk.qx = Qx + (int64_t)p * PS;
     snk.s = s;
     snk.dt = dt;
+    push_offsets(nbr, p, c % 9 + 3, (c / 9) % 9 + 3, c / 81 + 3, cr.o, snk.pd);
     rhs_cell_phased<T>(cr, prm, snk);
 }
 
@@ -508,7 +542,7 @@ template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_stage_lds(
     const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
     const PatchGeom *__restrict__ geom, int32_t npatch, int32_t nb_slab, RhsParams prm, int32_t s, double dt,
-    const BoundaryFace *__restrict__ bf, const double *__restrict__ bg)
+    const BoundaryFace *__restrict__ bf, const double *__restrict__ bg, const int32_t *__restrict__ nbr)
 {
     __shared__ double lds[LDS_DOUBLES];
     if ((int32_t)blockIdx.x >= nb_slab) {
@@ -530,6 +564,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     ss.qx = Qx + (int64_t)p * PS;
     ss.s = s;
     ss.dt = dt;
+    {
+        const int cc = act ? (int)threadIdx.x : 242;
+        push_offsets(nbr, p, cc % 9 + 3, (cc / 9) % 9 + 3, cc / 81 + 3 + 3 * sl, o, ss.pd);
+    }
     LdsStageSink snk{&ss, o};
     rhs_slab_lds<T>(Qs + (int64_t)p * PS, lds, sl, act, o, C, prm, snk);
 }
@@ -847,7 +885,8 @@ hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t
 // then one work-group per Sommerfeld boundary face.
 hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn, double *acc, double *Qx,
                         const PatchGeom *geom, int32_t npatch, const RhsParams &p, int32_t precision,
-                        int32_t variant, const BoundaryFace *bf, const double *bg, int32_t nbf, hipStream_t st)
+                        int32_t variant, const BoundaryFace *bf, const double *bg, int32_t nbf, const int32_t *nbr,
+                        hipStream_t st)
 {
     const int64_t nb_slab = ((int64_t)npatch * 3 + 7) / 8 * 8;
     const int64_t nb = nb_slab + (nbf > 0 ? nbf : 0);
@@ -855,17 +894,17 @@ hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn
     if (variant == KV_LDS) {
         if (precision == 1)
             hipLaunchKernelGGL(k_stage_lds<float>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                               ns, p, s, dt, bf, bg);
+                               ns, p, s, dt, bf, bg, nbr);
         else
             hipLaunchKernelGGL(k_stage_lds<double>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom,
-                               npatch, ns, p, s, dt, bf, bg);
+                               npatch, ns, p, s, dt, bf, bg, nbr);
     } else {
         if (precision == 1)
             hipLaunchKernelGGL(k_stage<float>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
-                               p, s, dt, bf, bg);
+                               p, s, dt, bf, bg, nbr);
         else
             hipLaunchKernelGGL(k_stage<double>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                               ns, p, s, dt, bf, bg);
+                               ns, p, s, dt, bf, bg, nbr);
     }
     return hipGetLastError();
 }

@@ -207,6 +207,34 @@ __device__ __forceinline__ double dot3(const double be[3], const double d[3])
     return be[0] * d[0] + be[1] * d[1] + be[2] * d[2];
 }
 
+// r = v, materialised here: the opaque move keeps the computation of v inside its block of
+// the algebra instead of letting it drift towards the round's output loop.
+__device__ __forceinline__ void keep(double &r, double v)
+{
+    r = v;
+    asm volatile("" : "+v"(r));
+}
+
+// Output slots of rounds 2, 3 and 4, in the order of the round's output buffer.
+__device__ constexpr int R2_OUT[15] = {SD, SD + 1, SD + 2, SD + 3, SD + 4, SD + 5, SD + 6, SD + 7,
+                                       SD + 8, SD + 9, SD + 10, SD + 11, SD + 12, SD + 13, SD + 14};
+__device__ constexpr int R3_OUT[20] = {SD + 15, SD + 16, SD + 17, SAT, SAT + 1, SAT + 2, SAT + 3,
+                                       SAT + 4, SAT + 5, SK, STHETA, SGHAT, SGHAT + 1, SGHAT + 2,
+                                       SA, SA + 1, SA + 2, SP, SP + 1, SP + 2};
+__device__ constexpr int R4_OUT[24] = {SB, SB + 1, SB + 2, SB + 3, SB + 4, SB + 5, SB + 6, SB + 7,
+                                       SB + 8, SBB, SBB + 1, SBB + 2, SG, SG + 1, SG + 2, SG + 3,
+                                       SG + 4, SG + 5, SALPHA, SBETA, SBETA + 1, SBETA + 2, SPHI, SK0};
+
+// Hand a round's outputs to the sink in one loop with no barrier in it, so that the sink's own
+// global loads (the RK4 combine reads Q^n and the accumulator) are all in flight together.
+template <typename Sink, int N>
+__device__ __forceinline__ void flush(Sink &snk, bool act, const int (&slots)[N], const double (&r)[N])
+{
+    if (!act) return;
+#pragma unroll
+    for (int j = 0; j < N; ++j) snk.put(slots[j], r[j]);
+}
+
 // Right-hand side of the lane's cell of slab sl of the patch at qp.  Every lane of the
 // work-group must call this (staging and barriers); only lanes with act = true compute.
 template <typename T, typename Sink>
@@ -224,6 +252,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
     T G1[3][3], H[3][3], U[3][3], E[6];
     T BB[3][3], curl[3][3];
     double rGb[3];
+    double ro2[15], ro3[20], ro4[24];  // each round's outputs, handed to the sink after the round
 
     // ------------------------------------------------------------ round 1: At, B
     {
@@ -382,9 +411,11 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
         for (int j = 0; j < 15; ++j) {
             const SlotDeriv sd = stencils(C, j);
             dD_accumulate<T>(sd.d, j, ig, G1, H, U, E);
-            snk.put(SD + j, dot3(be, sd.d) + static_cast<double>(partD[j / 6][j % 6]) + sd.k);
+            keep(ro2[j], dot3(be, sd.d) + static_cast<double>(partD[j / 6][j % 6]) + sd.k);
         }
     }
+
+    flush(snk, act, R2_OUT, ro2);
 
     // ------------------------------------------------------------ round 3
     // buffers: 0..2 D_zyy, D_zyz, D_zzz; 3..5 P; 6..8 A; 9..11 Ghat; 12 K; 13 Theta
@@ -408,7 +439,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
             for (int j = 0; j < 3; ++j) {
                 const SlotDeriv sd = stencils(C, j);
                 dD_accumulate<T>(sd.d, 15 + j, ig, G1, H, U, E);
-                snk.put(SD + 15 + j, dot3(be, sd.d) + static_cast<double>(partD[2][3 + j]) + sd.k);
+                keep(ro3[j], dot3(be, sd.d) + static_cast<double>(partD[2][3 + j]) + sd.k);
             }
         }
         {  // ---- Ricci sector: At, K, Theta; the curl term of B
@@ -588,21 +619,21 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
                     t += al * At[ij] * (Kt - T(2) * Th * cc);
                     t += T(-2) * al * (At[sym(i, 0)] * Am[0][j] + At[sym(i, 1)] * Am[1][j] + At[sym(i, 2)] * Am[2][j]);
                     const T tf = X[ij] - T(1.0 / 3.0) * g[ij] * trX;
-                    snk.put(SAT + ij, advkoAt[ij] + static_cast<double>(t) + phid * phid * static_cast<double>(tf));
+                    keep(ro3[3 + ij], advkoAt[ij] + static_cast<double>(t) + phid * phid * static_cast<double>(tf));
                 }
             const T kap1 = cvt<T>(p.kappa1), kap2 = cvt<T>(p.kappa2);
             CCZ4_PHASE_BARRIER();
             const SlotDeriv sK = stencils(C, 12);
-            snk.put(SK, dot3(be, sK.d) + static_cast<double>(-lapal + al * RpZ + al * Kt * (Kt - T(2) * Th * cc) -
+            keep(ro3[9], (dot3(be, sK.d) + static_cast<double>(-lapal + al * RpZ + al * Kt * (Kt - T(2) * Th * cc) -
                                                              T(3) * al * kap1 * (T(1) + kap2) * Th) +
-                            sK.k);
+                      sK.k));
             const T ee2 = cvt<T>(p.e * p.e);
             const T ZA = T(0.5) * phi2 * (dG[0] * A[0] + dG[1] * A[1] + dG[2] * A[2]);
             const SlotDeriv sTh = stencils(C, 13);
-            snk.put(STHETA, dot3(be, sTh.d) +
+            keep(ro3[10], (dot3(be, sTh.d) +
                                 static_cast<double>(T(0.5) * al * ee2 * (RpZ + T(2.0 / 3.0) * Kt * Kt - AA) -
                                                     al * Th * Kt * cc - ZA - al * kap1 * (T(2) + kap2) * Th) +
-                                sTh.k);
+                      sTh.k));
             // B without f d_k b^i (completed in round 4): B_k^l B_l^i and alpha^2 mu gt^ij (curl D - curl P)
             if (gdrv) {
                 T cP[3][3];
@@ -710,7 +741,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
                 const SlotDeriv sG = stencils(C, 9 + i);
                 const double advG = dot3(be, sG.d);
                 const double rG = advG + static_cast<double>(t);
-                snk.put(SGHAT + i, rG + sG.k);
+                keep(ro3[11 + i], rG + sG.k);
                 rGb[i] = rG - advG;
             }
         }
@@ -740,15 +771,17 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
                 t += Bm[k][0] * A[0] + Bm[k][1] * A[1] + Bm[k][2] * A[2];
                 t += -ga_lin * theta_term * A[k];
                 const SlotDeriv sA = stencils(C, 6 + k);
-                snk.put(SA + k, dot3(be, sA.d) + static_cast<double>(t) + sA.k);
+                keep(ro3[14 + k], dot3(be, sA.d) + static_cast<double>(t) + sA.k);
                 const T u = Bm[k][0] * P[0] + Bm[k][1] * P[1] + Bm[k][2] * P[2] + T(1.0 / 3.0) * (al * Kt - trB) * P[k];
                 const T phipart =
                     T(1.0 / 3.0) * (al * dK - sdBtr[k]) + T(1.0 / 3.0) * al * dtrA[k] + T(1.0 / 3.0) * Kt * A[k];
                 const SlotDeriv sP = stencils(C, 3 + k);
-                snk.put(SP + k, dot3(be, sP.d) + static_cast<double>(u) + phid * static_cast<double>(phipart) + sP.k);
+                keep(ro3[17 + k], dot3(be, sP.d) + static_cast<double>(u) + phid * static_cast<double>(phipart) + sP.k);
             }
         }
     }
+
+    flush(snk, act, R3_OUT, ro3);
 
     // ------------------------------------------------------------ round 4
     // buffers: 0..2 b; 3..8 gt; 9 alpha; 10..12 beta; 13 phi
@@ -775,15 +808,15 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
                     T t = ff * cvt<T>(sb.d[k]);
                     t += BB[k][i];
                     t += curl[k][i];
-                    snk.put(SB + 3 * k + i, advkoB[3 * k + i] + static_cast<double>(t));
+                    keep(ro4[3 * k + i], advkoB[3 * k + i] + static_cast<double>(t));
                 }
-                snk.put(SBB + i, rGb[i] + dot3(be, sb.d) - p.eta * q(SBB + i) + sb.k);
+                keep(ro4[9 + i], rGb[i] + dot3(be, sb.d) - p.eta * q(SBB + i) + sb.k);
             }
         } else {
 #pragma unroll
-            for (int s = 0; s < 9; ++s) snk.put(SB + s, 0.0);
+            for (int s = 0; s < 9; ++s) keep(ro4[s], 0.0);
 #pragma unroll
-            for (int i = 0; i < 3; ++i) snk.put(SBB + i, 0.0);
+            for (int i = 0; i < 3; ++i) keep(ro4[9 + i], 0.0);
         }
         // gt_ij, alpha, beta^i, phi, K_0
         double gd[6], igd[6], detg;
@@ -814,28 +847,29 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
                 for (int k = 0; k < 3; ++k) t += g[sym(k, i)] * Bm[j][k] + g[sym(k, j)] * Bm[i][k];
                 t += T(-2.0 / 3.0) * g[ij] * trB;
                 t += T(-2) * al * (At[ij] - T(1.0 / 3.0) * g[ij] * trAt);
-                snk.put(SG + ij, static_cast<double>(t) - (detg - 1.0) / p.tau * gd[ij] + stencils(C, 3 + ij).k);
+                keep(ro4[12 + ij], static_cast<double>(t) - (detg - 1.0) / p.tau * gd[ij] + stencils(C, 3 + ij).k);
             }
         const T Kt = cvt<T>(q(SK)), K0 = cvt<T>(q(SK0)), Th = cvt<T>(q(STHETA));
         const T ga = p.slicing == 1 ? T(2) / al : T(1);
-        snk.put(SALPHA, static_cast<double>(bet[0] * A[0] + bet[1] * A[1] + bet[2] * A[2] -
+        keep(ro4[18], (static_cast<double>(bet[0] * A[0] + bet[1] * A[1] + bet[2] * A[2] -
                                             al * al * ga * (Kt - K0 - T(2) * cc * Th)) +
-                            stencils(C, 9).k);
+                            stencils(C, 9).k));
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             if (gdrv)
-                snk.put(SBETA + i, static_cast<double>(bet[0] * Bm[0][i] + bet[1] * Bm[1][i] + bet[2] * Bm[2][i] +
+                keep(ro4[19 + i], (static_cast<double>(bet[0] * Bm[0][i] + bet[1] * Bm[1][i] + bet[2] * Bm[2][i] +
                                                        cvt<T>(p.f) * cvt<T>(q(SBB + i))) +
-                                       stencils(C, 10 + i).k);
+                                       stencils(C, 10 + i).k));
             else
-                snk.put(SBETA + i, 0.0);
+                keep(ro4[19 + i], 0.0);
         }
         const double phid = q(SPHI);
-        snk.put(SPHI, be[0] * q(SP) + be[1] * q(SP + 1) + be[2] * q(SP + 2) +
-                          phid * static_cast<double>((al * Kt - trB) * T(1.0 / 3.0)) + stencils(C, 13).k);
-        snk.put(SK0, 0.0);
-        snk.finish();
+        keep(ro4[22], (be[0] * q(SP) + be[1] * q(SP + 1) + be[2] * q(SP + 2) +
+                          phid * static_cast<double>((al * Kt - trB) * T(1.0 / 3.0)) + stencils(C, 13).k));
+        keep(ro4[23], 0.0);
     }
+    flush(snk, act, R4_OUT, ro4);
+    if (act) snk.finish();
 }
 
 }  // namespace ccz4

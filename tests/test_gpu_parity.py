@@ -347,7 +347,7 @@ def test_full_size_sampled(cfg):
 
 # ------------------------------------------------------------------ fused stage
 
-def _fused_vs_oracle(w, n0, refined=(), steps=2, perturb=False, kernel=ccz4.KERNEL_LDS):
+def _fused_vs_oracle(w, n0, refined=(), steps=2, perturb=False, kernel=ccz4.KERNEL_LDS, push=True):
     ctx, m = make_pair(n0, w.origin, w.extent, w.bc, w.params(), refined, kernel=kernel)
     Qo = m.zeros()
     m.init(Qo, w.scenario, w.scen)
@@ -357,11 +357,12 @@ def _fused_vs_oracle(w, n0, refined=(), steps=2, perturb=False, kernel=ccz4.KERN
     Qd = to_gpu(Qo)
     ctx.set_background(to_gpu(Qo))
     m.set_background(Qo)
+    ctx.fill_halos(Qd)
     bufs = (ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0))
     pr = oparams(w.params())
     dt = w.dt()
     for _ in range(steps):
-        ctx.rk4_step_fused(Qd, dt, bufs)
+        ctx.rk4_step_fused(Qd, dt, bufs, push=push)
         Qo = m.rk4_step(pr, Qo, dt)
     g = to_host(Qd)
     eg = np.zeros(59)
@@ -385,17 +386,19 @@ def boundary_ghost_mask(m, n0):
     return out
 
 
+@pytest.mark.parametrize("push", [True, False])
 @pytest.mark.parametrize("kernel", KERNELS)
-def test_fused_stage_config1_matches_oracle(kernel):
+def test_fused_stage_config1_matches_oracle(kernel, push):
     w = scenarios.config(1)
-    e, _, _, _ = _fused_vs_oracle(w, w.n0, steps=10, kernel=kernel)
+    e, _, _, _ = _fused_vs_oracle(w, w.n0, steps=10, kernel=kernel, push=push)
     assert e.max() <= 1e-11, (e.argmax(), e.max())
 
 
+@pytest.mark.parametrize("push", [True, False])
 @pytest.mark.parametrize("kernel", KERNELS)
-def test_fused_stage_puncture_sommerfeld_matches_oracle(kernel):
+def test_fused_stage_puncture_sommerfeld_matches_oracle(kernel, push):
     w = scenarios.config(2)
-    e, eg, _, _ = _fused_vs_oracle(w, (2, 2, 2), steps=2, perturb=True, kernel=kernel)
+    e, eg, _, _ = _fused_vs_oracle(w, (2, 2, 2), steps=2, perturb=True, kernel=kernel, push=push)
     assert e.max() <= 1e-11, (e.argmax(), e.max())
     assert eg.max() <= 1e-11, (eg.argmax(), eg.max())
 
@@ -410,6 +413,7 @@ def test_fused_stage_amr_matches_unfused_gpu_path(kernel):
     ctx.set_kernel(ccz4.PREC_FP64, kernel)
     Q = ctx.new_state(0.0)
     ctx.init_patches(Q, w.scenario, w.scen)
+    ctx.fill_halos(Q)
     Q2 = Q.clone()
     b1 = (ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0))
     b2 = (ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0))
@@ -417,6 +421,14 @@ def test_fused_stage_amr_matches_unfused_gpu_path(kernel):
     for _ in range(2):
         ctx.rk4_step_fused(Q, dt, b1)
         ctx.rk4_step(Q2, dt, b2)
+    e = parity_error(to_host(Q), to_host(Q2), INTERIOR)
+    assert e.max() <= 1e-13, (e.argmax(), e.max())
+    # the fused step with halo push leaves Q's halos filled; the unfused one leaves them from
+    # before its last stage: after a fill of the latter both agree on the halo slabs as well
+    Qf = Q.clone()
+    ctx.fill_halos(Q2)
+    ctx.fill_halos(Qf)
+    assert torch.equal(Qf, Q)
     e = parity_error(to_host(Q), to_host(Q2), INTERIOR | SLABS)
     assert e.max() <= 1e-13, (e.argmax(), e.max())
 
@@ -439,6 +451,7 @@ def test_mixed_precision_stage_error_bound(kernel):
         ctx.set_kernel(prec, kernel)
     Q = ctx.new_state(0.0)
     ctx.init_patches(Q, w.scenario, w.scen)
+    ctx.fill_halos(Q)
     Qm = Q.clone()
     b1 = (ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0))
     b2 = (ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0))
@@ -486,3 +499,42 @@ def test_kernel_selection_rejects_bad_arguments():
         with pytest.raises(ccz4.CCZ4Error):
             ctx.set_kernel(*args)
     assert ctx.get_kernel(ccz4.PREC_FP64) == ccz4.KERNEL_LDS
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("periodic", [True, False])
+def test_stage_push_writes_exactly_the_same_level_halos(kernel, periodic):
+    """A fused stage with CCZ4_STAGE_FILL_SAME_LEVEL leaves Qnext bit-identical to the same stage
+    without it followed by the same-level fill (s = 1 and the projected s = 3), on a mesh with
+    coarse-fine faces (left for the level fill) and periodic self-neighbours or Sommerfeld faces."""
+    if periodic:
+        w = scenarios.config(1)
+        ctx = ccz4.Context((1, 2, 3), (-0.5, -0.5, -0.5), (1.0 / 3, 2.0 / 3, 1.0), ccz4.BC_PERIODIC, w.params())
+        Q = ctx.new_state(0.0)
+        ctx.init_patches(Q, w.scenario, w.scen)
+    else:
+        w = scenarios.config(2)
+        ctx = ccz4.Context((3, 3, 2), (-9.0, -9.0, -6.0), (18.0, 18.0, 12.0), w.bc, w.params(), [(0, 1, 1, 0)])
+        Q = ctx.new_state(0.0)
+        ctx.init_patches(Q, w.scenario, w.scen)
+    counts = ctx.plan_counts()
+    assert counts["same_level"] > 0
+    if not periodic:
+        assert counts["restrict"] > 0 and counts["prolong"] > 0 and counts["sommerfeld"] > 0
+    ctx.set_kernel(ccz4.PREC_FP64, kernel)
+    ctx.fill_halos(Q)
+    for s in (1, 3):
+        acc = Q.clone()  # a valid state, so that the projection at s = 3 is well conditioned
+        a_push, a_ref = ctx.new_state(0.0), ctx.new_state(0.0)
+        acc2 = acc.clone()
+        ctx.rhs_rk4_stage(s, 0.01, Q, Q, acc, a_push, ccz4.PREC_FP64, ccz4.STAGE_FILL_SAME_LEVEL)
+        ctx.rhs_rk4_stage(s, 0.01, Q, Q, acc2, a_ref, ccz4.PREC_FP64, 0)
+        ctx.fill_halos_kinds(a_ref, ccz4.FILL_SAME_LEVEL)
+        assert bool(torch.isfinite(a_ref).all()), s
+        bad = (a_push != a_ref).nonzero()
+        assert bad.shape[0] == 0, (s, bad.shape[0], bad[:5].tolist())
+        assert torch.equal(acc, acc2), s
+    with pytest.raises(ccz4.CCZ4Error):
+        ctx.rhs_rk4_stage(1, 0.01, Q, Q, acc, a_push, ccz4.PREC_FP64, 2)
+    with pytest.raises(ccz4.CCZ4Error):
+        ctx.fill_halos_kinds(Q, 8)
