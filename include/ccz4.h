@@ -192,6 +192,52 @@ ccz4_status ccz4_constraints(ccz4_ctx *ctx, const double *Q, double *HM, double 
 ccz4_status ccz4_tag_refine(ccz4_ctx *ctx, const double *Q, double theta_r, double theta_c,
                             int32_t max_level, int8_t *tags, double *indicator, void *stream);
 
+/* ---------------------------------------------------------------------------------------
+   Learned refinement indicator (a project addition on the refinement-criterion hook of the
+   paper's Sec. 3): a small perceptron, trained on tags of the plain criterion, that can add
+   refinement ahead of the plain criterion and veto its coarsening; the plain criterion stays
+   the fallback.  Parameter vector of CCZ4_MLP_NPARAM floats, row-major (out x in):
+     W1[64][81] b1[64] W2[64][64] b2[64] W3[3][64] b3[3].
+   Inputs are standardised as x = (feat - mu) * inv_sigma in FP32 (norm = mu[81] followed by
+   inv_sigma[81]), then every matrix operand (x, weights, ReLU outputs; in the backward pass the
+   pre-activation gradients) is rounded to BF16 for the matrix cores, which accumulate in FP32.
+   All buffers are device memory owned by the caller; no call allocates. */
+enum { CCZ4_MLP_NIN = 81, CCZ4_MLP_NH = 64, CCZ4_MLP_NOUT = 3, CCZ4_MLP_NPARAM = 9603 };
+
+/* Per-leaf features (requires filled halos and HM from ccz4_constraints of the same Q): the
+   interior of each leaf is split into 3^3 blocks of 3^3 cells, b = (bz*3 + by)*3 + bx; feat[p*81
+   + 3b + q] = log10(max over the block of v_q + 1e-12) with v_0 = dx |grad chi| (chi = phi^2, FD4
+   of chi), v_1 = dx |grad alpha| (FD4), v_2 = dx^2 |H|, dx the leaf's spacing (the scaling of the
+   plain criterion's indicators, so that leaves of all levels are comparable).  feat: n_leaves x
+   81 floats. */
+ccz4_status ccz4_features(ccz4_ctx *ctx, const double *Q, const double *HM, float *feat, void *stream);
+
+/* logits[n][3] (classes COARSEN, KEEP, REFINE) of n standardised feature rows. */
+ccz4_status ccz4_mlp_forward(const float *params, const float *norm, const float *feat, int64_t n,
+                             float *logits, void *stream);
+
+/* Floats of workspace that ccz4_mlp_grad needs for n rows. */
+ccz4_status ccz4_mlp_workspace(int64_t n, int64_t *floats);
+
+/* Mean softmax cross-entropy of the logits of n rows against tags in {-1, 0, 1} (COARSEN,
+   KEEP, REFINE) and its gradient with respect to every parameter (grad: CCZ4_MLP_NPARAM floats;
+   loss: one float, may be NULL).  work: at least ccz4_mlp_workspace(n) floats. */
+ccz4_status ccz4_mlp_grad(const float *params, const float *norm, const float *feat, const int8_t *tags,
+                          int64_t n, float *work, int64_t work_floats, float *grad, float *loss, void *stream);
+
+/* One Adam step t >= 1 on every parameter (FP32): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+   params -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
+ccz4_status ccz4_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr,
+                          float beta1, float beta2, float eps, void *stream);
+
+/* Combined tags per leaf from the network's logits and the plain criterion's tags: a plain
+   REFINE stays; a REFINE predicted with softmax probability >= conf is added (below max_level);
+   a plain COARSEN survives unless the network predicts KEEP or REFINE with probability >= conf,
+   and a family coarsens only if all 27 of its leaves still do; otherwise KEEP.  Arg-max ties go
+   to the higher class. */
+ccz4_status ccz4_tag_learned(ccz4_ctx *ctx, const float *logits, const int8_t *plain_tags, float conf,
+                             int32_t max_level, int8_t *tags, void *stream);
+
 /* Message of the last failing call of this thread ("" if none). */
 const char *ccz4_last_error(void);
 

@@ -93,6 +93,57 @@ def _c(a, dt=np.float64):
     return np.ascontiguousarray(a, dtype=dt)
 
 
+_feat = _sig("orc_features", None, [ctypes.c_void_p, _dp, _dp])
+_bf16 = _sig("orc_bf16_round", ctypes.c_double, [ctypes.c_double])
+_tag_learned = _sig("orc_tag_learned", None, [ctypes.c_void_p, np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS"),
+                                              _i8p, ctypes.c_float, ctypes.c_int, _i8p])
+_fp = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_stdz = _sig("orc_mlp_standardize", None, [ctypes.c_int64, _fp, _fp, _dp])
+_mlp_fwd = _sig("orc_mlp_forward", None, [ctypes.c_int64, _dp, _dp, ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p])
+_mlp_grad = _sig("orc_mlp_loss_grad", ctypes.c_double, [ctypes.c_int64, _dp, _i32p, _dp, ctypes.c_int, _dp])
+_adam = _sig("orc_adam_step", None, [ctypes.c_int64, _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double])
+
+MLP_NIN, MLP_NH, MLP_NOUT, MLP_NPARAM = 81, 64, 3, 9603
+
+
+def bf16_round(x):
+    """Nearest BF16 (ties to even) of the FP32 value nearest to x."""
+    return float(_bf16(float(x)))
+
+
+def mlp_standardize(feat, norm):
+    feat = np.ascontiguousarray(feat, dtype=np.float32)
+    out = np.zeros(feat.shape, dtype=np.float64)
+    _stdz(feat.shape[0], feat, np.ascontiguousarray(norm, dtype=np.float32), out)
+    return out
+
+
+def mlp_forward(x, prm, bf16=True):
+    """(a1, a2, logits) of the perceptron on standardised inputs x[n][81]."""
+    x = _c(x)
+    n = x.shape[0]
+    a1, a2, z3 = np.zeros((n, MLP_NH)), np.zeros((n, MLP_NH)), np.zeros((n, MLP_NOUT))
+    _mlp_fwd(n, x, _c(prm), int(bf16), a1.ctypes.data, a2.ctypes.data, z3.ctypes.data)
+    return a1, a2, z3
+
+
+def mlp_loss_grad(x, labels, prm, bf16=True):
+    x = _c(x)
+    g = np.zeros(MLP_NPARAM)
+    loss = _mlp_grad(x.shape[0], x, np.ascontiguousarray(labels, dtype=np.int32), _c(prm), int(bf16), g)
+    return loss, g
+
+
+def adam_step(p, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """In place on float64 arrays p, m, v."""
+    _adam(p.size, p, m, v, _c(g), int(t), lr, b1, b2, eps)
+
+
+
+
 def rhs_point(pr, q, dq):
     out = np.zeros(NV)
     _rhs_point(ctypes.byref(pr), _c(q), _c(dq).reshape(-1), out)
@@ -206,6 +257,17 @@ class Mesh:
         ind = np.zeros((self.np, 3))
         _tag_ind(self._h, Q, ind)
         return ind
+
+    def features(self, Q):
+        f = np.zeros((self.np, MLP_NIN))
+        _feat(self._h, Q, f)
+        return f
+
+    def tag_learned(self, logits, plain, conf, max_level):
+        tags = np.zeros(self.np, dtype=np.int8)
+        _tag_learned(self._h, np.ascontiguousarray(logits, dtype=np.float32),
+                     np.ascontiguousarray(plain, dtype=np.int8), conf, max_level, tags)
+        return tags
 
     def tag_refine(self, Q, theta_r, theta_c, max_level):
         tags = np.zeros(self.np, dtype=np.int8)

@@ -903,3 +903,46 @@ void orc_tag_refine(const orc_mesh *m, const double *Q, double theta_r, double t
     free(ind);
     free(e);
 }
+
+/* Learned tags (the combination rule of the learned indicator with the plain criterion):
+   per leaf, the softmax of the three logits (COARSEN, KEEP, REFINE) and its arg-max class, ties
+   to the higher class, evaluated in FP32 as on the GPU; a plain REFINE stays, a REFINE predicted
+   with probability >= conf is added below max_level, a plain COARSEN survives unless KEEP or
+   REFINE is predicted with probability >= conf, and a family coarsens only if all 27 of its
+   leaves still do. */
+void orc_tag_learned(const orc_mesh *m, const float *logits, const int8_t *plain, float conf, int max_level,
+                     int8_t *tags)
+{
+    int64_t p;
+    int8_t *pre = (int8_t *)malloc(m->np ? (size_t)m->np : 1);
+    for (p = 0; p < m->np; p++) {
+        const float z0 = logits[3 * p], z1 = logits[3 * p + 1], z2 = logits[3 * p + 2];
+        const float zm = fmaxf(fmaxf(z0, z1), z2);
+        const float se = expf(z0 - zm) + expf(z1 - zm) + expf(z2 - zm);
+        const float pm = 1.0f / se;
+        const int cls = z2 >= zm ? 1 : (z1 >= zm ? 0 : -1);
+        const int sure = pm >= conf;
+        int8_t tg = 0;
+        if (plain[p] == 1) tg = 1;
+        else if (sure && cls == 1 && m->id[4 * p] < max_level) tg = 1;
+        else if (plain[p] == -1 && !(sure && cls != -1)) tg = -1;
+        pre[p] = tg;
+    }
+    for (p = 0; p < m->np; p++) {
+        int8_t tg = pre[p];
+        const int lev = m->id[4 * p];
+        if (tg == -1) {
+            int u, v, w;
+            const int pi = m->id[4 * p + 1] / 3, pj = m->id[4 * p + 2] / 3, pk = m->id[4 * p + 3] / 3;
+            if (lev == 0) tg = 0;
+            for (w = 0; w < 3 && tg; w++)
+                for (v = 0; v < 3 && tg; v++)
+                    for (u = 0; u < 3 && tg; u++) {
+                        const int64_t s = lev > 0 ? find_leaf(m, lev, 3 * pi + u, 3 * pj + v, 3 * pk + w) : -1;
+                        if (s < 0 || pre[s] != -1) tg = 0;
+                    }
+        }
+        tags[p] = tg;
+    }
+    free(pre);
+}

@@ -89,16 +89,23 @@ void orc_tag_indicator(const orc_mesh *m, const double *Q, double *ind /* [n][3]
 void orc_tag_refine(const orc_mesh *m, const double *Q, double theta_r, double theta_c,
                     int max_level, int8_t *tags);
 
-/* ---- learned-indicator MLP, FP64 with BF16-rounded operands ---- */
+/* ---- learned refinement indicator (ccz4_mlp.c) ---- */
+#define ORC_MLP_NIN 81
+#define ORC_MLP_NH 64
+#define ORC_MLP_NOUT 3
+#define ORC_MLP_NPARAM 9603 /* W1[64][81] b1[64] W2[64][64] b2[64] W3[3][64] b3[3] */
 void orc_features(const orc_mesh *m, const double *Q, double *feat /* [n][81] */);
 double orc_bf16_round(double x);
-void orc_mlp_forward(int n, const double *x /* [n][81] */, const double *W1, const double *b1,
-                     const double *W2, const double *b2, const double *W3, const double *b3,
-                     double *h1, double *h2, double *logits);
-double orc_mlp_loss_grad(int n, const double *x, const int *labels, const double *W1,
-                         const double *b1, const double *W2, const double *b2, const double *W3,
-                         const double *b3, double *gW1, double *gb1, double *gW2, double *gb2,
-                         double *gW3, double *gb3);
+void orc_mlp_standardize(int64_t n, const float *feat, const float *norm /* mu[81], inv_sigma[81] */,
+                         double *x);
+void orc_mlp_forward(int64_t n, const double *x, const double *prm, int bf16, double *a1, double *a2,
+                     double *z3);
+double orc_mlp_loss_grad(int64_t n, const double *x, const int32_t *labels, const double *prm, int bf16,
+                         double *grad);
+void orc_tag_learned(const orc_mesh *m, const float *logits /* [n][3] */, const int8_t *plain, float conf,
+                     int max_level, int8_t *tags);
+void orc_adam_step(int64_t n, double *p, double *mom, double *vel, const double *g, int t, double lr, double b1,
+                   double b2, double eps);
 
 #ifdef __cplusplus
 }

@@ -19,6 +19,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 KERNEL_PHASED, KERNEL_LDS = 0, 1
 FILL_SAME_LEVEL, FILL_NEUMANN, FILL_LEVELS, FILL_ALL = 1, 2, 4, 7
 STAGE_FILL_SAME_LEVEL = 1
+MLP_NIN, MLP_NH, MLP_NOUT, MLP_NPARAM = 81, 64, 3, 9603
 SCEN_GAUGE_WAVE, SCEN_PUNCTURE, SCEN_BL_BY = 0, 1, 2
 
 
@@ -83,6 +84,13 @@ def lib():
             "ccz4_tag_refine": (i32, [P, P, f64, f64, i32, P, P, P]),
             "ccz4_set_kernel": (i32, [P, i32, i32]),
             "ccz4_get_kernel": (i32, [P, i32, ctypes.POINTER(i32)]),
+            "ccz4_features": (i32, [P, P, P, P, P]),
+            "ccz4_mlp_forward": (i32, [P, P, P, i64, P, P]),
+            "ccz4_mlp_workspace": (i32, [i64, ctypes.POINTER(i64)]),
+            "ccz4_mlp_grad": (i32, [P, P, P, P, i64, P, i64, P, P, P]),
+            "ccz4_mlp_adam": (i32, [P, P, P, P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, P]),
+            "ccz4_tag_learned": (i32, [P, P, P, ctypes.c_float, i32, P, P]),
             "ccz4_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -210,6 +218,36 @@ def ccz4_get_kernel(h, precision):
     return out.value
 
 
+def ccz4_features(h, Q, HM, feat, stream=None):
+    return _check(lib().ccz4_features(h, _ptr(Q), _ptr(HM), _ptr(feat), _stream(stream)))
+
+
+def ccz4_mlp_forward(params, norm, feat, n, logits, stream=None):
+    return _check(lib().ccz4_mlp_forward(_ptr(params), _ptr(norm), _ptr(feat), int(n), _ptr(logits),
+                                         _stream(stream)))
+
+
+def ccz4_mlp_workspace(n):
+    out = ctypes.c_int64(0)
+    _check(lib().ccz4_mlp_workspace(int(n), ctypes.byref(out)))
+    return out.value
+
+
+def ccz4_mlp_grad(params, norm, feat, tags, n, work, grad, loss=None, stream=None):
+    return _check(lib().ccz4_mlp_grad(_ptr(params), _ptr(norm), _ptr(feat), _ptr(tags), int(n), _ptr(work),
+                                      int(work.numel()), _ptr(grad), _ptr(loss), _stream(stream)))
+
+
+def ccz4_mlp_adam(params, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    return _check(lib().ccz4_mlp_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(step), float(lr),
+                                      float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def ccz4_tag_learned(h, logits, plain_tags, conf, max_level, tags, stream=None):
+    return _check(lib().ccz4_tag_learned(h, _ptr(logits), _ptr(plain_tags), float(conf), int(max_level),
+                                         _ptr(tags), _stream(stream)))
+
+
 def ccz4_constraints(h, Q, HM=None, r_excise=0.0, want_norms=True, stream=None):
     norms = (ctypes.c_double * 3)()
     st = lib().ccz4_constraints(h, _ptr(Q), _ptr(HM), float(r_excise),
@@ -289,6 +327,20 @@ class Context:
     def plan_counts(self):
         return ccz4_plan_counts(self.h)
 
+    def features(self, Q, HM, feat=None, stream=None):
+        import torch
+        if feat is None:
+            feat = torch.empty((self.n_patches, MLP_NIN), dtype=torch.float32, device="cuda")
+        ccz4_features(self.h, Q, HM, feat, stream)
+        return feat
+
+    def tag_learned(self, logits, plain_tags, conf, max_level, tags=None, stream=None):
+        import torch
+        if tags is None:
+            tags = torch.empty(self.n_patches, dtype=torch.int8, device="cuda")
+        ccz4_tag_learned(self.h, logits, plain_tags, conf, max_level, tags, stream)
+        return tags
+
     def set_kernel(self, precision, kernel):
         ccz4_set_kernel(self.h, precision, kernel)
 
@@ -324,3 +376,4 @@ class Context:
             nxt = Qn if s == 3 else Qs
             self.rk4_stage(s, dt, Qn, k, acc, nxt, stream)
             cur = nxt
+

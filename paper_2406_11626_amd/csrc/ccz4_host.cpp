@@ -15,6 +15,7 @@
 
 #include "../../include/ccz4.h"
 #include "ccz4_kernels.hpp"
+#include "ccz4_mlp.hpp"
 
 using namespace ccz4;
 
@@ -92,6 +93,7 @@ struct ccz4_ctx {
     DevBuf<uint8_t> d_bmask;
     DevBuf<int32_t> d_sib;
     DevBuf<double> d_bg, d_part, d_out3, d_hm;
+    DevBuf<int8_t> d_pre;                     // learned tags, first pass
     double *h_out3 = nullptr;  // pinned
     bool bg_valid = false;
     int32_t kernel[2] = {KV_LDS, KV_LDS};  // per precision
@@ -334,6 +336,7 @@ ccz4_status ccz4_create(ccz4_ctx **out, const ccz4_grid_desc *g, const ccz4_para
     if (e == hipSuccess) e = c->d_phr.upload(c->ph_res);
     if (e == hipSuccess) e = c->d_php.upload(c->ph_pro);
     if (e == hipSuccess) e = c->d_nbr.upload(c->nbr);
+    if (e == hipSuccess) e = c->d_pre.alloc(c->leaf.size());
     if (e == hipSuccess) e = c->d_bf.upload(c->bface);
     if (e == hipSuccess) e = c->d_bmask.upload(c->bmask);
     if (e == hipSuccess) e = c->d_sib.upload(c->sib);
@@ -360,6 +363,7 @@ void ccz4_destroy(ccz4_ctx *c)
     c->d_phr.release();
     c->d_php.release();
     c->d_nbr.release();
+    c->d_pre.release();
     c->d_bf.release();
     c->d_bmask.release();
     c->d_sib.release();
@@ -536,6 +540,65 @@ ccz4_status ccz4_get_kernel(const ccz4_ctx *c, int32_t precision, int32_t *kerne
     if (!c || !kernel) return fail(CCZ4_EINVAL, "ctx or kernel is NULL");
     if (precision != CCZ4_PREC_FP64 && precision != CCZ4_PREC_MIXED) return fail(CCZ4_EINVAL, "bad precision");
     *kernel = c->kernel[precision] == KV_LDS ? CCZ4_KERNEL_LDS : CCZ4_KERNEL_PHASED;
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_features(ccz4_ctx *c, const double *Q, const double *HM, float *feat, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    ccz4_status st = check_ptr(Q, "Q");
+    if (!st) st = check_ptr(HM, "HM");
+    if (!st) st = check_ptr(feat, "feat");
+    if (st) return st;
+    HIP_TRY(launch_features(Q, HM, c->d_geom.p, (int32_t)c->leaf.size(), feat, S(stream)));
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_mlp_forward(const float *params, const float *norm, const float *feat, int64_t n, float *logits,
+                             void *stream)
+{
+    if (!params || !norm || !logits || (n > 0 && !feat)) return fail(CCZ4_EINVAL, "NULL buffer");
+    if (n < 0) return fail(CCZ4_EINVAL, "n < 0");
+    HIP_TRY(launch_mlp_forward(params, norm, feat, n, logits, S(stream)));
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_mlp_workspace(int64_t n, int64_t *floats)
+{
+    if (!floats || n < 0) return fail(CCZ4_EINVAL, "bad arguments");
+    *floats = (int64_t)(n > 0 ? mlp_tiles(n) : 0) * (MLP_NPARAM + 1);
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_mlp_grad(const float *params, const float *norm, const float *feat, const int8_t *tags, int64_t n,
+                          float *work, int64_t work_floats, float *grad, float *loss, void *stream)
+{
+    if (!params || !norm || !feat || !tags || !work || !grad) return fail(CCZ4_EINVAL, "NULL buffer");
+    if (n <= 0) return fail(CCZ4_EINVAL, "n must be > 0");
+    if (work_floats < (int64_t)mlp_tiles(n) * (MLP_NPARAM + 1)) return fail(CCZ4_EINVAL, "workspace too small");
+    HIP_TRY(launch_mlp_grad(params, norm, feat, tags, n, work, grad, loss, S(stream)));
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr, float beta1,
+                          float beta2, float eps, void *stream)
+{
+    if (!params || !m || !v || !grad) return fail(CCZ4_EINVAL, "NULL buffer");
+    if (step < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return fail(CCZ4_EINVAL, "bad Adam hyper-parameters");
+    const double c1 = 1.0 - std::pow((double)beta1, step), c2 = 1.0 - std::pow((double)beta2, step);
+    HIP_TRY(launch_mlp_adam(params, m, v, grad, lr, beta1, beta2, eps, (float)c1, (float)c2, S(stream)));
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_tag_learned(ccz4_ctx *c, const float *logits, const int8_t *plain_tags, float conf, int32_t max_level,
+                             int8_t *tags, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    if (!logits || !plain_tags || !tags) return fail(CCZ4_EINVAL, "NULL buffer");
+    if (!(conf >= 0 && conf <= 1)) return fail(CCZ4_EINVAL, "conf must lie in [0, 1]");
+    HIP_TRY(launch_tag_learned(logits, plain_tags, c->d_geom.p, c->d_sib.p, (int32_t)c->leaf.size(), conf, max_level,
+                               c->d_pre.p, tags, S(stream)));
     return CCZ4_OK;
 }
 

@@ -1,0 +1,24 @@
+// Launchers of the learned-indicator kernels (implemented in ccz4_mlp.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ccz4_layout.hpp"
+
+namespace ccz4 {
+
+constexpr int MLP_NIN = 81, MLP_NH = 64, MLP_NOUT = 3, MLP_NPARAM = 9603;
+
+int32_t mlp_tiles(int64_t n);
+hipError_t launch_features(const double *Q, const double *HM, const PatchGeom *geom, int32_t npatch, float *feat,
+                           hipStream_t st);
+hipError_t launch_mlp_forward(const float *prm, const float *norm, const float *feat, int64_t n, float *logits,
+                              hipStream_t st);
+hipError_t launch_mlp_grad(const float *prm, const float *norm, const float *feat, const int8_t *tags, int64_t n,
+                           float *work, float *grad, float *loss, hipStream_t st);
+hipError_t launch_mlp_adam(float *prm, float *m, float *v, const float *grad, float lr, float b1, float b2, float eps,
+                           float c1, float c2, hipStream_t st);
+hipError_t launch_tag_learned(const float *logits, const int8_t *plain, const PatchGeom *geom, const int32_t *sib,
+                              int32_t npatch, float conf, int32_t max_level, int8_t *pre, int8_t *tags,
+                              hipStream_t st);
+
+}  // namespace ccz4

@@ -6,6 +6,8 @@ kappa3 = 0.5, e = c = tau = 1, mu = 0.2, f = 0.75) with KO strength 0.1, the Gam
 eta = 2 of these workloads, and dt = CFL * (smallest dx) with CFL = 0.1.
 """
 import math
+
+import numpy as np
 from dataclasses import dataclass, field
 
 from . import ccz4
@@ -44,8 +46,9 @@ BLACK_HOLE = dict(kappa1=0.1, kappa2=0.0, kappa3=0.5, tau=1.0, e=1.0, c=1.0, mu=
 
 def sphere_refinement(n0, origin, extent, center, radii):
     """Static refinement by concentric spheres: every cube of level l whose nearest point to
-    `center` lies within radii[l] is refined (levels 0..len(radii)-1), keeping only cubes whose
-    parents are refined."""
+    `center` (one point, or a list of points: the nearest of them) lies within radii[l] is
+    refined (levels 0..len(radii)-1), keeping only cubes whose parents are refined."""
+    centers = [center] if np.ndim(center) == 1 else list(center)
     refined = []
     current = [(0, i, j, k) for k in range(n0[2]) for j in range(n0[1]) for i in range(n0[0])]
     for lev, R in enumerate(radii):
@@ -54,11 +57,14 @@ def sphere_refinement(n0, origin, extent, center, radii):
         nxt = []
         for (l, i, j, k) in current:
             lo = [origin[a] + L[a] * idx for a, idx in enumerate((i, j, k))]
-            d2 = 0.0
-            for a in range(3):
-                c = min(max(center[a], lo[a]), lo[a] + L[a])
-                d2 += (c - center[a]) ** 2
-            if math.sqrt(d2) <= R:
+            dmin = math.inf
+            for cen in centers:
+                d2 = 0.0
+                for a in range(3):
+                    c = min(max(cen[a], lo[a]), lo[a] + L[a])
+                    d2 += (c - cen[a]) ** 2
+                dmin = min(dmin, math.sqrt(d2))
+            if dmin <= R:
                 refined.append((lev, i, j, k))
                 nxt += [(lev + 1, 3 * i + u, 3 * j + v, 3 * k + w)
                         for w in range(3) for v in range(3) for u in range(3)]

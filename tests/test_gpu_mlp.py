@@ -1,0 +1,139 @@
+"""GPU parity of the learned refinement indicator against the oracle: features, forward pass,
+loss gradient, Adam step and the combination with the plain criterion.
+
+Tolerances.  Features are FP64 stencil maxima written as FP32 log10 values: within a few FP32
+ulps.  The perceptron uses the same BF16 operands on both sides (the standardised inputs are
+formed in FP32 identically); what differs is the accumulation (FP32 on the matrix cores, FP64
+in the oracle), which occasionally flips the BF16 rounding of a hidden activation or of a
+back-propagated gradient by one BF16 ulp (2^-8 relative); the normwise bounds below allow for
+a few such flips per tensor.  Adam is FP32 against FP64 with the same FP32 hyper-parameters: a
+few FP32 roundings of the terms of each update.  The tags are integers: bit-exact."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle as orc  # noqa: E402
+from gpu_helpers import to_gpu  # noqa: E402
+from paper_2406_11626_amd import ccz4, scenarios  # noqa: E402
+from paper_2406_11626_amd.learned import LearnedIndicator  # noqa: E402
+from seeded_inputs import box_centers, smooth_state  # noqa: E402
+
+NP = ccz4.MLP_NPARAM
+BLOCKS = {"W1": (0, 5184), "b1": (5184, 5248), "W2": (5248, 9344), "b2": (9344, 9408), "W3": (9408, 9600),
+          "b3": (9600, 9603)}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ccz4.lib()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def mlp_inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    prm = (rng.normal(size=NP) * 0.2).astype(np.float32)
+    feat = (rng.normal(size=(n, 81)) * 2.0 - 3.0).astype(np.float32)
+    norm = np.concatenate([rng.normal(size=81) - 3.0, 0.3 + rng.random(81)]).astype(np.float32)
+    tags = rng.integers(-1, 2, n).astype(np.int8)
+    return prm, feat, norm, tags
+
+
+def dev(a):
+    return torch.tensor(a, device="cuda")
+
+
+def test_features_parity():
+    w = scenarios.config(2)
+    refined = [(0, 1, 1, 1)]
+    ctx = ccz4.Context((3, 3, 3), (-9.0,) * 3, (18.0,) * 3, w.bc, w.params(), refined)
+    m = orc.Mesh((3, 3, 3), (-9.0,) * 3, (18.0,) * 3, w.bc, refined)
+    Qo = m.zeros()
+    m.init(Qo, w.scenario, w.scen)
+    for p in range(m.np):  # a seeded smooth perturbation so that every feature is non-trivial
+        Qo[p] += 1e-3 * smooth_state(box_centers(m.geom[p, :3], m.geom[p, 3:]), 70 + p % 5)
+    m.fill_halos(Qo)
+    fo = m.features(Qo)
+    Qd = to_gpu(Qo)
+    HM = torch.empty((ctx.n_patches, 4, 729), dtype=torch.float64, device="cuda")
+    ctx.constraints(Qd, HM)
+    fd = ctx.features(Qd, HM).cpu().numpy()
+    assert np.isfinite(fd).all()
+    err = np.abs(fd - fo)
+    assert err.max() <= 4 * np.finfo(np.float32).eps * max(1.0, np.abs(fo).max()), err.max()
+
+
+@pytest.mark.parametrize("n", [1, 200])
+def test_forward_parity(n):
+    prm, feat, norm, _ = mlp_inputs(n, 10 + n)
+    logits = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    ccz4.ccz4_mlp_forward(dev(prm), dev(norm), dev(feat), n, logits)
+    x = orc.mlp_standardize(feat, norm)
+    zo = orc.mlp_forward(x, prm.astype(np.float64), bf16=True)[2]
+    assert rel(logits.cpu().numpy(), zo) <= 2e-3, rel(logits.cpu().numpy(), zo)
+
+
+@pytest.mark.parametrize("n", [64, 331])
+def test_gradient_parity(n):
+    prm, feat, norm, tags = mlp_inputs(n, 20 + n)
+    ind = LearnedIndicator()
+    ind.params = dev(prm)
+    ind.norm = dev(norm)
+    g = ind.gradient(dev(feat), dev(tags)).cpu().numpy()
+    loss = float(ind.loss.item())
+    x = orc.mlp_standardize(feat, norm)
+    lo, go = orc.mlp_loss_grad(x, tags.astype(np.int32) + 1, prm.astype(np.float64), bf16=True)
+    assert abs(loss - lo) <= 1e-4 * abs(lo), (loss, lo)
+    for name, (a, b) in BLOCKS.items():
+        assert rel(g[a:b], go[a:b]) <= 1e-2, (name, rel(g[a:b], go[a:b]))
+    # the workspace query and its check
+    with pytest.raises(ccz4.CCZ4Error):
+        ccz4.ccz4_mlp_grad(ind.params, ind.norm, dev(feat), dev(tags), n, ind._work[:10], ind.grad)
+
+
+def test_adam_parity():
+    rng = np.random.default_rng(30)
+    p = rng.normal(size=NP).astype(np.float32)
+    m = (rng.normal(size=NP) * 0.1).astype(np.float32)
+    v = (rng.random(NP) * 0.01).astype(np.float32)
+    g = rng.normal(size=NP).astype(np.float32)
+    pd, md, vd = dev(p), dev(m), dev(v)
+    ccz4.ccz4_mlp_adam(pd, md, vd, dev(g), 3, 1e-3)
+    po, mo, vo = p.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    # the kernel holds lr, beta1, beta2 and eps in FP32: the oracle takes the same values
+    f32 = lambda a: float(np.float32(a))  # noqa: E731
+    orc.adam_step(po, mo, vo, g.astype(np.float64), 3, f32(1e-3), f32(0.9), f32(0.999), f32(1e-8))
+    # FP32 against FP64: a few roundings relative to the size of the terms of each update
+    eps32 = np.finfo(np.float32).eps
+    bm = 4 * eps32 * (0.9 * np.abs(m) + 0.1 * np.abs(g))
+    bv = 4 * eps32 * (0.999 * v + 0.001 * g.astype(np.float64) ** 2)
+    assert np.all(np.abs(md.cpu().numpy() - mo) <= bm)
+    assert np.all(np.abs(vd.cpu().numpy() - vo) <= bv)
+    step = np.abs(po - p)  # the change of the parameters is accurate to FP32 relative rounding
+    assert np.all(np.abs(pd.cpu().numpy() - po) <= 1e-5 * step + 2 * eps32 * np.abs(p))
+    with pytest.raises(ccz4.CCZ4Error):
+        ccz4.ccz4_mlp_adam(pd, md, vd, dev(g), 0, 1e-3)
+
+
+def test_tag_learned_parity():
+    w = scenarios.config(2)
+    refined = [(0, 1, 1, 1), (1, 4, 4, 4)]
+    ctx = ccz4.Context((3, 3, 3), (-9.0,) * 3, (18.0,) * 3, w.bc, w.params(), refined)
+    m = orc.Mesh((3, 3, 3), (-9.0,) * 3, (18.0,) * 3, w.bc, refined)
+    rng = np.random.default_rng(40)
+    for trial in range(4):
+        logits = (rng.normal(size=(m.np, 3)) * (1 + 3 * trial)).astype(np.float32)
+        plain = rng.integers(-1, 2, m.np).astype(np.int8)
+        if trial == 3:  # whole families asked to coarsen, so that the family rule is exercised
+            plain[m.ids[:, 0] == 2] = -1
+        for conf in (0.0, 0.6, 0.95):
+            for max_level in (1, 3):
+                got = ctx.tag_learned(dev(logits), dev(plain), conf, max_level).cpu().numpy()
+                assert np.array_equal(got, m.tag_learned(logits, plain, conf, max_level)), (trial, conf, max_level)
