@@ -92,6 +92,8 @@ def run_gpu(args, w, precision):
     rest = ccz4.FILL_NEUMANN | ccz4.FILL_LEVELS
     events = []
     ctx.fill_halos(Q, stream)
+    tune_ms = ctx.autotune(Q, precision, reps=2) if args.autotune else None
+    ctx.fill_halos(Q, stream)
 
     def step(timed):
         for s, (src, dst) in enumerate(order):
@@ -116,17 +118,34 @@ def run_gpu(args, w, precision):
         if args.progress:
             print(f"# step {i + 1}/{args.steps}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    wall_eager = time.perf_counter() - t0
+    # the same step captured once as a HIP graph and replayed (the production path)
+    graph = ctx.step_graph(Q, (Q1, Q2, acc), dt, precision)
+    for _ in range(args.warmup):
+        graph.launch(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        graph.launch(stream)
+        if args.progress:
+            print(f"# graph step {i + 1}/{args.steps}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    graph.close()
     cells = ctx.n_patches * 729
     nsame = ctx.plan_counts()["same_level"]
     stage_ms = [a.elapsed_time(b) for _, a, b in events]
     launch_bytes = [stage_bytes(s, cells, nsame) for s, _, _ in events]
     norms, st = ctx.constraints(Q, r_excise=1.0)
-    kname = {ccz4.KERNEL_LDS: "k_stage_lds", ccz4.KERNEL_PHASED: "k_stage"}[ctx.get_kernel(precision)]
-    out = dict(wall=wall, cells=cells, patches=ctx.n_patches, stage_ms=sum(stage_ms) / len(stage_ms),
+    kc = ctx.get_kernel(precision)
+    kname = ("k_stage_lds" if kc & ccz4.KERNEL_LDS else "k_stage") + \
+        ("<double>" if precision == ccz4.PREC_FP64 else "<float>") + \
+        (" (plain block order)" if kc & ccz4.KERNEL_LINEAR_ORDER else "")
+    out = dict(wall=wall, wall_eager=wall_eager, tune_ms=tune_ms, cells=cells, patches=ctx.n_patches,
+               stage_ms=sum(stage_ms) / len(stage_ms),
                stage_bytes=sum(launch_bytes) / len(launch_bytes),
                stage_gbs=sum(launch_bytes) / (sum(stage_ms) * 1e-3) / 1e9, norms=norms, status=st,
-               kernel=kname + ("<double>" if precision == ccz4.PREC_FP64 else "<float>"))
+               kernel=kname)
     del Q, Q1, Q2, acc
     ctx.close()
     torch.cuda.empty_cache()
@@ -181,6 +200,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference kernel for the HBM byte counters)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the default launch configuration instead of timing the candidates first")
     ap.add_argument("--progress", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -215,7 +236,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic (analytic puncture initial data)",
         "config": {"workload": w.name, "patches": r64["patches"], "cells": r64["cells"],
-                   "stages_per_step": 4, "dt": w.dt(), "precision": "fp64"},
+                   "stages_per_step": 4, "dt": w.dt(), "precision": "fp64",
+                   "step": "HIP graph of 4 fused stages with same-level halo push",
+                   "launch_config": r64["kernel"], "autotune_ms": r64["tune_ms"]},
+        "eager_ms_per_step": r64["wall_eager"] * 1e3 / args.steps,
         "roofline": {"bound": "hbm", "achieved": r64["stage_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r64["stage_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": r64["kernel"], "avg_ms": r64["stage_ms"],

@@ -164,16 +164,39 @@ enum { CCZ4_STAGE_FILL_SAME_LEVEL = 1 };
 ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double *Qs, const double *Qn,
                                double *acc, double *Qnext, int32_t precision, int32_t flags, void *stream);
 
-/* Kernel choice for ccz4_rhs and ccz4_rhs_rk4_stage, per precision (CCZ4_PREC_FP64 or
-   CCZ4_PREC_MIXED).  Both kernels evaluate the same right-hand side (App. B algebra, App. D FD4
-   and KO stencils) and agree up to floating-point rounding order; they differ only in how the
-   stencil footprints reach the registers.  CCZ4_KERNEL_PHASED reads every stencil point from the
-   state in six phases; CCZ4_KERNEL_LDS copies each slot's slab footprint once into LDS per
-   evaluation, in four rounds.  Default after ccz4_create: CCZ4_KERNEL_LDS for both precisions.
-   EINVAL on an unknown precision or kernel, or a NULL out pointer. */
-typedef enum { CCZ4_KERNEL_PHASED = 0, CCZ4_KERNEL_LDS = 1 } ccz4_kernel;
+/* Launch configuration of ccz4_rhs and ccz4_rhs_rk4_stage, per precision (CCZ4_PREC_FP64 or
+   CCZ4_PREC_MIXED): CCZ4_KERNEL_PHASED or CCZ4_KERNEL_LDS, optionally with
+   CCZ4_KERNEL_LINEAR_ORDER added.  Both kernels evaluate the same right-hand side (App. B algebra,
+   App. D FD4 and KO stencils) and agree up to floating-point rounding order; they differ only in
+   how the stencil footprints reach the registers.  CCZ4_KERNEL_PHASED reads every stencil point
+   from the state in six phases; CCZ4_KERNEL_LDS copies each slot's slab footprint once into LDS
+   per evaluation, in four rounds.  The work-groups of a patch run on one XCD unless
+   CCZ4_KERNEL_LINEAR_ORDER is given (plain block order).  Default after ccz4_create:
+   CCZ4_KERNEL_LDS for both precisions.  EINVAL on an unknown precision or value, or a NULL out
+   pointer. */
+typedef enum { CCZ4_KERNEL_PHASED = 0, CCZ4_KERNEL_LDS = 1, CCZ4_KERNEL_LINEAR_ORDER = 2 } ccz4_kernel;
 ccz4_status ccz4_set_kernel(ccz4_ctx *ctx, int32_t precision, int32_t kernel);
 ccz4_status ccz4_get_kernel(const ccz4_ctx *ctx, int32_t precision, int32_t *kernel);
+
+/* Autotuner: times one fused stage (s = 1, with CCZ4_STAGE_FILL_SAME_LEVEL) of every launch
+   configuration (0..3 above) on this context's mesh, `reps` launches each after one warm-up,
+   with events on `stream`, and selects the fastest for `precision`.  Q: a state with filled
+   halos (read only); acc and Qx: state-sized scratch (overwritten).  ms (host, may be NULL)
+   receives the four average launch times in milliseconds.  Synchronises `stream`. */
+ccz4_status ccz4_autotune(ccz4_ctx *ctx, const double *Q, double *acc, double *Qx, int32_t precision,
+                          int32_t reps, double *ms, void *stream);
+
+/* A fused RK4 step captured as a HIP graph: the four stages of ccz4_rhs_rk4_stage with
+   CCZ4_STAGE_FILL_SAME_LEVEL, (Qn -> Q1), (Q1 -> Q2), (Q2 -> Q1), (Q1 -> Qn), each followed by
+   ccz4_fill_halos_kinds(NEUMANN | LEVELS) of its output, with the launch configuration current at
+   creation.  Buffers and dt are fixed at creation; Qn must enter each launch with all halos filled
+   and leaves with them filled.  The graph uses the context's tables: destroy it before the
+   context.  Launch is asynchronous on `stream`. */
+typedef struct ccz4_graph ccz4_graph;
+ccz4_status ccz4_step_graph_create(ccz4_ctx *ctx, double *Qn, double *Q1, double *Q2, double *acc, double dt,
+                                   int32_t precision, ccz4_graph **out);
+ccz4_status ccz4_step_graph_launch(ccz4_graph *graph, void *stream);
+void ccz4_step_graph_destroy(ccz4_graph *graph);
 
 /* Constraint monitor.  Hamiltonian H = R + 2/3 K^2 - At_ij At^ij and momentum M_i (App. B) on every interior
    cell (FD4 derivatives; requires filled halos).  HM (device, may be NULL) receives

@@ -16,7 +16,7 @@ NV = 59
 CCZ4_OK, CCZ4_EINVAL, CCZ4_ENOMEM, CCZ4_ELAYOUT, CCZ4_EHIP, CCZ4_ENONFINITE, CCZ4_ESTATE = range(7)
 BC_PERIODIC, BC_NEUMANN, BC_SOMMERFELD = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
-KERNEL_PHASED, KERNEL_LDS = 0, 1
+KERNEL_PHASED, KERNEL_LDS, KERNEL_LINEAR_ORDER = 0, 1, 2
 FILL_SAME_LEVEL, FILL_NEUMANN, FILL_LEVELS, FILL_ALL = 1, 2, 4, 7
 STAGE_FILL_SAME_LEVEL = 1
 MLP_NIN, MLP_NH, MLP_NOUT, MLP_NPARAM = 81, 64, 3, 9603
@@ -84,6 +84,10 @@ def lib():
             "ccz4_tag_refine": (i32, [P, P, f64, f64, i32, P, P, P]),
             "ccz4_set_kernel": (i32, [P, i32, i32]),
             "ccz4_get_kernel": (i32, [P, i32, ctypes.POINTER(i32)]),
+            "ccz4_autotune": (i32, [P, P, P, P, i32, i32, ctypes.POINTER(f64), P]),
+            "ccz4_step_graph_create": (i32, [P, P, P, P, P, f64, i32, ctypes.POINTER(P)]),
+            "ccz4_step_graph_launch": (i32, [P, P]),
+            "ccz4_step_graph_destroy": (None, [P]),
             "ccz4_features": (i32, [P, P, P, P, P]),
             "ccz4_mlp_forward": (i32, [P, P, P, i64, P, P]),
             "ccz4_mlp_workspace": (i32, [i64, ctypes.POINTER(i64)]),
@@ -218,6 +222,27 @@ def ccz4_get_kernel(h, precision):
     return out.value
 
 
+def ccz4_autotune(h, Q, acc, Qx, precision=PREC_FP64, reps=3, stream=None):
+    ms = (ctypes.c_double * 4)()
+    _check(lib().ccz4_autotune(h, _ptr(Q), _ptr(acc), _ptr(Qx), int(precision), int(reps), ms, _stream(stream)))
+    return list(ms)
+
+
+def ccz4_step_graph_create(h, Qn, Q1, Q2, acc, dt, precision=PREC_FP64):
+    g = ctypes.c_void_p()
+    _check(lib().ccz4_step_graph_create(h, _ptr(Qn), _ptr(Q1), _ptr(Q2), _ptr(acc), float(dt), int(precision),
+                                        ctypes.byref(g)))
+    return g
+
+
+def ccz4_step_graph_launch(g, stream=None):
+    return _check(lib().ccz4_step_graph_launch(g, _stream(stream)))
+
+
+def ccz4_step_graph_destroy(g):
+    lib().ccz4_step_graph_destroy(g)
+
+
 def ccz4_features(h, Q, HM, feat, stream=None):
     return _check(lib().ccz4_features(h, _ptr(Q), _ptr(HM), _ptr(feat), _stream(stream)))
 
@@ -273,6 +298,7 @@ class Context:
 
     def __init__(self, n0, origin, extent, bc=BC_PERIODIC, prm=None, refined=()):
         self.prm = prm if prm is not None else params()
+        self.bc = bc
         self.h = ccz4_create(n0, origin, extent, bc, self.prm, refined)
         self.n_patches, self.patch_doubles, self.bytes_per_state = ccz4_layout(self.h)
         self.ids, self.geom = ccz4_patch_table(self.h)
@@ -327,6 +353,18 @@ class Context:
     def plan_counts(self):
         return ccz4_plan_counts(self.h)
 
+    def autotune(self, Q, precision=PREC_FP64, reps=3, stream=None):
+        """Time the four launch configurations on this mesh and keep the fastest; returns the
+        average stage times in ms (index = configuration)."""
+        acc, Qx = self.new_state(0.0), self.new_state(0.0)
+        ms = ccz4_autotune(self.h, Q, acc, Qx, precision, reps, stream)
+        del acc, Qx
+        return ms
+
+    def step_graph(self, Qn, bufs, dt, precision=PREC_FP64):
+        """A captured fused RK4 step on (Qn, Q1, Q2, acc) = (Qn,) + bufs; see StepGraph."""
+        return StepGraph(self, Qn, bufs, dt, precision)
+
     def features(self, Q, HM, feat=None, stream=None):
         import torch
         if feat is None:
@@ -377,3 +415,26 @@ class Context:
             self.rk4_stage(s, dt, Qn, k, acc, nxt, stream)
             cur = nxt
 
+
+
+class StepGraph:
+    """ccz4_step_graph_*: one fused RK4 step (push fill) captured once and replayed."""
+
+    def __init__(self, ctx, Qn, bufs, dt, precision=PREC_FP64):
+        Q1, Q2, acc = bufs
+        self._keep = (ctx, Qn, Q1, Q2, acc)  # the graph holds raw pointers to these
+        self.g = ccz4_step_graph_create(ctx.h, Qn, Q1, Q2, acc, dt, precision)
+
+    def launch(self, stream=None):
+        ccz4_step_graph_launch(self.g, stream)
+
+    def close(self):
+        if self.g is not None and _lib is not None:
+            ccz4_step_graph_destroy(self.g)
+        self.g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

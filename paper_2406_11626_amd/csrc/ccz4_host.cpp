@@ -530,8 +530,8 @@ ccz4_status ccz4_set_kernel(ccz4_ctx *c, int32_t precision, int32_t kernel)
 {
     if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
     if (precision != CCZ4_PREC_FP64 && precision != CCZ4_PREC_MIXED) return fail(CCZ4_EINVAL, "bad precision");
-    if (kernel != CCZ4_KERNEL_PHASED && kernel != CCZ4_KERNEL_LDS) return fail(CCZ4_EINVAL, "unknown kernel");
-    c->kernel[precision] = kernel == CCZ4_KERNEL_LDS ? KV_LDS : KV_PHASED;
+    if (kernel < 0 || kernel >= KV_COUNT) return fail(CCZ4_EINVAL, "unknown kernel");
+    c->kernel[precision] = kernel;  // the ABI codes are the launch configurations
     return CCZ4_OK;
 }
 
@@ -539,8 +539,126 @@ ccz4_status ccz4_get_kernel(const ccz4_ctx *c, int32_t precision, int32_t *kerne
 {
     if (!c || !kernel) return fail(CCZ4_EINVAL, "ctx or kernel is NULL");
     if (precision != CCZ4_PREC_FP64 && precision != CCZ4_PREC_MIXED) return fail(CCZ4_EINVAL, "bad precision");
-    *kernel = c->kernel[precision] == KV_LDS ? CCZ4_KERNEL_LDS : CCZ4_KERNEL_PHASED;
+    *kernel = c->kernel[precision];
     return CCZ4_OK;
+}
+
+ccz4_status ccz4_autotune(ccz4_ctx *c, const double *Q, double *acc, double *Qx, int32_t precision, int32_t reps,
+                          double *ms, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    ccz4_status st = check_ptr(Q, "Q");
+    if (!st) st = check_ptr(acc, "acc");
+    if (!st) st = check_ptr(Qx, "Qx");
+    if (st) return st;
+    if (precision != CCZ4_PREC_FP64 && precision != CCZ4_PREC_MIXED) return fail(CCZ4_EINVAL, "bad precision");
+    if (reps < 1) return fail(CCZ4_EINVAL, "reps must be >= 1");
+    if (Q == acc || Q == Qx || acc == Qx) return fail(CCZ4_EINVAL, "Q, acc and Qx must be distinct");
+    if (!c->bface.empty() && !c->bg_valid)
+        return fail(CCZ4_ESTATE, "Sommerfeld background not set (call ccz4_init_patches or ccz4_set_background)");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(CCZ4_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
+    }
+    double best = 0.0;
+    int32_t pick = c->kernel[precision];
+    const double dt = 1e-3;
+    for (int32_t v = 0; v < KV_COUNT && he == hipSuccess; ++v) {
+        auto stage = [&]() {
+            return launch_stage(1, dt, Q, Q, acc, Qx, c->d_geom.p, (int32_t)c->leaf.size(), c->prm, precision, v,
+                                c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(), c->d_nbr.p, S(stream));
+        };
+        he = stage();  // warm-up
+        if (he == hipSuccess) he = hipEventRecord(e0, S(stream));
+        for (int r = 0; r < reps && he == hipSuccess; ++r) he = stage();
+        if (he == hipSuccess) he = hipEventRecord(e1, S(stream));
+        if (he == hipSuccess) he = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&t, e0, e1);
+        const double per = (double)t / reps;
+        if (ms) ms[v] = per;
+        if (he == hipSuccess && (v == 0 || per < best)) {
+            best = per;
+            pick = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (he != hipSuccess) return fail(CCZ4_EHIP, std::string("autotune: ") + hipGetErrorString(he));
+    c->kernel[precision] = pick;
+    return CCZ4_OK;
+}
+
+// A captured fused RK4 step: four stages with same-level halo push and the Neumann / coarse-fine
+// fill between them, replayed as one graph launch.
+struct ccz4_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+ccz4_status ccz4_step_graph_create(ccz4_ctx *c, double *Qn, double *Q1, double *Q2, double *acc, double dt,
+                                   int32_t precision, ccz4_graph **out)
+{
+    if (!c || !out) return fail(CCZ4_EINVAL, "ctx or out is NULL");
+    *out = nullptr;
+    ccz4_status st = check_ptr(Qn, "Qn");
+    if (!st) st = check_ptr(Q1, "Q1");
+    if (!st) st = check_ptr(Q2, "Q2");
+    if (!st) st = check_ptr(acc, "acc");
+    if (st) return st;
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(CCZ4_EINVAL, "dt must be finite and > 0");
+    if (precision != CCZ4_PREC_FP64 && precision != CCZ4_PREC_MIXED) return fail(CCZ4_EINVAL, "bad precision");
+    const double *bufs[4] = {Qn, Q1, Q2, acc};
+    for (int i = 0; i < 4; ++i)
+        for (int j = i + 1; j < 4; ++j)
+            if (bufs[i] == bufs[j]) return fail(CCZ4_EINVAL, "Qn, Q1, Q2 and acc must be distinct");
+    if (!c->bface.empty() && !c->bg_valid)
+        return fail(CCZ4_ESTATE, "Sommerfeld background not set (call ccz4_init_patches or ccz4_set_background)");
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    ccz4_graph *g = new (std::nothrow) ccz4_graph;
+    if (!g) {
+        (void)hipStreamDestroy(cs);
+        return fail(CCZ4_ENOMEM, "graph");
+    }
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    const int32_t np = (int32_t)c->leaf.size(), nbf = (int32_t)c->bface.size();
+    double *src[4] = {Qn, Q1, Q2, Q1}, *dst[4] = {Q1, Q2, Q1, Qn};
+    for (int s = 0; s < 4 && e == hipSuccess; ++s) {
+        e = launch_stage(s, dt, src[s], Qn, acc, dst[s], c->d_geom.p, np, c->prm, precision, c->kernel[precision],
+                         c->d_bf.p, c->d_bg.p, nbf, c->d_nbr.p, cs);
+        if (e == hipSuccess) e = launch_fill(dst[s], c->d_phn.p, (int32_t)c->ph_neu.size(), cs);
+        if (e == hipSuccess) e = launch_fill(dst[s], c->d_phr.p, (int32_t)c->ph_res.size(), cs);
+        if (e == hipSuccess) e = launch_fill(dst[s], c->d_php.p, (int32_t)c->ph_pro.size(), cs);
+    }
+    hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        ccz4_step_graph_destroy(g);
+        return fail(CCZ4_EHIP, std::string("step graph: ") + hipGetErrorString(e));
+    }
+    *out = g;
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_step_graph_launch(ccz4_graph *g, void *stream)
+{
+    if (!g || !g->exec) return fail(CCZ4_EINVAL, "graph is NULL");
+    HIP_TRY(hipGraphLaunch(g->exec, S(stream)));
+    return CCZ4_OK;
+}
+
+void ccz4_step_graph_destroy(ccz4_graph *g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
 }
 
 ccz4_status ccz4_features(ccz4_ctx *c, const double *Q, const double *HM, float *feat, void *stream)

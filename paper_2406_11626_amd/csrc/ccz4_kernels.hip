@@ -299,9 +299,9 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk)
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WPE))) void k_rhs(const double *__restrict__ Q, double *__restrict__ K,
                                              const PatchGeom *__restrict__ geom, int32_t npatch,
-                                             RhsParams prm)
+                                             RhsParams prm, int32_t linear)
 {
-    const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t lb = linear ? (int64_t)blockIdx.x : xcd_logical_block(blockIdx.x, gridDim.x);
     const int p = (int)(lb / 3);
     if (p >= npatch || threadIdx.x >= 243) return;
     const int c = (int)(lb % 3) * 243 + threadIdx.x;
@@ -455,13 +455,14 @@ template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WPE))) void k_stage(
     const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
     const PatchGeom *__restrict__ geom, int32_t npatch, int32_t nb_slab, RhsParams prm, int32_t s, double dt,
-    const BoundaryFace *__restrict__ bf, const double *__restrict__ bg, const int32_t *__restrict__ nbr)
+    const BoundaryFace *__restrict__ bf, const double *__restrict__ bg, const int32_t *__restrict__ nbr,
+    int32_t linear)
 {
     if ((int32_t)blockIdx.x >= nb_slab) {
         stage_ghost_face((int)blockIdx.x - nb_slab, threadIdx.x, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, prm.shift == 0);
         return;
     }
-    const int64_t lb = xcd_logical_block(blockIdx.x, nb_slab);
+    const int64_t lb = linear ? (int64_t)blockIdx.x : xcd_logical_block(blockIdx.x, nb_slab);
     const int p = (int)(lb / 3);
     if (p >= npatch || threadIdx.x >= 243) return;
     const int c = (int)(lb % 3) * 243 + threadIdx.x;
@@ -513,10 +514,10 @@ __device__ __forceinline__ void lds_cell_setup(double *lds, int sl, const PatchG
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rhs_lds(
     const double *__restrict__ Q, double *__restrict__ K, const PatchGeom *__restrict__ geom, int32_t npatch,
-    RhsParams prm)
+    RhsParams prm, int32_t linear)
 {
     __shared__ double lds[LDS_DOUBLES];
-    const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t lb = linear ? (int64_t)blockIdx.x : xcd_logical_block(blockIdx.x, gridDim.x);
     const int p = (int)(lb / 3);
     if (p >= npatch) return;  // uniform over the work-group
     const int sl = (int)(lb % 3);
@@ -542,14 +543,15 @@ template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_stage_lds(
     const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
     const PatchGeom *__restrict__ geom, int32_t npatch, int32_t nb_slab, RhsParams prm, int32_t s, double dt,
-    const BoundaryFace *__restrict__ bf, const double *__restrict__ bg, const int32_t *__restrict__ nbr)
+    const BoundaryFace *__restrict__ bf, const double *__restrict__ bg, const int32_t *__restrict__ nbr,
+    int32_t linear)
 {
     __shared__ double lds[LDS_DOUBLES];
     if ((int32_t)blockIdx.x >= nb_slab) {
         stage_ghost_face((int)blockIdx.x - nb_slab, threadIdx.x, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, prm.shift == 0);
         return;
     }
-    const int64_t lb = xcd_logical_block(blockIdx.x, nb_slab);
+    const int64_t lb = linear ? (int64_t)blockIdx.x : xcd_logical_block(blockIdx.x, nb_slab);
     const int p = (int)(lb / 3);
     if (p >= npatch) return;  // uniform over the work-group
     const int sl = (int)(lb % 3);
@@ -867,16 +869,17 @@ hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t
                       int32_t precision, int32_t variant, hipStream_t st)
 {
     const int64_t nb = ((int64_t)npatch * 3 + 7) / 8 * 8;
-    if (variant == KV_LDS) {
+    const int32_t lin = (variant & KV_LINEAR) ? 1 : 0;
+    if (variant & KV_LDS) {
         if (precision == 1)
-            hipLaunchKernelGGL(k_rhs_lds<float>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p);
+            hipLaunchKernelGGL(k_rhs_lds<float>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p, lin);
         else
-            hipLaunchKernelGGL(k_rhs_lds<double>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p);
+            hipLaunchKernelGGL(k_rhs_lds<double>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p, lin);
     } else {
         if (precision == 1)
-            hipLaunchKernelGGL(k_rhs<float>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p);
+            hipLaunchKernelGGL(k_rhs<float>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p, lin);
         else
-            hipLaunchKernelGGL(k_rhs<double>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p);
+            hipLaunchKernelGGL(k_rhs<double>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p, lin);
     }
     return hipGetLastError();
 }
@@ -891,20 +894,21 @@ hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn
     const int64_t nb_slab = ((int64_t)npatch * 3 + 7) / 8 * 8;
     const int64_t nb = nb_slab + (nbf > 0 ? nbf : 0);
     const int32_t ns = (int32_t)nb_slab;
-    if (variant == KV_LDS) {
+    const int32_t lin = (variant & KV_LINEAR) ? 1 : 0;
+    if (variant & KV_LDS) {
         if (precision == 1)
             hipLaunchKernelGGL(k_stage_lds<float>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                               ns, p, s, dt, bf, bg, nbr);
+                               ns, p, s, dt, bf, bg, nbr, lin);
         else
             hipLaunchKernelGGL(k_stage_lds<double>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom,
-                               npatch, ns, p, s, dt, bf, bg, nbr);
+                               npatch, ns, p, s, dt, bf, bg, nbr, lin);
     } else {
         if (precision == 1)
             hipLaunchKernelGGL(k_stage<float>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
-                               p, s, dt, bf, bg, nbr);
+                               p, s, dt, bf, bg, nbr, lin);
         else
             hipLaunchKernelGGL(k_stage<double>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                               ns, p, s, dt, bf, bg, nbr);
+                               ns, p, s, dt, bf, bg, nbr, lin);
     }
     return hipGetLastError();
 }
