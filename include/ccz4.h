@@ -215,6 +215,27 @@ ccz4_status ccz4_constraints(ccz4_ctx *ctx, const double *Q, double *HM, double 
 ccz4_status ccz4_tag_refine(ccz4_ctx *ctx, const double *Q, double theta_r, double theta_c,
                             int32_t max_level, int8_t *tags, double *indicator, void *stream);
 
+/* Regrid plan (dynamic AMR on the refinement-criterion hook): the refined cubes of the mesh that
+   results from per-leaf tags (host, +1 refine, -1 coarsen, 0 keep; e.g. from ccz4_tag_refine or
+   ccz4_tag_learned): every leaf tagged +1 below max_level is refined; a family of 27 leaves all
+   tagged -1 is merged into its parent unless a face neighbour of one of them outside the family
+   stays refined; then cubes are refined until no face joins leaves two levels apart.
+   refined_out (host, cap x 4 int32: lev, i, j, k, sorted by level, k, j, i) receives the list
+   for ccz4_create; *n_out its length (also when cap is too small, which returns EINVAL). */
+ccz4_status ccz4_regrid_plan(const ccz4_ctx *ctx, const int8_t *tags_host, int32_t max_level,
+                             int32_t *refined_out, int64_t cap, int64_t *n_out);
+
+/* State transfer onto the leaves of another mesh of the same domain whose leaves differ from the
+   old ones by at most one level (a mesh from ccz4_regrid_plan): a leaf present in both is copied
+   whole; a new leaf inside an old leaf one level coarser takes, at each fine cell centre, the
+   tensor product over the axes of the linear interpolation of App. E's P-parallel rule on the old
+   leaf's interior; a new leaf covering 27 old leaves takes the mean of the 3^3 fine cells at
+   each cell.  Halos and ghost slabs of interpolated or averaged leaves keep what Qnew held (the
+   analytic initial data after ccz4_init_patches on the new context); fill the halos afterwards.
+   Synchronises `stream`. */
+ccz4_status ccz4_regrid_transfer(const ccz4_ctx *old_ctx, const double *Qold, const ccz4_ctx *new_ctx,
+                                 double *Qnew, void *stream);
+
 /* ---------------------------------------------------------------------------------------
    Learned refinement indicator (a project addition on the refinement-criterion hook of the
    paper's Sec. 3): a small perceptron, trained on tags of the plain criterion, that can add

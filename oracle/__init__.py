@@ -94,6 +94,8 @@ def _c(a, dt=np.float64):
 
 
 _feat = _sig("orc_features", None, [ctypes.c_void_p, _dp, _dp])
+_rg_plan = _sig("orc_regrid_plan", ctypes.c_int64, [ctypes.c_void_p, _i8p, ctypes.c_int, _ip, ctypes.c_int64])
+_rg_transfer = _sig("orc_regrid_transfer", None, [ctypes.c_void_p, _dp, ctypes.c_void_p, _dp])
 _bf16 = _sig("orc_bf16_round", ctypes.c_double, [ctypes.c_double])
 _tag_learned = _sig("orc_tag_learned", None, [ctypes.c_void_p, np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS"),
                                               _i8p, ctypes.c_float, ctypes.c_int, _i8p])
@@ -257,6 +259,18 @@ class Mesh:
         ind = np.zeros((self.np, 3))
         _tag_ind(self._h, Q, ind)
         return ind
+
+    def regrid_plan(self, tags, max_level):
+        """Refined cubes (n, 4) of the mesh after the tags."""
+        cap = 4 * (len(self.ids) + 64) * 27
+        out = np.zeros((cap, 4), dtype=np.int32)
+        n = _rg_plan(self._h, np.ascontiguousarray(tags, dtype=np.int8), int(max_level), out, cap)
+        assert n >= 0
+        return out[:n]
+
+    def regrid_transfer(self, Q, new, Qnew):
+        """In place on Qnew (a state of the Mesh `new`)."""
+        _rg_transfer(self._h, Q, new._h, Qnew)
 
     def features(self, Q):
         f = np.zeros((self.np, MLP_NIN))

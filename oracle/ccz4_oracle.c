@@ -946,3 +946,199 @@ void orc_tag_learned(const orc_mesh *m, const float *logits, const int8_t *plain
     }
     free(pre);
 }
+
+/* ----------------------------------------------------------------------------------------
+ * Regrid (dynamic AMR on the refinement-criterion hook, Sec. 3): the refined cubes of the mesh
+ * after per-leaf tags, and the transfer of a state onto the new leaves.
+ * ---------------------------------------------------------------------------------------- */
+typedef struct {
+    int *c; /* [n][4] */
+    int64_t n, cap;
+} cubeset;
+
+static int cs_has(const cubeset *s, int l, int i, int j, int k)
+{
+    int64_t r;
+    for (r = 0; r < s->n; r++)
+        if (s->c[4 * r] == l && s->c[4 * r + 1] == i && s->c[4 * r + 2] == j && s->c[4 * r + 3] == k) return 1;
+    return 0;
+}
+
+static void cs_add(cubeset *s, int l, int i, int j, int k)
+{
+    if (cs_has(s, l, i, j, k)) return;
+    push4(&s->c, &s->n, &s->cap, l, i, j, k);
+}
+
+static void cs_del(cubeset *s, int l, int i, int j, int k)
+{
+    int64_t r;
+    for (r = 0; r < s->n; r++)
+        if (s->c[4 * r] == l && s->c[4 * r + 1] == i && s->c[4 * r + 2] == j && s->c[4 * r + 3] == k) {
+            memmove(s->c + 4 * r, s->c + 4 * (r + 1), sizeof(int) * 4 * (size_t)(s->n - r - 1));
+            s->n--;
+            return;
+        }
+}
+
+/* the face neighbour of cube (l, c) along axis a, side sd, wrapped if periodic; 0 if outside */
+static int face_nb(const orc_mesh *m, int l, const int c[3], int a, int sd, int out[3])
+{
+    const int na = lev_n(m, l, a);
+    out[0] = c[0];
+    out[1] = c[1];
+    out[2] = c[2];
+    out[a] += sd;
+    if (out[a] < 0 || out[a] >= na) {
+        if (m->bc != ORC_BC_PERIODIC) return 0;
+        out[a] = (out[a] + na) % na;
+    }
+    return 1;
+}
+
+/* Rules: a leaf tagged +1 below max_level is refined; a refined cube whose 27 children are all
+   leaves tagged -1 is coarsened unless a face neighbour of one of those children (outside the
+   cube) is refined; then, while some refined cube of level L >= 1 has a face neighbour at level L
+   whose parent is not refined, that parent is refined (no face joins leaves two levels apart).
+   Writes the refined cubes, sorted, to out (cap entries); returns their number, or -1 if cap is
+   too small. */
+int64_t orc_regrid_plan(const orc_mesh *m, const int8_t *tags, int max_level, int *out, int64_t cap)
+{
+    cubeset R = {NULL, 0, 0};
+    int64_t r, p;
+    int a, sd, u, v, w, changed;
+    for (r = 0; r < m->nref; r++) {
+        const int *c = m->ref + 4 * r;
+        if (exists(m, c[0], c[1], c[2], c[3])) cs_add(&R, c[0], c[1], c[2], c[3]);
+    }
+    const int64_t nold = R.n;
+    int *old = (int *)malloc(sizeof(int) * 4 * (size_t)(nold ? nold : 1));
+    memcpy(old, R.c, sizeof(int) * 4 * (size_t)nold);
+    for (p = 0; p < m->np; p++)
+        if (tags[p] == 1 && m->id[4 * p] < max_level)
+            cs_add(&R, m->id[4 * p], m->id[4 * p + 1], m->id[4 * p + 2], m->id[4 * p + 3]);
+    for (r = 0; r < nold; r++) {
+        const int *P = old + 4 * r;
+        const int L = P[0] + 1;
+        int all = 1;
+        for (w = 0; w < 3 && all; w++)
+            for (v = 0; v < 3 && all; v++)
+                for (u = 0; u < 3 && all; u++) {
+                    const int64_t q = find_leaf(m, L, 3 * P[1] + u, 3 * P[2] + v, 3 * P[3] + w);
+                    if (q < 0 || tags[q] != -1) all = 0;
+                }
+        for (w = 0; w < 3 && all; w++)
+            for (v = 0; v < 3 && all; v++)
+                for (u = 0; u < 3 && all; u++) {
+                    const int ch[3] = {3 * P[1] + u, 3 * P[2] + v, 3 * P[3] + w};
+                    for (a = 0; a < 3 && all; a++)
+                        for (sd = -1; sd <= 1 && all; sd += 2) {
+                            int nb[3];
+                            if (!face_nb(m, L, ch, a, sd, nb)) continue;
+                            if (nb[0] / 3 == P[1] && nb[1] / 3 == P[2] && nb[2] / 3 == P[3]) continue;
+                            if (cs_has(&R, L, nb[0], nb[1], nb[2])) all = 0;
+                        }
+                }
+        if (all) cs_del(&R, P[0], P[1], P[2], P[3]);
+    }
+    do {
+        changed = 0;
+        for (r = 0; r < R.n; r++) {
+            const int L = R.c[4 * r];
+            const int c[3] = {R.c[4 * r + 1], R.c[4 * r + 2], R.c[4 * r + 3]};
+            if (L == 0) continue;
+            for (a = 0; a < 3; a++)
+                for (sd = -1; sd <= 1; sd += 2) {
+                    int nb[3];
+                    if (!face_nb(m, L, c, a, sd, nb)) continue;
+                    if (!cs_has(&R, L - 1, nb[0] / 3, nb[1] / 3, nb[2] / 3)) {
+                        cs_add(&R, L - 1, nb[0] / 3, nb[1] / 3, nb[2] / 3);
+                        changed = 1;
+                    }
+                }
+        }
+    } while (changed);
+    free(old);
+    if (R.n > cap) {
+        free(R.c);
+        return -1;
+    }
+    qsort(R.c, R.n, sizeof(int) * 4, cmp4);
+    if (R.n) memcpy(out, R.c, sizeof(int) * 4 * (size_t)R.n);
+    free(R.c);
+    return R.n;
+}
+
+/* Transfer of Qo (mesh mo) to the leaves of mn (same domain, levels differing by at most one
+   leaf-wise): a leaf of both meshes is copied (whole box); a new leaf inside an old leaf one
+   level coarser takes, at each fine cell centre, the tensor product along the three axes of the
+   linear interpolation of App. E's P-parallel rule (fine index f in 0..26 across the old leaf,
+   u = (f + 1/2)/3 - 1/2, l = clamp(floor(u), 0, 7), weights 1 - (u - l) and u - l on the old
+   interior cells l and l+1); a new leaf covering 27 old leaves one level finer takes at each
+   cell the mean of the 3^3 fine cells it covers.  Halos and ghost slabs of interpolated or
+   averaged leaves keep the values Qn held. */
+void orc_regrid_transfer(const orc_mesh *mo, const double *Qo, const orc_mesh *mn, double *Qn)
+{
+    const int64_t bs = (int64_t)ORC_BOXCELLS * NV;
+    int64_t p;
+    for (p = 0; p < mn->np; p++) {
+        const int L = mn->id[4 * p], I[3] = {mn->id[4 * p + 1], mn->id[4 * p + 2], mn->id[4 * p + 3]};
+        double *dst = Qn + p * bs;
+        const int64_t same = find_leaf(mo, L, I[0], I[1], I[2]);
+        int x, y, z, v;
+        if (same >= 0) {
+            memcpy(dst, Qo + same * bs, sizeof(double) * (size_t)bs);
+            continue;
+        }
+        const int64_t par = L > 0 ? find_leaf(mo, L - 1, I[0] / 3, I[1] / 3, I[2] / 3) : -1;
+        if (par >= 0) {
+            const double *src = Qo + par * bs;
+            for (z = 0; z < PP; z++)
+                for (y = 0; y < PP; y++)
+                    for (x = 0; x < PP; x++) {
+                        const int fc[3] = {x, y, z};
+                        int l[3];
+                        double wt[3];
+                        for (int a = 0; a < 3; a++) {
+                            const int f = 9 * (I[a] % 3) + fc[a];
+                            const double uu = (f + 0.5) / 3.0 - 0.5;
+                            int ll = (int)floor(uu);
+                            if (ll < 0) ll = 0;
+                            if (ll > PP - 2) ll = PP - 2;
+                            l[a] = ll;
+                            wt[a] = uu - ll;
+                        }
+                        double *q = dst + cix(x + HH, y + HH, z + HH) * NV;
+                        for (v = 0; v < NV; v++) {
+                            double s = 0.0;
+                            for (int dz = 0; dz < 2; dz++)
+                                for (int dy = 0; dy < 2; dy++)
+                                    for (int dx = 0; dx < 2; dx++) {
+                                        const double wgt = (dz ? wt[2] : 1.0 - wt[2]) * (dy ? wt[1] : 1.0 - wt[1]) *
+                                                           (dx ? wt[0] : 1.0 - wt[0]);
+                                        s += wgt * src[cix(l[0] + dx + HH, l[1] + dy + HH, l[2] + dz + HH) * NV + v];
+                                    }
+                            q[v] = s;
+                        }
+                    }
+            continue;
+        }
+        /* the 27 finer leaves */
+        for (z = 0; z < PP; z++)
+            for (y = 0; y < PP; y++)
+                for (x = 0; x < PP; x++) {
+                    const int64_t kid = find_leaf(mo, L + 1, 3 * I[0] + x / 3, 3 * I[1] + y / 3, 3 * I[2] + z / 3);
+                    double *q = dst + cix(x + HH, y + HH, z + HH) * NV;
+                    if (kid < 0) continue; /* cannot happen for a valid pair of meshes */
+                    const double *src = Qo + kid * bs;
+                    for (v = 0; v < NV; v++) {
+                        double s = 0.0;
+                        for (int dz = 0; dz < 3; dz++)
+                            for (int dy = 0; dy < 3; dy++)
+                                for (int dx = 0; dx < 3; dx++)
+                                    s += src[cix(3 * (x % 3) + dx + HH, 3 * (y % 3) + dy + HH, 3 * (z % 3) + dz + HH) * NV + v];
+                        q[v] = s / 27.0;
+                    }
+                }
+    }
+}

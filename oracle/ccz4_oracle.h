@@ -89,6 +89,11 @@ void orc_tag_indicator(const orc_mesh *m, const double *Q, double *ind /* [n][3]
 void orc_tag_refine(const orc_mesh *m, const double *Q, double theta_r, double theta_c,
                     int max_level, int8_t *tags);
 
+/* ---- regrid ---- */
+int64_t orc_regrid_plan(const orc_mesh *m, const int8_t *tags, int max_level, int *out /* [cap][4] */,
+                        int64_t cap);
+void orc_regrid_transfer(const orc_mesh *mo, const double *Qo, const orc_mesh *mn, double *Qn);
+
 /* ---- learned refinement indicator (ccz4_mlp.c) ---- */
 #define ORC_MLP_NIN 81
 #define ORC_MLP_NH 64

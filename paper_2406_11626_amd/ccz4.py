@@ -88,6 +88,8 @@ def lib():
             "ccz4_step_graph_create": (i32, [P, P, P, P, P, f64, i32, ctypes.POINTER(P)]),
             "ccz4_step_graph_launch": (i32, [P, P]),
             "ccz4_step_graph_destroy": (None, [P]),
+            "ccz4_regrid_plan": (i32, [P, P, i32, P, i64, ctypes.POINTER(i64)]),
+            "ccz4_regrid_transfer": (i32, [P, P, P, P, P]),
             "ccz4_features": (i32, [P, P, P, P, P]),
             "ccz4_mlp_forward": (i32, [P, P, P, i64, P, P]),
             "ccz4_mlp_workspace": (i32, [i64, ctypes.POINTER(i64)]),
@@ -243,6 +245,23 @@ def ccz4_step_graph_destroy(g):
     lib().ccz4_step_graph_destroy(g)
 
 
+def ccz4_regrid_plan(h, tags_host, max_level):
+    """Refined cubes (n, 4) int32 of the mesh after the tags (host array or tensor)."""
+    import numpy as np
+    if hasattr(tags_host, "cpu"):
+        tags_host = tags_host.cpu().numpy()
+    tags = np.ascontiguousarray(tags_host, dtype=np.int8)
+    n = ctypes.c_int64(0)
+    lib().ccz4_regrid_plan(h, tags.ctypes.data, int(max_level), None, 0, ctypes.byref(n))
+    buf = np.zeros((max(n.value, 1), 4), dtype=np.int32)
+    _check(lib().ccz4_regrid_plan(h, tags.ctypes.data, int(max_level), buf.ctypes.data, n.value, ctypes.byref(n)))
+    return buf[:n.value]
+
+
+def ccz4_regrid_transfer(h_old, Qold, h_new, Qnew, stream=None):
+    return _check(lib().ccz4_regrid_transfer(h_old, _ptr(Qold), h_new, _ptr(Qnew), _stream(stream)))
+
+
 def ccz4_features(h, Q, HM, feat, stream=None):
     return _check(lib().ccz4_features(h, _ptr(Q), _ptr(HM), _ptr(feat), _stream(stream)))
 
@@ -299,6 +318,7 @@ class Context:
     def __init__(self, n0, origin, extent, bc=BC_PERIODIC, prm=None, refined=()):
         self.prm = prm if prm is not None else params()
         self.bc = bc
+        self.n0, self.origin, self.extent = tuple(n0), tuple(origin), tuple(extent)
         self.h = ccz4_create(n0, origin, extent, bc, self.prm, refined)
         self.n_patches, self.patch_doubles, self.bytes_per_state = ccz4_layout(self.h)
         self.ids, self.geom = ccz4_patch_table(self.h)
@@ -352,6 +372,19 @@ class Context:
 
     def plan_counts(self):
         return ccz4_plan_counts(self.h)
+
+    def regrid(self, Q, tags, max_level, scenario, scen, stream=None):
+        """(new context, new state) after the tags: plan, new mesh, the analytic initial data for
+        its background and new ghost slabs, the transfer of Q, and a full halo fill."""
+        refined = [tuple(int(v) for v in r) for r in ccz4_regrid_plan(self.h, tags, max_level)]
+        new = Context(self.n0, self.origin, self.extent, self.bc, self.prm, refined)
+        for prec in (PREC_FP64, PREC_MIXED):
+            new.set_kernel(prec, self.get_kernel(prec))
+        Qn = new.new_state(0.0)
+        new.init_patches(Qn, scenario, scen, stream)
+        ccz4_regrid_transfer(self.h, Q, new.h, Qn, stream)
+        new.fill_halos(Qn, stream)
+        return new, Qn
 
     def autotune(self, Q, precision=PREC_FP64, reps=3, stream=None):
         """Time the four launch configurations on this mesh and keep the fastest; returns the
@@ -432,6 +465,7 @@ class StepGraph:
         if self.g is not None and _lib is not None:
             ccz4_step_graph_destroy(self.g)
         self.g = None
+        self._keep = None
 
     def __del__(self):
         try:

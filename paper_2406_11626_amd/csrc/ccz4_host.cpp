@@ -80,6 +80,8 @@ struct ccz4_ctx {
     int bc;
     RhsParams prm;
     std::vector<std::array<int, 4>> leaf;     // lev, i, j, k
+    std::vector<std::array<int, 4>> refined;  // refined cubes of the forest (lev, i, j, k)
+    std::unordered_map<uint64_t, int> index;  // leaf key -> leaf index
     std::vector<PatchGeom> geom;
     std::vector<FaceTask> ph_copy, ph_neu, ph_res, ph_pro;  // fill tasks by kind (restrict before prolong)
     std::vector<int32_t> nbr;                 // [leaf][6] same-level face neighbour or -1
@@ -133,6 +135,7 @@ ccz4_status build_plan(ccz4_ctx *c, const ccz4_grid_desc *g)
             leaves.push_back(cu);
             continue;
         }
+        c->refined.push_back(cu);
         for (int w = 0; w < 3; ++w)
             for (int v = 0; v < 3; ++v)
                 for (int u = 0; u < 3; ++u) cubes.push_back({cu[0] + 1, 3 * cu[1] + u, 3 * cu[2] + v, 3 * cu[3] + w});
@@ -145,7 +148,8 @@ ccz4_status build_plan(ccz4_ctx *c, const ccz4_grid_desc *g)
     });
     if (leaves.size() > (size_t)INT32_MAX / 4) return fail(CCZ4_EINVAL, "too many leaves");
     c->leaf = leaves;
-    std::unordered_map<uint64_t, int> index;
+    std::unordered_map<uint64_t, int> &index = c->index;
+    index.clear();
     for (size_t p = 0; p < leaves.size(); ++p)
         index[key(leaves[p][0], leaves[p][1], leaves[p][2], leaves[p][3])] = (int)p;
     auto find = [&](int l, int i, int j, int k) -> int {
@@ -659,6 +663,154 @@ void ccz4_step_graph_destroy(ccz4_graph *g)
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     delete g;
+}
+
+namespace {
+
+// face neighbour of cube (l, c) along axis a, side sd (periodic wrap); false if outside
+bool face_nb(const ccz4_ctx *c, int l, const int cu[3], int a, int sd, int nb[3])
+{
+    const int na = level_n(c, l, a);
+    nb[0] = cu[0];
+    nb[1] = cu[1];
+    nb[2] = cu[2];
+    nb[a] += sd;
+    if (nb[a] < 0 || nb[a] >= na) {
+        if (c->bc != CCZ4_BC_PERIODIC) return false;
+        nb[a] = (nb[a] + na) % na;
+    }
+    return true;
+}
+
+}  // namespace
+
+ccz4_status ccz4_regrid_plan(const ccz4_ctx *c, const int8_t *tags, int32_t max_level, int32_t *refined_out,
+                             int64_t cap, int64_t *n_out)
+{
+    if (!c || !tags || !n_out) return fail(CCZ4_EINVAL, "ctx, tags or n_out is NULL");
+    if (max_level < 0 || max_level > 12) return fail(CCZ4_EINVAL, "max_level out of range");
+    std::unordered_set<uint64_t> R;
+    for (const auto &cu : c->refined) R.insert(key(cu[0], cu[1], cu[2], cu[3]));
+    auto has = [&](int l, int i, int j, int k) { return R.count(key(l, i, j, k)) > 0; };
+    std::vector<std::array<int, 4>> cubes(c->refined);
+    auto add = [&](int l, int i, int j, int k) {
+        if (R.insert(key(l, i, j, k)).second) cubes.push_back({l, i, j, k});
+    };
+    auto leaf_of = [&](int l, int i, int j, int k) -> int {
+        auto it = c->index.find(key(l, i, j, k));
+        return it == c->index.end() ? -1 : it->second;
+    };
+    const size_t np = c->leaf.size();
+    for (size_t p = 0; p < np; ++p)
+        if (tags[p] == 1 && c->leaf[p][0] < max_level) add(c->leaf[p][0], c->leaf[p][1], c->leaf[p][2], c->leaf[p][3]);
+    // coarsening of families whose 27 leaves all ask for it, unless a neighbour stays refined
+    for (const auto &P : c->refined) {
+        const int L = P[0] + 1;
+        bool all = true;
+        for (int w = 0; w < 3 && all; ++w)
+            for (int v = 0; v < 3 && all; ++v)
+                for (int u = 0; u < 3 && all; ++u) {
+                    const int q = leaf_of(L, 3 * P[1] + u, 3 * P[2] + v, 3 * P[3] + w);
+                    if (q < 0 || tags[q] != -1) all = false;
+                }
+        for (int w = 0; w < 3 && all; ++w)
+            for (int v = 0; v < 3 && all; ++v)
+                for (int u = 0; u < 3 && all; ++u) {
+                    const int ch[3] = {3 * P[1] + u, 3 * P[2] + v, 3 * P[3] + w};
+                    for (int a = 0; a < 3 && all; ++a)
+                        for (int sd = -1; sd <= 1 && all; sd += 2) {
+                            int nb[3];
+                            if (!face_nb(c, L, ch, a, sd, nb)) continue;
+                            if (nb[0] / 3 == P[1] && nb[1] / 3 == P[2] && nb[2] / 3 == P[3]) continue;
+                            if (has(L, nb[0], nb[1], nb[2])) all = false;
+                        }
+                }
+        if (all) R.erase(key(P[0], P[1], P[2], P[3]));
+    }
+    // balance: the face neighbours of a refined cube of level L >= 1 have refined parents
+    bool changed = true;
+    while (changed) {
+        changed = false;
+        for (size_t r = 0; r < cubes.size(); ++r) {
+            const auto cu = cubes[r];
+            if (!has(cu[0], cu[1], cu[2], cu[3]) || cu[0] == 0) continue;
+            const int ci[3] = {cu[1], cu[2], cu[3]};
+            for (int a = 0; a < 3; ++a)
+                for (int sd = -1; sd <= 1; sd += 2) {
+                    int nb[3];
+                    if (!face_nb(c, cu[0], ci, a, sd, nb)) continue;
+                    if (!has(cu[0] - 1, nb[0] / 3, nb[1] / 3, nb[2] / 3)) {
+                        add(cu[0] - 1, nb[0] / 3, nb[1] / 3, nb[2] / 3);
+                        changed = true;
+                    }
+                }
+        }
+    }
+    std::vector<std::array<int, 4>> outv;
+    for (const auto &cu : cubes)
+        if (has(cu[0], cu[1], cu[2], cu[3])) outv.push_back(cu);
+    std::sort(outv.begin(), outv.end());
+    outv.erase(std::unique(outv.begin(), outv.end()), outv.end());
+    std::sort(outv.begin(), outv.end(), [](const std::array<int, 4> &x, const std::array<int, 4> &y) {
+        if (x[0] != y[0]) return x[0] < y[0];
+        if (x[3] != y[3]) return x[3] < y[3];
+        if (x[2] != y[2]) return x[2] < y[2];
+        return x[1] < y[1];
+    });
+    *n_out = (int64_t)outv.size();
+    if ((int64_t)outv.size() > cap) return fail(CCZ4_EINVAL, "refined_out too small (see n_out)");
+    if (!refined_out && !outv.empty()) return fail(CCZ4_EINVAL, "refined_out is NULL");
+    for (size_t r = 0; r < outv.size(); ++r)
+        for (int q = 0; q < 4; ++q) refined_out[4 * r + q] = outv[r][q];
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_regrid_transfer(const ccz4_ctx *co, const double *Qo, const ccz4_ctx *cn, double *Qn, void *stream)
+{
+    if (!co || !cn) return fail(CCZ4_EINVAL, "ctx is NULL");
+    ccz4_status st = check_ptr(Qo, "Qold");
+    if (!st) st = check_ptr(Qn, "Qnew");
+    if (st) return st;
+    if (Qo == Qn) return fail(CCZ4_EINVAL, "Qold and Qnew must differ");
+    for (int a = 0; a < 3; ++a)
+        if (co->n0[a] != cn->n0[a] || co->origin[a] != cn->origin[a] || co->extent[a] != cn->extent[a])
+            return fail(CCZ4_EINVAL, "meshes of different domains");
+    auto leaf_of = [&](int l, int i, int j, int k) -> int {
+        auto it = co->index.find(key(l, i, j, k));
+        return it == co->index.end() ? -1 : it->second;
+    };
+    std::vector<RegridTask> tasks(cn->leaf.size());
+    for (size_t p = 0; p < cn->leaf.size(); ++p) {
+        const auto &lf = cn->leaf[p];
+        RegridTask &t = tasks[p];
+        std::memset(&t, 0, sizeof(t));
+        const int same = leaf_of(lf[0], lf[1], lf[2], lf[3]);
+        if (same >= 0) {
+            t.kind = RG_COPY;
+            t.src = same;
+            continue;
+        }
+        const int par = lf[0] > 0 ? leaf_of(lf[0] - 1, lf[1] / 3, lf[2] / 3, lf[3] / 3) : -1;
+        if (par >= 0) {
+            t.kind = RG_PROLONG;
+            t.src = par;
+            for (int a = 0; a < 3; ++a) t.o[a] = lf[1 + a] % 3;
+            continue;
+        }
+        t.kind = RG_RESTRICT;
+        for (int w = 0; w < 3; ++w)
+            for (int v = 0; v < 3; ++v)
+                for (int u = 0; u < 3; ++u) {
+                    const int kid = leaf_of(lf[0] + 1, 3 * lf[1] + u, 3 * lf[2] + v, 3 * lf[3] + w);
+                    if (kid < 0) return fail(CCZ4_ELAYOUT, "new leaf neither kept, inside an old leaf, nor covering 27");
+                    t.kid[w * 9 + v * 3 + u] = kid;
+                }
+    }
+    DevBuf<RegridTask> d;
+    HIP_TRY(d.upload(tasks));
+    HIP_TRY(launch_regrid(Qo, Qn, d.p, (int32_t)tasks.size(), S(stream)));
+    HIP_TRY(hipStreamSynchronize(S(stream)));  // the task table is released on return
+    return CCZ4_OK;
 }
 
 ccz4_status ccz4_features(ccz4_ctx *c, const double *Q, const double *HM, float *feat, void *stream)

@@ -849,6 +849,70 @@ __global__ void k_tag_decide(const double *__restrict__ ind, const int32_t *__re
     tags[p] = tg;
 }
 
+// ------------------------------------------------------------------ regrid transfer
+// One work-group per leaf of the new mesh.  COPY: the whole box.  PROLONG: at each fine cell
+// centre the tensor product over the axes of linear interpolation on the parent's interior
+// (fine index f = 9 o + x across the parent, u = (f + 1/2)/3 - 1/2, l = clamp(floor(u), 0, 7),
+// weights 1 - (u - l), u - l), summed in the order dz, dy, dx.  RESTRICT: the mean of the 3^3
+// fine cells.  No contraction, so that the sums round exactly as written.
+__global__ __launch_bounds__(256) void k_regrid(const double *__restrict__ Qo, double *__restrict__ Qn,
+                                                const RegridTask *__restrict__ tasks, int32_t n)
+{
+#pragma clang fp contract(off)
+    const int p = blockIdx.x;
+    if (p >= n) return;
+    const RegridTask tk = tasks[p];
+    double *dst = Qn + (int64_t)p * PS;
+    if (tk.kind == RG_COPY) {
+        const double *src = Qo + (int64_t)tk.src * PS;
+        for (int e = threadIdx.x; e < PS; e += blockDim.x) dst[e] = src[e];
+        return;
+    }
+    for (int e = threadIdx.x; e < NCELL * NV; e += blockDim.x) {
+        const int v = e / NCELL, c = e % NCELL;
+        const int x = c % 9, y = (c / 9) % 9, z = c / 81;
+        double s = 0.0;
+        if (tk.kind == RG_PROLONG) {
+            const double *src = Qo + (int64_t)tk.src * PS + (int64_t)v * CS;
+            const int fc[3] = {x, y, z};
+            int l[3];
+            double wt[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int f = 9 * tk.o[a] + fc[a];
+                const double uu = (f + 0.5) / 3.0 - 0.5;
+                int ll = (int)floor(uu);
+                ll = ll < 0 ? 0 : (ll > PN - 2 ? PN - 2 : ll);
+                l[a] = ll;
+                wt[a] = uu - ll;
+            }
+            for (int dz = 0; dz < 2; ++dz)
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx) {
+                        const double wgt = (dz ? wt[2] : 1.0 - wt[2]) * (dy ? wt[1] : 1.0 - wt[1]) *
+                                           (dx ? wt[0] : 1.0 - wt[0]);
+                        s += wgt * src[boff(l[0] + dx + 3, l[1] + dy + 3, l[2] + dz + 3)];
+                    }
+        } else {
+            const int kid = tk.kid[(z / 3) * 9 + (y / 3) * 3 + x / 3];
+            const double *src = Qo + (int64_t)kid * PS + (int64_t)v * CS;
+            for (int dz = 0; dz < 3; ++dz)
+                for (int dy = 0; dy < 3; ++dy)
+                    for (int dx = 0; dx < 3; ++dx)
+                        s += src[boff(3 * (x % 3) + dx + 3, 3 * (y % 3) + dy + 3, 3 * (z % 3) + dz + 3)];
+            s = s / 27.0;
+        }
+        dst[(int64_t)v * CS + boff(x + 3, y + 3, z + 3)] = s;
+    }
+}
+
+hipError_t launch_regrid(const double *Qo, double *Qn, const RegridTask *tasks, int32_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_regrid, dim3(n), dim3(256), 0, st, Qo, Qn, tasks, n);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ launchers
 hipError_t launch_init(double *Q, const PatchGeom *geom, const uint8_t *bmask, int32_t npatch, int32_t scen,
                        const InitArgs &a, hipStream_t st)

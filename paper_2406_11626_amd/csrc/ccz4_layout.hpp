@@ -40,6 +40,15 @@ struct FaceTask {
     int32_t o1, o2;    // PROLONG: position of the fine patch inside the coarse face
 };
 
+enum RegridKind : int32_t { RG_COPY = 0, RG_PROLONG = 1, RG_RESTRICT = 2 };
+
+struct RegridTask {  // how one leaf of a new mesh takes its data from the old mesh
+    int32_t kind;
+    int32_t src;       // COPY: old leaf; PROLONG: old parent leaf
+    int32_t o[3];      // PROLONG: position of the new leaf inside the parent (0..2 per axis)
+    int32_t kid[27];   // RESTRICT: the 27 old leaves, index (z/3)*9 + (y/3)*3 + x/3
+};
+
 struct BoundaryFace {  // a Sommerfeld face of a leaf and its background slab
     int32_t patch, axis, side, bg;
 };

@@ -37,6 +37,11 @@ class Workload:
     def dt(self):
         return self.cfl * self.dx_min()
 
+    def dt_for(self, ctx):
+        """CFL * the finest spacing of the context's current mesh (global time step)."""
+        maxlev = int(ctx.ids[:, 0].max()) if ctx.n_patches else 0
+        return self.cfl * self.extent[0] / (self.n0[0] * 9 * 3 ** maxlev)
+
 
 GAUGE = dict(kappa1=1.0, kappa2=0.0, kappa3=0.0, tau=1.0, e=1.0, c=1.0, mu=0.2, f=0.75, eta=2.0,
              ko_eps=0.1, slicing=0, shift=0)
@@ -90,6 +95,9 @@ def config(n):
                         (18.0,) * 3, ccz4.BC_SOMMERFELD, BLACK_HOLE, ccz4.SCEN_PUNCTURE, [1.0, 0.0, 0.0, 0.0, 0], 50)
     if n == 5:
         scen = [0.5, 3.0, 0.0, 0.0, 0.0, 0.095, 0.0, 0.5, -3.0, 0.0, 0.0, 0.0, -0.095, 0.0]
-        return Workload("binary puncture (Brill-Lindquist + Bowen-York) on [-12,12]^3", (16, 16, 16), (-12.0,) * 3,
-                        (24.0,) * 3, ccz4.BC_SOMMERFELD, BLACK_HOLE, ccz4.SCEN_BL_BY, scen, 20)
+        ref = sphere_refinement((16, 16, 16), (-12.0,) * 3, (24.0,) * 3, [(3.0, 0.0, 0.0), (-3.0, 0.0, 0.0)],
+                                [3.0, 1.0, 0.4])
+        return Workload("binary puncture (Brill-Lindquist + Bowen-York) on [-12,12]^3, 4 levels, dynamic regrid",
+                        (16, 16, 16), (-12.0,) * 3, (24.0,) * 3, ccz4.BC_SOMMERFELD, BLACK_HOLE, ccz4.SCEN_BL_BY, scen,
+                        20, refined=ref)
     raise ValueError(n)

@@ -589,3 +589,32 @@ def test_step_graph_replays_match_eager_steps(kernel):
         assert torch.equal(Qg, Qe), rep
         norms, _ = ctx.constraints(Qe)  # unrelated eager work between replays
     graph.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_regrid_plan_and_transfer_match_oracle(seed):
+    """Regrid of a Sommerfeld mesh with two levels under random tags: the library's plan equals
+    the oracle's (integer work: exactly), and the transferred state equals the oracle's bit for
+    bit on every new leaf (whole box for kept leaves, interior for the others)."""
+    w = scenarios.config(2)
+    refined = [(0, 1, 1, 1), (0, 2, 2, 1), (1, 4, 4, 4)]
+    n0, org, ext = (4, 4, 3), (-9.0, -9.0, -6.75), (18.0, 18.0, 13.5)
+    ctx, m = make_pair(n0, org, ext, w.bc, w.params(), refined)
+    rng = np.random.default_rng(80 + seed)
+    tags = rng.choice(np.array([-1, 0, 0, 1], np.int8), m.np)
+    if seed == 0:  # one whole family asked to coarsen
+        tags[m.ids[:, 0] == 2] = -1
+    plan_d = ccz4.ccz4_regrid_plan(ctx.h, tags, 3)
+    plan_o = m.regrid_plan(tags, 3)
+    assert {tuple(r) for r in plan_d.tolist()} == {tuple(r) for r in plan_o.tolist()}
+    new_refined = [tuple(int(v) for v in r) for r in plan_o]
+    ctx2, m2 = make_pair(n0, org, ext, w.bc, w.params(), new_refined)
+    Qo = random_state(m, 90 + seed)
+    Qn_o = m2.zeros()
+    m.regrid_transfer(Qo, m2, Qn_o)
+    Qn_d = ctx2.new_state(0.0)
+    ccz4.ccz4_regrid_transfer(ctx.h, to_gpu(Qo), ctx2.h, Qn_d)
+    got = to_host(Qn_d)
+    assert np.array_equal(got[:, 3:12, 3:12, 3:12], Qn_o[:, 3:12, 3:12, 3:12])
+    kept = [p for p, idv in enumerate(m2.ids.tolist()) if idv in m.ids.tolist()]
+    assert np.array_equal(got[kept], Qn_o[kept])
