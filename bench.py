@@ -45,7 +45,7 @@ def stage_bytes(s, cells, same_level_faces):
     return stage_bytes_per_cell(s) * cells + HALO_BYTES_PER_FACE * same_level_faces
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_puncture16_hbm_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_lds_puncture16_hbm_traffic.md")
 
 
 def kernel_source_digest():

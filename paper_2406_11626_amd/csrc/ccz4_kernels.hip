@@ -537,6 +537,39 @@ struct LdsStageSink {
     int o;
     __device__ __forceinline__ void put(int v, double r) { st->combine_at(o, v, r); }
     __device__ __forceinline__ void finish() { st->finish_at(o); }
+    // A round's outputs: every load of Q^n and acc first, then the combines and stores, so that
+    // the loads are in flight together (the compiler cannot reorder them past the stores itself,
+    // not knowing that acc, Q^n and Q_next do not overlap).
+    template <int N>
+    __device__ __forceinline__ void flush(const int (&slots)[N], const double (&r)[N])
+    {
+        const int s = st->s;
+        double a[N], b[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const int e = slots[j] * CS + o;
+            a[j] = s < 3 ? st->qn[e] : 0.0;
+            b[j] = s > 0 ? st->acc[e] : 0.0;
+        }
+        const double dt = st->dt;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const int v = slots[j];
+            const int e = v * CS + o;
+            if (s == 0) {
+                st->acc[e] = a[j] + (1.0 / 6.0) * dt * r[j];
+                st->out(e, a[j] + 0.5 * dt * r[j]);
+            } else if (s < 3) {
+                st->acc[e] = b[j] + (1.0 / 3.0) * dt * r[j];
+                st->out(e, a[j] + (s == 1 ? 0.5 : 1.0) * dt * r[j]);
+            } else {
+                const double val = b[j] + (1.0 / 6.0) * dt * r[j];
+                if (v < 6) st->carry[v] = val;
+                else if (v >= SAT && v < SAT + 6) st->carry[v - SAT + 6] = val;
+                else st->out(e, val);
+            }
+        }
+    }
 };
 
 template <typename T>

@@ -124,6 +124,12 @@ struct LdsRhsSink {
     int o;
     __device__ __forceinline__ void put(int v, double r) { kb[v * CS + o] = r; }
     __device__ __forceinline__ void finish() {}
+    template <int N>
+    __device__ __forceinline__ void flush(const int (&slots)[N], const double (&r)[N])
+    {
+#pragma unroll
+        for (int j = 0; j < N; ++j) put(slots[j], r[j]);
+    }
 };
 
 // (s, d) of the symmetric index s = sym(cc, dd), cc <= dd
@@ -230,9 +236,7 @@ __device__ constexpr int R4_OUT[24] = {SB, SB + 1, SB + 2, SB + 3, SB + 4, SB + 
 template <typename Sink, int N>
 __device__ __forceinline__ void flush(Sink &snk, bool act, const int (&slots)[N], const double (&r)[N])
 {
-    if (!act) return;
-#pragma unroll
-    for (int j = 0; j < N; ++j) snk.put(slots[j], r[j]);
+    if (act) snk.flush(slots, r);
 }
 
 // Right-hand side of the lane's cell of slab sl of the patch at qp.  Every lane of the
