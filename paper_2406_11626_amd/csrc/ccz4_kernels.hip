@@ -537,20 +537,25 @@ struct LdsStageSink {
     int o;
     __device__ __forceinline__ void put(int v, double r) { st->combine_at(o, v, r); }
     __device__ __forceinline__ void finish() { st->finish_at(o); }
-    // A round's outputs: every load of Q^n and acc first, then the combines and stores, so that
-    // the loads are in flight together (the compiler cannot reorder them past the stores itself,
-    // not knowing that acc, Q^n and Q_next do not overlap).
+    // A round's outputs in two halves: every load of Q^n and acc first, so that they are in
+    // flight together (the compiler cannot move them past the stores itself, not knowing that
+    // acc, Q^n and Q_next do not overlap), then the combines and stores.
     template <int N>
-    __device__ __forceinline__ void flush(const int (&slots)[N], const double (&r)[N])
+    __device__ __forceinline__ void load(const int (&slots)[N], double (&a)[N], double (&b)[N])
     {
         const int s = st->s;
-        double a[N], b[N];
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             const int e = slots[j] * CS + o;
             a[j] = s < 3 ? st->qn[e] : 0.0;
             b[j] = s > 0 ? st->acc[e] : 0.0;
         }
+    }
+    template <int N>
+    __device__ __forceinline__ void store(const int (&slots)[N], const double (&r)[N], const double (&a)[N],
+                                          const double (&b)[N])
+    {
+        const int s = st->s;
         const double dt = st->dt;
 #pragma unroll
         for (int j = 0; j < N; ++j) {

@@ -60,16 +60,32 @@ __device__ __forceinline__ void lds_stage_slot(const double *__restrict__ qp, do
     }
 }
 
-// Stage the N slots of a round into buffers 0..N-1 and make them visible to the work-group.
+// Issue the copies of a round's N slots into buffers 0..N-1 once every wave is done with the
+// previous round's buffers; returns without waiting for them.
+template <int N>
+__device__ __forceinline__ void lds_issue(const double *__restrict__ qp, double *lds, int sl, const int (&slots)[N],
+                                          int w, int lane)
+{
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < N; ++j) lds_stage_slot(qp, lds, sl, slots[j], j, w, lane);
+}
+
+// Wait for every outstanding memory operation of the lane and make the staged slots visible to
+// the work-group.
+__device__ __forceinline__ void lds_wait()
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// Stage the N slots of a round and wait for them.
 template <int N>
 __device__ __forceinline__ void lds_round(const double *__restrict__ qp, double *lds, int sl, const int (&slots)[N],
                                           int w, int lane)
 {
-    __syncthreads();  // every lane is done with the previous round's buffers
-#pragma unroll
-    for (int j = 0; j < N; ++j) lds_stage_slot(qp, lds, sl, slots[j], j, w, lane);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    lds_issue(qp, lds, sl, slots, w, lane);
+    lds_wait();
 }
 
 // One cell's view of the staged slab.
@@ -124,8 +140,12 @@ struct LdsRhsSink {
     int o;
     __device__ __forceinline__ void put(int v, double r) { kb[v * CS + o] = r; }
     __device__ __forceinline__ void finish() {}
+    // A round's outputs in two halves (see flush below): the RHS alone reads nothing.
     template <int N>
-    __device__ __forceinline__ void flush(const int (&slots)[N], const double (&r)[N])
+    __device__ __forceinline__ void load(const int (&)[N], double (&)[N], double (&)[N]) {}
+    template <int N>
+    __device__ __forceinline__ void store(const int (&slots)[N], const double (&r)[N], const double (&)[N],
+                                          const double (&)[N])
     {
 #pragma unroll
         for (int j = 0; j < N; ++j) put(slots[j], r[j]);
@@ -231,14 +251,10 @@ __device__ constexpr int R4_OUT[24] = {SB, SB + 1, SB + 2, SB + 3, SB + 4, SB + 
                                        SB + 8, SBB, SBB + 1, SBB + 2, SG, SG + 1, SG + 2, SG + 3,
                                        SG + 4, SG + 5, SALPHA, SBETA, SBETA + 1, SBETA + 2, SPHI, SK0};
 
-// Hand a round's outputs to the sink in one loop with no barrier in it, so that the sink's own
-// global loads (the RK4 combine reads Q^n and the accumulator) are all in flight together.
-template <typename Sink, int N>
-__device__ __forceinline__ void flush(Sink &snk, bool act, const int (&slots)[N], const double (&r)[N])
-{
-    if (act) snk.flush(slots, r);
-}
-
+// A round's outputs go to the sink in two halves: its global loads (the RK4 combine reads Q^n
+// and the accumulator), issued together, and its stores.  Between the two the caller issues the
+// staging of the following round, so that those copies and the sink's loads are in flight
+// together, and waits for both; the stores are then left in flight over the next barrier.
 // Right-hand side of the lane's cell of slab sl of the patch at qp.  Every lane of the
 // work-group must call this (staging and barriers); only lanes with act = true compute.
 template <typename T, typename Sink>
@@ -419,15 +435,19 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
         }
     }
 
-    flush(snk, act, R2_OUT, ro2);
-
-    // ------------------------------------------------------------ round 3
-    // buffers: 0..2 D_zyy, D_zyz, D_zzz; 3..5 P; 6..8 A; 9..11 Ghat; 12 K; 13 Theta
     {
         const int r3[14] = {SD + 15, SD + 16, SD + 17, SP, SP + 1, SP + 2, SA, SA + 1, SA + 2,
                             SGHAT, SGHAT + 1, SGHAT + 2, SK, STHETA};
-        lds_round(qp, lds, sl, r3, w, lane);
+        double qa[15], qb[15];
+        if (act) snk.load(R2_OUT, qa, qb);
+        lds_issue(qp, lds, sl, r3, w, lane);
+        __builtin_amdgcn_s_waitcnt(0);  // the sink's loads and this wave's copies have landed
+        if (act) snk.store(R2_OUT, ro2, qa, qb);
     }
+    __syncthreads();  // every wave's copies have landed; the stores may still be in flight
+
+    // ------------------------------------------------------------ round 3
+    // buffers: 0..2 D_zyy, D_zyz, D_zzz; 3..5 P; 6..8 A; 9..11 Ghat; 12 K; 13 Theta
     if (act) {
         const LdsCell C = fresh(C0);
         const int o = fresh(o0);
@@ -785,15 +805,19 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
         }
     }
 
-    flush(snk, act, R3_OUT, ro3);
-
-    // ------------------------------------------------------------ round 4
-    // buffers: 0..2 b; 3..8 gt; 9 alpha; 10..12 beta; 13 phi
     {
         const int r4[14] = {SBB, SBB + 1, SBB + 2, SG, SG + 1, SG + 2, SG + 3, SG + 4, SG + 5,
                             SALPHA, SBETA, SBETA + 1, SBETA + 2, SPHI};
-        lds_round(qp, lds, sl, r4, w, lane);
+        double qa[20], qb[20];
+        if (act) snk.load(R3_OUT, qa, qb);
+        lds_issue(qp, lds, sl, r4, w, lane);
+        __builtin_amdgcn_s_waitcnt(0);  // the sink's loads and this wave's copies have landed
+        if (act) snk.store(R3_OUT, ro3, qa, qb);
     }
+    __syncthreads();  // every wave's copies have landed; the stores may still be in flight
+
+    // ------------------------------------------------------------ round 4
+    // buffers: 0..2 b; 3..8 gt; 9 alpha; 10..12 beta; 13 phi
     if (act) {
         const LdsCell C = fresh(C0);
         const int o = fresh(o0);
@@ -872,7 +896,13 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
                           phid * static_cast<double>((al * Kt - trB) * T(1.0 / 3.0)) + stencils(C, 13).k));
         keep(ro4[23], 0.0);
     }
-    flush(snk, act, R4_OUT, ro4);
+    {
+        double qa[24], qb[24];
+        if (act) {
+            snk.load(R4_OUT, qa, qb);
+            snk.store(R4_OUT, ro4, qa, qb);
+        }
+    }
     if (act) snk.finish();
 }
 
