@@ -60,9 +60,10 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(config):
     """HBM bytes per launch of the fused stage kernel from the committed counter summary, or None
-    when there is none or the kernel sources have changed since the counters were taken."""
+    when there is none, when it covers another workload, or when the kernel sources have changed
+    since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     rec = {}
@@ -71,12 +72,31 @@ def measured_traffic():
             if ln.startswith("- ") and ":" in ln:
                 k, v = ln[2:].split(":", 1)
                 rec[k.strip()] = v.strip().strip("`")
-    if rec.get("source_sha256") != kernel_source_digest():
+    if rec.get("source_sha256") != kernel_source_digest() or rec.get("workload_config") != str(config):
         return None
     try:
         return float(rec["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def copy_bandwidth(nbytes=2**30, reps=10):
+    """Measured device-to-device copy rate in GB/s (read + write bytes per second) of a plain torch
+    copy of nbytes, the practical reference beside the spec peak."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def run_gpu(args, w, precision):
@@ -272,7 +292,8 @@ def main():
     r64 = run_gpu(args, w, 0)
     stages = 4 * args.steps
     value = r64["cells"] * stages / r64["wall"]
-    traffic = measured_traffic()
+    traffic = measured_traffic(args.config)
+    copy_gbs = copy_bandwidth()
     line = {
         "metric": "CCZ4 cell-updates/s per RK4 stage (FP64 vs mixed), % of FP64/HBM roofline",
         "value": value,
@@ -294,6 +315,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": r64["stage_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r64["stage_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": r64["kernel"], "avg_ms": r64["stage_ms"],
+                     "copy_gbs": copy_gbs, "frac_of_copy": r64["stage_gbs"] / copy_gbs,
                      "algorithmic_bytes_per_launch": r64["stage_bytes"]},
         "constraints_after": {"L2_H": r64["norms"][0], "L2_M": r64["norms"][1], "nonfinite": r64["norms"][2]},
     }
