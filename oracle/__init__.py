@@ -42,12 +42,13 @@ class Params(ctypes.Structure):
         ("tau", ctypes.c_double), ("e", ctypes.c_double), ("c", ctypes.c_double),
         ("mu", ctypes.c_double), ("f", ctypes.c_double), ("eta", ctypes.c_double),
         ("ko_eps", ctypes.c_double), ("slicing", ctypes.c_int), ("shift", ctypes.c_int),
+        ("formulation", ctypes.c_int),
     ]
 
 
 def params(**kw):
     d = dict(kappa1=0.1, kappa2=0.0, kappa3=0.5, tau=1.0, e=1.0, c=1.0, mu=0.2, f=0.75,
-             eta=2.0, ko_eps=0.1, slicing=1, shift=1)
+             eta=2.0, ko_eps=0.1, slicing=1, shift=1, formulation=0)
     d.update(kw)
     return Params(**d)
 
@@ -77,6 +78,7 @@ _init = _sig("orc_init", ctypes.c_int, [ctypes.c_void_p, _dp, ctypes.c_int, _dp]
 _set_bg = _sig("orc_set_background", None, [ctypes.c_void_p, _dp])
 _fill = _sig("orc_fill_halos", None, [ctypes.c_void_p, _dp])
 _rhs = _sig("orc_rhs", None, [ctypes.c_void_p, _PP, _dp, _dp])
+_recon = _sig("orc_reconstruct_aux", None, [ctypes.c_void_p, _dp])
 _rhs_subset = _sig("orc_rhs_subset", None,
                    [ctypes.c_void_p, _PP, _dp, _dp, ctypes.c_int64, _i64p])
 _rk4 = _sig("orc_rk4_stage", ctypes.c_int,
@@ -245,6 +247,11 @@ class Mesh:
             _rhs_subset(self._h, ctypes.byref(pr), Q, k, sel.size, sel)
         return k
 
+    def reconstruct(self, Q):
+        """Second-order formulation: the auxiliaries of every interior cell from FD4
+        differences of the primaries (halos of Q must be filled); in place."""
+        _recon(self._h, Q)
+
     def rk4_stage(self, s, dt, Qn, k, acc, Qnext):
         if _rk4(self._h, s, dt, Qn, k, acc, Qnext):
             raise ValueError("bad stage")
@@ -289,7 +296,9 @@ class Mesh:
         return tags
 
     def rk4_step(self, pr, Q, dt):
-        """One classical RK4 step: four (fill, rhs, stage) sweeps."""
+        """One classical RK4 step: four (fill, rhs, stage) sweeps.  In the second-order
+        formulation every stage result (the final one after its projection) gets its halos
+        filled and its auxiliaries reconstructed before it is used (Algorithm 2)."""
         acc = np.zeros_like(Q)
         Qs = Q.copy()
         Qnew = Q.copy()
@@ -298,5 +307,8 @@ class Mesh:
             k = self.rhs(pr, Qs)
             Qnext = Q.copy() if s < 3 else Qnew
             self.rk4_stage(s, dt, Q, k, acc, Qnext)
+            if pr.formulation:
+                self.fill_halos(Qnext)
+                self.reconstruct(Qnext)
             Qs = Qnext
         return Qnew

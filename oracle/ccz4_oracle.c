@@ -69,6 +69,7 @@ void orc_rhs_box(const orc_params *pr, const double dx[3], const double *box, do
                 for (v = 0; v < 58; v++) {
                     double ko = 0;
                     if (frozen_slot(pr, v)) continue;
+                    if (pr->formulation && v >= 25) continue; /* SO: KO on the primaries only */
                     for (a = 0; a < 3; a++) {
                         for (s = -3; s <= 3; s++) {
                             int xx = x + (a == 0 ? s : 0), yy = y + (a == 1 ? s : 0),
@@ -704,6 +705,45 @@ void orc_rhs(const orc_mesh *m, const orc_params *pr, const double *Q, double *k
 {
     int64_t p;
     for (p = 0; p < m->np; p++) orc_rhs_subset(m, pr, Q, kout, 1, &p);
+}
+
+/* ----------------------------------------------------------------------------------------
+ * Second-order formulation (Sec. 2, "explicit gradient reconstruction", and Algorithm 2):
+ * after each update the auxiliaries are recomputed from the primaries with the central FD4
+ * difference, by their definitions A_i = d_i alpha, B_k^i = d_k beta^i,
+ * D_kij = d_k gt_ij / 2, P_i = d_i phi (eq. auxiliary-variables).  Interior cells of every
+ * leaf; the primaries' halos must be filled; no halo is written.
+ * ---------------------------------------------------------------------------------------- */
+void orc_reconstruct_aux(const orc_mesh *m, double *Q)
+{
+    int64_t p;
+    int x, y, z, a, s, i, v;
+    double w[5], d[11];
+    for (p = 0; p < m->np; p++) {
+        double org[3], dx[3];
+        double *box = Q + p * (int64_t)ORC_BOXCELLS * NV;
+        patch_geom(m, p, org, dx);
+        for (z = HH; z < HH + PP; z++)
+            for (y = HH; y < HH + PP; y++)
+                for (x = HH; x < HH + PP; x++) {
+                    double *q = box + cix(x, y, z) * NV;
+                    for (a = 0; a < 3; a++) {
+                        /* FD4 along axis a of gt (slots 0-5), alpha (6), beta (7-9), phi (10) */
+                        for (v = 0; v <= 10; v++) {
+                            for (s = -2; s <= 2; s++) {
+                                int xx = x + (a == 0 ? s : 0), yy = y + (a == 1 ? s : 0),
+                                    zz = z + (a == 2 ? s : 0);
+                                w[s + 2] = box[cix(xx, yy, zz) * NV + v];
+                            }
+                            d[v] = orc_fd4(w, dx[a]);
+                        }
+                        q[25 + a] = d[6];                                       /* A_a */
+                        for (i = 0; i < 3; i++) q[28 + 3 * a + i] = d[7 + i];   /* B_a^i */
+                        for (i = 0; i < 6; i++) q[37 + 6 * a + i] = 0.5 * d[i]; /* D_a(ij) */
+                        q[55 + a] = d[10];                                      /* P_a */
+                    }
+                }
+    }
 }
 
 /* ----------------------------------------------------------------------------------------

@@ -41,6 +41,9 @@ typedef struct {
     double ko_eps;                 /* Kreiss-Oliger strength epsilon */
     int slicing;                   /* 0: harmonic g(alpha)=1, 1: 1+log g(alpha)=2/alpha */
     int shift;                     /* 0: frozen (static) shift, 1: Gamma-driver (s=1) */
+    int formulation;               /* 0: first order (FO, all 58 evolve, red terms on);
+                                      1: second order (SO, the 24 primaries evolve, red terms
+                                      off, A, B, D, P reconstructed after every update) */
 } orc_params;
 
 /* ---- pointwise algebra (App. B) ---- */
@@ -78,6 +81,10 @@ int orc_init(const orc_mesh *m, double *Q, int scenario, const double *sp);
 void orc_set_background(orc_mesh *m, const double *Q);
 void orc_fill_halos(const orc_mesh *m, double *Q);
 void orc_rhs(const orc_mesh *m, const orc_params *pr, const double *Q, double *kout);
+/* Second-order formulation: the auxiliaries A_k = d_k alpha, B_k^i = d_k beta^i,
+   D_kij = d_k gt_ij / 2, P_k = d_k phi on every leaf interior cell, from central FD4
+   differences of the primaries (whose halos must be filled); halos are left as they are. */
+void orc_reconstruct_aux(const orc_mesh *m, double *Q);
 void orc_rhs_subset(const orc_mesh *m, const orc_params *pr, const double *Q, double *kout,
                     int64_t n_sel, const int64_t *sel);
 int orc_rk4_stage(const orc_mesh *m, int s, double dt, const double *Qn, const double *k,

@@ -11,7 +11,10 @@
  *   - d_(k D_i)jl = (d_k D_ijl + d_i D_kjl)/2, d_(k P_i) = (d_k P_i + d_i P_k)/2,
  *     d_(k B_l)^i = (d_k B_l^i + d_l B_k^i)/2, d_(i A_j) = (d_i A_j + d_j A_i)/2;
  *   - the Ricci tensor R_ij is evaluated for all nine index pairs from the relations of
- *     App. B and its symmetric part enters the At equation (its trace uses all nine).
+ *     App. B and its symmetric part enters the At equation (its trace uses all nine);
+ *   - second-order formulation (pr->formulation = 1, Sec. 2 and Algorithm 2): the same
+ *     equations for the primaries with the red terms removed (App. B: they are used in the
+ *     first-order formulation only), and zero right-hand sides for A, B, D, P.
  * dq[k][v] is the derivative along axis k of slot v; only slots 11..57 are ever read.
  */
 #include <math.h>
@@ -400,7 +403,8 @@ void orc_rhs_point(const orc_params *pr, const double *q, const double *dq, doub
         for (k = 0; k < 3; k++)
             for (l = 0; l < 3; l++) s += c->ig[k][l] * 0.5 * (c->dB[k][l][i] + c->dB[l][k][i]);
         for (k = 0; k < 3; k++) s += s_on * 1.0 / 3.0 * c->ig[i][k] * sdBtr[k];
-        for (k = 0; k < 3; k++) s += 2.0 * al * c->ig[i][k] * trdAt[k]; /* red */
+        if (!pr->formulation)
+            for (k = 0; k < 3; k++) s += 2.0 * al * c->ig[i][k] * trdAt[k]; /* red */
         for (j = 0; j < 3; j++) s += -4.0 / 3.0 * al * c->ig[i][j] * c->dK[j];
         s += 2.0 / 3.0 * Gtv[i] * trB;
         for (k = 0; k < 3; k++) s += -Gtv[k] * c->B[k][i];
@@ -415,7 +419,8 @@ void orc_rhs_point(const orc_params *pr, const double *q, const double *dq, doub
         for (k = 0; k < 3; k++)
             s += -2.0 * al * c->ig[k][i] * (c->Theta * c->A[k] / al + 2.0 / 3.0 * c->K * Z[k]);
         for (j = 0; j < 3; j++) s += -2.0 * Aup[i][j] * c->A[j];
-        for (k = 0; k < 3; k++) s += -4.0 * al * c->ig[i][k] * DA[k]; /* red */
+        if (!pr->formulation)
+            for (k = 0; k < 3; k++) s += -4.0 * al * c->ig[i][k] * DA[k]; /* red */
         for (j = 0; j < 3; j++) s += -2.0 * al * k1 * c->ig[i][j] * Z[j];
         {
             double t = 0;
@@ -499,6 +504,11 @@ void orc_rhs_point(const orc_params *pr, const double *q, const double *dq, doub
     }
     /* --- K_0: constant --- */
     out[S_K0] = 0.0;
+    /* second-order formulation: the auxiliaries do not evolve (they are reconstructed from
+       the primaries after each update); the red terms are already off above, and the red
+       terms of the auxiliary equations go with those equations */
+    if (pr->formulation)
+        for (i = S_A(0); i <= S_P(2); i++) out[i] = 0.0;
 }
 
 /* Hamiltonian H = R + 2/3 K^2 - At_ij At^ij with R = phi^2 gt^ij R_ij (pure Ricci, no Z terms),
