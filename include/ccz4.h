@@ -57,11 +57,16 @@ enum { CCZ4_PREC_FP64 = 0, CCZ4_PREC_MIXED = 1 };
 enum { CCZ4_SCEN_GAUGE_WAVE = 0, CCZ4_SCEN_PUNCTURE = 1, CCZ4_SCEN_BL_BY = 2 };
 
 /* Parameters of App. B (kappa1..3, tau, e, c, mu, f, eta), the KO strength epsilon of
-   App. D, the slicing function g(alpha) (harmonic: 1; 1+log: 2/alpha) and the shift
-   condition (frozen: beta, b, B do not evolve; Gamma-driver: s = 1). */
+   App. D, the slicing function g(alpha) (harmonic: 1; 1+log: 2/alpha), the shift
+   condition (frozen: beta, b, B do not evolve; Gamma-driver: s = 1) and the formulation
+   (Sec. 2): first order (all 58 variables evolve, with the red constraint-addition terms of
+   App. B) or second order (the 24 primaries evolve without the red terms; the auxiliaries
+   A, B, D, P are recomputed from the primaries after every update, ccz4_reconstruct_aux). */
+enum { CCZ4_FORMULATION_FIRST_ORDER = 0, CCZ4_FORMULATION_SECOND_ORDER = 1 };
 typedef struct {
     double kappa1, kappa2, kappa3, tau, e, c, mu, f, eta, ko_eps;
     int32_t slicing, shift;
+    int32_t formulation;
 } ccz4_params;
 
 /* Forest of n0[0] x n0[1] x n0[2] level-0 cubes over [origin, origin + extent], every cube
@@ -138,7 +143,9 @@ ccz4_status ccz4_plan_counts(const ccz4_ctx *ctx, int64_t *counts);
    the ghost slots receive G_L = -(r/|x_n|)(Q_L - Q_{L-1})/dx - (Q_L - Q_ini)/r.  Requires
    filled halos; never modifies Q.  Q and k must not alias.  precision: CCZ4_PREC_FP64, or
    CCZ4_PREC_MIXED (stencil differences in FP64, nonlinear algebra in FP32, the inverse
-   metric, det gt and every factor of 1/phi in FP64, result promoted to FP64). */
+   metric, det gt and every factor of 1/phi in FP64, result promoted to FP64).  In the
+   second-order formulation the red terms are off and the interior slots of A, B, D, P get 0
+   (the Sommerfeld ghost slots keep G_L for every slot). */
 ccz4_status ccz4_rhs(ccz4_ctx *ctx, const double *Q, double *k, int32_t precision, void *stream);
 
 /* RK4 stage.  Stage s (0..3) of classical RK4 in two-register form, on interior cells and
@@ -159,10 +166,23 @@ ccz4_status ccz4_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double *Qn
    lies within three layers of a face shared with a same-level leaf into that leaf's face halo
    of Qnext (what CCZ4_FILL_SAME_LEVEL would copy there afterwards), so that before the next
    stage only ccz4_fill_halos_kinds(NEUMANN | LEVELS) remains; Qnext's halos are then complete
-   once that runs.  EINVAL on unknown flags. */
+   once that runs.  EINVAL on unknown flags.  In the second-order formulation the interior
+   slots of A, B, D, P in acc and Qnext are not written: after the halo fill of Qnext, call
+   ccz4_reconstruct_aux on it (and fill again). */
 enum { CCZ4_STAGE_FILL_SAME_LEVEL = 1 };
 ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double *Qs, const double *Qn,
                                double *acc, double *Qnext, int32_t precision, int32_t flags, void *stream);
+
+/* Second-order formulation, explicit gradient reconstruction (Sec. 2 and Algorithm 2): on every
+   interior cell of every leaf, A_k = d_k alpha, B_k^i = d_k beta^i, D_kij = d_k gt_ij / 2 and
+   P_k = d_k phi (eq. auxiliary-variables) from the central FD4 difference of the primaries.
+   Q (device, a state of this context) is updated in place; the primaries' halos must be filled
+   (gt, alpha, beta, phi), and no primary is modified.  flags: 0, or CCZ4_STAGE_FILL_SAME_LEVEL:
+   the new values within three layers of a face shared with a same-level leaf are also written
+   into that leaf's face halo (then only ccz4_fill_halos_kinds(NEUMANN | LEVELS) remains for the
+   auxiliaries' halos).  Independent of the context's formulation setting.  EINVAL on a NULL
+   pointer or unknown flags. */
+ccz4_status ccz4_reconstruct_aux(ccz4_ctx *ctx, double *Q, int32_t flags, void *stream);
 
 /* Launch configuration of ccz4_rhs and ccz4_rhs_rk4_stage, per precision (CCZ4_PREC_FP64 or
    CCZ4_PREC_MIXED): CCZ4_KERNEL_PHASED or CCZ4_KERNEL_LDS, optionally with
@@ -188,7 +208,8 @@ ccz4_status ccz4_autotune(ccz4_ctx *ctx, const double *Q, double *acc, double *Q
 
 /* A fused RK4 step captured as a HIP graph: the four stages of ccz4_rhs_rk4_stage with
    CCZ4_STAGE_FILL_SAME_LEVEL, (Qn -> Q1), (Q1 -> Q2), (Q2 -> Q1), (Q1 -> Qn), each followed by
-   ccz4_fill_halos_kinds(NEUMANN | LEVELS) of its output, with the launch configuration current at
+   ccz4_fill_halos_kinds(NEUMANN | LEVELS) of its output (in the second-order formulation then
+   ccz4_reconstruct_aux with CCZ4_STAGE_FILL_SAME_LEVEL and the same fill again), with the launch configuration current at
    creation.  Buffers and dt are fixed at creation; Qn must enter each launch with all halos filled
    and leaves with them filled.  The graph uses the context's tables: destroy it before the
    context.  Launch is asynchronous on `stream`. */

@@ -16,6 +16,7 @@ NV = 59
 CCZ4_OK, CCZ4_EINVAL, CCZ4_ENOMEM, CCZ4_ELAYOUT, CCZ4_EHIP, CCZ4_ENONFINITE, CCZ4_ESTATE = range(7)
 BC_PERIODIC, BC_NEUMANN, BC_SOMMERFELD = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
+FORMULATION_FO, FORMULATION_SO = 0, 1
 KERNEL_PHASED, KERNEL_LDS, KERNEL_LINEAR_ORDER = 0, 1, 2
 FILL_SAME_LEVEL, FILL_NEUMANN, FILL_LEVELS, FILL_ALL = 1, 2, 4, 7
 STAGE_FILL_SAME_LEVEL = 1
@@ -35,6 +36,7 @@ class Params(ctypes.Structure):
         ("tau", ctypes.c_double), ("e", ctypes.c_double), ("c", ctypes.c_double),
         ("mu", ctypes.c_double), ("f", ctypes.c_double), ("eta", ctypes.c_double),
         ("ko_eps", ctypes.c_double), ("slicing", ctypes.c_int32), ("shift", ctypes.c_int32),
+        ("formulation", ctypes.c_int32),
     ]
 
 
@@ -47,9 +49,10 @@ class GridDesc(ctypes.Structure):
 
 def params(**kw):
     """Black-hole defaults of the paper (kappa1 = 0.1, kappa3 = 0.5, e = c = tau = 1, mu = 0.2,
-    f = 0.75), eta = 2, KO 0.1, 1+log slicing, Gamma-driver shift."""
+    f = 0.75), eta = 2, KO 0.1, 1+log slicing, Gamma-driver shift, first-order formulation
+    (formulation=FORMULATION_SO for the second-order one)."""
     d = dict(kappa1=0.1, kappa2=0.0, kappa3=0.5, tau=1.0, e=1.0, c=1.0, mu=0.2, f=0.75,
-             eta=2.0, ko_eps=0.1, slicing=1, shift=1)
+             eta=2.0, ko_eps=0.1, slicing=1, shift=1, formulation=0)
     d.update(kw)
     return Params(**d)
 
@@ -78,6 +81,7 @@ def lib():
             "ccz4_rhs": (i32, [P, P, P, i32, P]),
             "ccz4_rk4_stage": (i32, [P, i32, f64, P, P, P, P, P]),
             "ccz4_rhs_rk4_stage": (i32, [P, i32, f64, P, P, P, P, i32, i32, P]),
+            "ccz4_reconstruct_aux": (i32, [P, P, i32, P]),
             "ccz4_fill_halos_kinds": (i32, [P, P, i32, P]),
             "ccz4_plan_counts": (i32, [P, ctypes.POINTER(i64)]),
             "ccz4_constraints": (i32, [P, P, P, f64, P, P]),
@@ -207,6 +211,10 @@ def ccz4_rhs(h, Q, k, precision=PREC_FP64, stream=None):
 def ccz4_rk4_stage(h, s, dt, Qn, k, acc, Qnext, stream=None):
     return _check(lib().ccz4_rk4_stage(h, int(s), float(dt), _ptr(Qn), _ptr(k), _ptr(acc), _ptr(Qnext),
                                        _stream(stream)))
+
+
+def ccz4_reconstruct_aux(h, Q, flags=0, stream=None):
+    return _check(lib().ccz4_reconstruct_aux(h, _ptr(Q), int(flags), _stream(stream)))
 
 
 def ccz4_rhs_rk4_stage(h, s, dt, Qs, Qn, acc, Qnext, precision=PREC_FP64, flags=0, stream=None):
@@ -367,6 +375,16 @@ class Context:
     def rhs_rk4_stage(self, s, dt, Qs, Qn, acc, Qnext, precision=PREC_FP64, flags=0, stream=None):
         ccz4_rhs_rk4_stage(self.h, s, dt, Qs, Qn, acc, Qnext, precision, flags, stream)
 
+    def reconstruct(self, Q, push=True, stream=None):
+        """Second-order formulation: the auxiliaries A, B, D, P of every interior cell from FD4
+        differences of the primaries (whose halos must be filled); with push, also into the
+        same-level neighbours' face halos."""
+        ccz4_reconstruct_aux(self.h, Q, STAGE_FILL_SAME_LEVEL if push else 0, stream)
+
+    @property
+    def second_order(self):
+        return self.prm.formulation == FORMULATION_SO
+
     def fill_halos_kinds(self, Q, kinds, stream=None):
         ccz4_fill_halos_kinds(self.h, Q, kinds, stream)
 
@@ -431,9 +449,15 @@ class Context:
                 if s > 0:
                     self.fill_halos_kinds(src, rest, stream)
                 self.rhs_rk4_stage(s, dt, src, Qn, acc, dst, precision, STAGE_FILL_SAME_LEVEL, stream)
+                if self.second_order:  # Algorithm 2: the auxiliaries of the new state
+                    self.fill_halos_kinds(dst, rest, stream)
+                    self.reconstruct(dst, True, stream)
             else:
                 self.fill_halos(src, stream)
                 self.rhs_rk4_stage(s, dt, src, Qn, acc, dst, precision, 0, stream)
+                if self.second_order:
+                    self.fill_halos(dst, stream)
+                    self.reconstruct(dst, False, stream)
         if push:
             self.fill_halos_kinds(Qn, rest, stream)
 
@@ -446,6 +470,9 @@ class Context:
             self.rhs(cur, k, precision, stream)
             nxt = Qn if s == 3 else Qs
             self.rk4_stage(s, dt, Qn, k, acc, nxt, stream)
+            if self.second_order:  # Algorithm 2: the auxiliaries of the new state
+                self.fill_halos(nxt, stream)
+                self.reconstruct(nxt, False, stream)
             cur = nxt
 
 

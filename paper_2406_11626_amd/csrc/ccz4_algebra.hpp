@@ -20,6 +20,7 @@ namespace ccz4 {
 struct RhsParams {
     double kappa1, kappa2, kappa3, tau, e, c, mu, f, eta, ko_eps;
     int32_t slicing, shift;
+    int32_t formulation;  // 0: first order (red terms on), 1: second order (red terms off, aux RHS 0)
 };
 
 // derivative inputs: dq[a][v - 11] = d_a (slot v) for v = 11..57
@@ -434,7 +435,7 @@ __device__ void ccz4_algebra(const double *__restrict__ q, const double (*__rest
         for (int k = 0; k < 3; ++k) {
             const T igik = ig[sym(i, k)];
             t += T(2) * al * igik * dv(k, STHETA);
-            t += T(2) * al * igik * (trdAt[k] - T(2) * DA[k]);             // constraint additions
+            if (!p.formulation) t += T(2) * al * igik * (trdAt[k] - T(2) * DA[k]);  // constraint additions
             t += T(-4.0 / 3.0) * al * igik * dv(k, SK);
             t += sfac * T(1.0 / 3.0) * igik * sdBtr[k];
             t += T(-2) * igik * (Th * A[k] + T(2.0 / 3.0) * al * Kt * Zl[k]);

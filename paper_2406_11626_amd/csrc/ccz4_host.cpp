@@ -272,6 +272,7 @@ RhsParams to_rhs(const ccz4_params *p)
     r.ko_eps = p->ko_eps;
     r.slicing = p->slicing;
     r.shift = p->shift;
+    r.formulation = p->formulation;
     return r;
 }
 
@@ -280,6 +281,8 @@ ccz4_status check_params(const ccz4_params *p)
     if (!p) return fail(CCZ4_EINVAL, "params is NULL");
     if (p->slicing != 0 && p->slicing != 1) return fail(CCZ4_EINVAL, "slicing must be 0 or 1");
     if (p->shift != 0 && p->shift != 1) return fail(CCZ4_EINVAL, "shift must be 0 or 1");
+    if (p->formulation != CCZ4_FORMULATION_FIRST_ORDER && p->formulation != CCZ4_FORMULATION_SECOND_ORDER)
+        return fail(CCZ4_EINVAL, "formulation must be 0 (first order) or 1 (second order)");
     if (!(p->tau > 0)) return fail(CCZ4_EINVAL, "tau must be > 0");
     return CCZ4_OK;
 }
@@ -530,6 +533,17 @@ ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *c, int32_t s, double dt, const double *
     return CCZ4_OK;
 }
 
+ccz4_status ccz4_reconstruct_aux(ccz4_ctx *c, double *Q, int32_t flags, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    ccz4_status st = check_ptr(Q, "Q");
+    if (st) return st;
+    if (flags & ~CCZ4_STAGE_FILL_SAME_LEVEL) return fail(CCZ4_EINVAL, "unknown reconstruction flags");
+    HIP_TRY(launch_reconstruct(Q, c->d_geom.p, (int32_t)c->leaf.size(),
+                               (flags & CCZ4_STAGE_FILL_SAME_LEVEL) ? c->d_nbr.p : nullptr, S(stream)));
+    return CCZ4_OK;
+}
+
 ccz4_status ccz4_set_kernel(ccz4_ctx *c, int32_t precision, int32_t kernel)
 {
     if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
@@ -637,6 +651,13 @@ ccz4_status ccz4_step_graph_create(ccz4_ctx *c, double *Qn, double *Q1, double *
         if (e == hipSuccess) e = launch_fill(dst[s], c->d_phn.p, (int32_t)c->ph_neu.size(), cs);
         if (e == hipSuccess) e = launch_fill(dst[s], c->d_phr.p, (int32_t)c->ph_res.size(), cs);
         if (e == hipSuccess) e = launch_fill(dst[s], c->d_php.p, (int32_t)c->ph_pro.size(), cs);
+        if (c->prm.formulation == CCZ4_FORMULATION_SECOND_ORDER) {
+            // Algorithm 2: the auxiliaries of the new state from its primaries, then their halos
+            if (e == hipSuccess) e = launch_reconstruct(dst[s], c->d_geom.p, np, c->d_nbr.p, cs);
+            if (e == hipSuccess) e = launch_fill(dst[s], c->d_phn.p, (int32_t)c->ph_neu.size(), cs);
+            if (e == hipSuccess) e = launch_fill(dst[s], c->d_phr.p, (int32_t)c->ph_res.size(), cs);
+            if (e == hipSuccess) e = launch_fill(dst[s], c->d_php.p, (int32_t)c->ph_pro.size(), cs);
+        }
     }
     hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
     if (e == hipSuccess) e = e2;

@@ -316,6 +316,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WP
         cr.koc[a] = prm.ko_eps / (64.0 * g.dx[a]);
     }
     RhsSink snk;
+    snk.so = prm.formulation;
     rhs_cell_phased<T>(cr, prm, snk);
 }
 
@@ -327,6 +328,7 @@ struct StageSink {
     double *__restrict__ acc;
     double *__restrict__ qx;
     int s;
+    int so;  // second-order formulation: the auxiliaries are left alone (reconstructed afterwards)
     double dt;
     double carry[12];  // s = 3: gt_ij and At_ij of Q^{n+1}, projected in finish()
     int64_t pd[3];     // offsets (doubles, from this cell) of its copies in same-level neighbours'
@@ -343,6 +345,7 @@ struct StageSink {
 
     __device__ __forceinline__ void combine_at(int o, int v, double r)
     {
+        if (so && aux_slot(v)) return;
         const int e = v * CS + o;
         if (s == 0) {
             const double q0 = qn[e];
@@ -481,6 +484,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WP
     snk.acc = acc + (int64_t)p * PS;
     snk.qx = Qx + (int64_t)p * PS;
     snk.s = s;
+    snk.so = prm.formulation;
     snk.dt = dt;
     push_offsets(nbr, p, c % 9 + 3, (c / 9) % 9 + 3, c / 81 + 3, cr.o, snk.pd);
     rhs_cell_phased<T>(cr, prm, snk);
@@ -529,6 +533,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     LdsRhsSink snk;
     snk.kb = K + (int64_t)p * PS;
     snk.o = o;
+    snk.so = prm.formulation;
     rhs_slab_lds<T>(Q + (int64_t)p * PS, lds, sl, act, o, C, prm, snk);
 }
 
@@ -546,6 +551,7 @@ struct LdsStageSink {
         const int s = st->s;
 #pragma unroll
         for (int j = 0; j < N; ++j) {
+            if (st->so && aux_slot(slots[j])) continue;
             const int e = slots[j] * CS + o;
             a[j] = s < 3 ? st->qn[e] : 0.0;
             b[j] = s > 0 ? st->acc[e] : 0.0;
@@ -560,6 +566,7 @@ struct LdsStageSink {
 #pragma unroll
         for (int j = 0; j < N; ++j) {
             const int v = slots[j];
+            if (st->so && aux_slot(v)) continue;
             const int e = v * CS + o;
             if (s == 0) {
                 st->acc[e] = a[j] + (1.0 / 6.0) * dt * r[j];
@@ -603,6 +610,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     ss.acc = acc + (int64_t)p * PS;
     ss.qx = Qx + (int64_t)p * PS;
     ss.s = s;
+    ss.so = prm.formulation;
     ss.dt = dt;
     {
         const int cc = act ? (int)threadIdx.x : 242;
@@ -942,6 +950,61 @@ __global__ __launch_bounds__(256) void k_regrid(const double *__restrict__ Qo, d
         }
         dst[(int64_t)v * CS + boff(x + 3, y + 3, z + 3)] = s;
     }
+}
+
+// Second-order formulation (Sec. 2, explicit gradient reconstruction; Algorithm 2): the
+// auxiliaries from central FD4 differences of the primaries by their definitions,
+// A_k = d_k alpha, B_k^i = d_k beta^i, D_kij = d_k gt_ij / 2, P_k = d_k phi, on the interior
+// cells of every leaf.  One thread per cell, three work-groups per patch; the primaries'
+// halos must be filled.  With nbr, every value within three layers of a face shared with a
+// same-level leaf is also written into that leaf's face halo (as the stage push does).
+__global__ __launch_bounds__(256) void k_reconstruct(double *__restrict__ Q, const PatchGeom *__restrict__ geom,
+                                                     int32_t npatch, const int32_t *__restrict__ nbr)
+{
+    const int p = (int)(blockIdx.x / 3);
+    if (p >= npatch || threadIdx.x >= 243) return;
+    const int c = (int)(blockIdx.x % 3) * 243 + (int)threadIdx.x;
+    const int x = c % 9 + 3, y = (c / 9) % 9 + 3, z = c / 81 + 3;
+    double *qb = Q + (int64_t)p * PS;
+    const int o = boff(x, y, z);
+    const PatchGeom g = geom[p];
+    int64_t pd[3];
+    push_offsets(nbr, p, x, y, z, o, pd);
+    const int stride[3] = {1, YS, ZS};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double i12 = 1.0 / (12.0 * g.dx[a]);
+        const int h = stride[a];
+#pragma unroll
+        for (int v = 0; v <= SPHI; ++v) {
+            const double *f = qb + v * CS + o;
+            const double d = (8.0 * (f[h] - f[-h]) - (f[2 * h] - f[-2 * h])) * i12;
+            int dst;
+            double val = d;
+            if (v < SALPHA) {
+                dst = SD + 6 * a + v;
+                val = 0.5 * d;
+            } else if (v == SALPHA) {
+                dst = SA + a;
+            } else if (v < SPHI) {
+                dst = SB + 3 * a + (v - SBETA);
+            } else {
+                dst = SP + a;
+            }
+            const int64_t e = (int64_t)dst * CS + o;
+            qb[e] = val;
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (pd[b] != 0) qb[e + pd[b]] = val;
+        }
+    }
+}
+
+hipError_t launch_reconstruct(double *Q, const PatchGeom *geom, int32_t npatch, const int32_t *nbr, hipStream_t st)
+{
+    if (npatch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reconstruct, dim3((unsigned)npatch * 3u), dim3(256), 0, st, Q, geom, npatch, nbr);
+    return hipGetLastError();
 }
 
 hipError_t launch_regrid(const double *Qo, double *Qn, const RegridTask *tasks, int32_t n, hipStream_t st)

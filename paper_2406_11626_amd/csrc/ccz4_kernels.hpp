@@ -30,6 +30,7 @@ hipError_t launch_capture_bg(const double *Q, const BoundaryFace *bf, double *bg
 hipError_t launch_rk4(int32_t s, double dt, const double *Qn, const double *K, double *acc, double *Qx,
                       int32_t npatch, const BoundaryFace *bf, int32_t nbf, hipStream_t st);
 hipError_t launch_regrid(const double *Qo, double *Qn, const RegridTask *tasks, int32_t n, hipStream_t st);
+hipError_t launch_reconstruct(double *Q, const PatchGeom *geom, int32_t npatch, const int32_t *nbr, hipStream_t st);
 int64_t constraints_blocks(int32_t npatch);
 hipError_t launch_constraints(const double *Q, double *HM, const PatchGeom *geom, int32_t npatch,
                               double r_excise, double *part, double *out3, hipStream_t st);

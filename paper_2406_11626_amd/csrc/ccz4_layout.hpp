@@ -24,6 +24,9 @@ __host__ __device__ constexpr int sym(int i, int j)
 }
 constexpr int SG = 0, SALPHA = 6, SBETA = 7, SPHI = 10, SAT = 11, SK = 17, STHETA = 18,
               SGHAT = 19, SBB = 22, SA = 25, SB = 28, SD = 37, SP = 55, SK0 = 58;
+// the auxiliaries A, B, D, P (slots 25..57): evolved in the first-order formulation,
+// reconstructed from the primaries in the second-order one
+__host__ __device__ constexpr bool aux_slot(int v) { return v >= SA && v < SK0; }
 
 // box offset of cell (x, y, z) inside one slot of a patch
 __host__ __device__ constexpr int boff(int x, int y, int z) { return z * ZS + y * YS + x; }

@@ -138,6 +138,7 @@ __device__ __forceinline__ double adv(const LdsCell &c, int b, const double be[3
 struct LdsRhsSink {
     double *__restrict__ kb;
     int o;
+    int so;  // second-order formulation: the auxiliaries' right-hand sides are 0
     __device__ __forceinline__ void put(int v, double r) { kb[v * CS + o] = r; }
     __device__ __forceinline__ void finish() {}
     // A round's outputs in two halves (see flush below): the RHS alone reads nothing.
@@ -148,7 +149,7 @@ struct LdsRhsSink {
                                           const double (&)[N])
     {
 #pragma unroll
-        for (int j = 0; j < N; ++j) put(slots[j], r[j]);
+        for (int j = 0; j < N; ++j) put(slots[j], (so && aux_slot(slots[j])) ? 0.0 : r[j]);
     }
 };
 
@@ -265,6 +266,9 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
     const bool gdrv = p.shift != 0;
     const T sfac = gdrv ? T(1) : T(0);
     const T cc = cvt<T>(p.c);
+    // the red terms of the Ghat equation (2 alpha gt^ik d_k tr At, with d_k gt^nm = -2 D_k^nm)
+    // belong to the first-order formulation only
+    const T red = p.formulation ? T(0) : T(1);
 
     // carried between rounds
     T dtrA[3], sdBtr[3], GB[3], partD[3][6];
@@ -746,7 +750,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     const T igik = ig[sym(i, k)];
-                    t += T(2) * al * igik * (dTh[k] + dtrA[k]) - T(4.0 / 3.0) * al * igik * dK[k];
+                    t += T(2) * al * igik * (dTh[k] + red * dtrA[k]) - T(4.0 / 3.0) * al * igik * dK[k];
                     t += sfac * T(1.0 / 3.0) * igik * sdBtr[k];
                     t += T(-2) * igik * (Th * A[k] + T(2.0 / 3.0) * al * Kt * Zl[k] + al * kap1 * Zl[k]);
                     u += igik * Zl[k];

@@ -75,7 +75,11 @@ __device__ __forceinline__ double adv(const CellRef &c, int v, const double be[3
 // Output sinks: the plain right-hand side writes k = algebra + KO; the fused stage folds each
 // finished slot at once into the RK4 stage combine (see StageSink).
 struct RhsSink {
-    __device__ __forceinline__ void put(const CellRef &c, int v, double alg) { c.kb[v * CS + c.o] = alg + ko(c, v); }
+    int so;  // second-order formulation: the auxiliaries' right-hand sides are 0
+    __device__ __forceinline__ void put(const CellRef &c, int v, double alg)
+    {
+        c.kb[v * CS + c.o] = (so && aux_slot(v)) ? 0.0 : alg + ko(c, v);
+    }
     __device__ __forceinline__ void zero(const CellRef &c, int v) { c.kb[v * CS + c.o] = 0.0; }
     __device__ __forceinline__ void finish(const CellRef &) {}
 };
@@ -528,7 +532,7 @@ __device__ __forceinline__ void phase_gamma(Sink &snk, const CellRef &c, const R
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const T igik = ig[sym(i, k)];
-            t += T(2) * al * igik * (dTh[k] + dtrA[k]) - T(4.0 / 3.0) * al * igik * dK[k];
+            t += T(2) * al * igik * (dTh[k] + (p.formulation ? T(0) : dtrA[k])) - T(4.0 / 3.0) * al * igik * dK[k];
             t += sfac * T(1.0 / 3.0) * igik * sdBtr[k];
             t += T(-2) * igik * (Th * A[k] + T(2.0 / 3.0) * al * Kt * Zl[k] + al * kap1 * Zl[k]);
             u += igik * Zl[k];

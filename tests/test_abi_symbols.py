@@ -39,7 +39,8 @@ def test_argument_errors_without_gpu():
     for fn, args in (("ccz4_fill_halos", (None, None, None)), ("ccz4_rhs", (None, None, None, 0, None)),
                      ("ccz4_rk4_stage", (None, 0, 0.1, None, None, None, None, None)),
                      ("ccz4_constraints", (None, None, None, 0.0, None, None)),
-                     ("ccz4_set_kernel", (None, 0, 1)), ("ccz4_get_kernel", (None, 0, None))):
+                     ("ccz4_set_kernel", (None, 0, 1)), ("ccz4_get_kernel", (None, 0, None)),
+                     ("ccz4_reconstruct_aux", (None, None, 0, None))):
         assert getattr(L, fn)(*args) == ccz4.CCZ4_EINVAL
     g = ccz4.GridDesc()
     g.n0[:] = [0, 1, 1]
@@ -49,4 +50,7 @@ def test_argument_errors_without_gpu():
     g.n0[:] = [1, 1, 1]
     bad = ccz4.params(slicing=7)
     assert L.ccz4_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(bad)) == ccz4.CCZ4_EINVAL
+    bad = ccz4.params(formulation=2)
+    assert L.ccz4_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(bad)) == ccz4.CCZ4_EINVAL
+    assert b"formulation" in L.ccz4_last_error()
     ccz4.ccz4_destroy(None)

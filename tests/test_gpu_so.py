@@ -1,0 +1,184 @@
+"""GPU parity of the second-order formulation against the oracle: the right-hand side without
+the red terms (auxiliaries' right-hand sides zero), the FD4 reconstruction of A, B, D, P with
+and without the same-level halo push, and whole fused RK4 steps (Algorithm 2 with RK4) on the
+gauge wave, the puncture with Sommerfeld ghosts and a static AMR mesh, eager and as a graph.
+Same 1e-12 normwise measure per slot as the first-order parity tests."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle as orc  # noqa: E402
+from gpu_helpers import INTERIOR, SLABS, parity_error, to_gpu, to_host  # noqa: E402
+from paper_2406_11626_amd import ccz4, scenarios  # noqa: E402
+from seeded_inputs import box_centers, smooth_state  # noqa: E402
+
+KERNELS = [ccz4.KERNEL_PHASED, ccz4.KERNEL_LDS]
+AUX = slice(25, 58)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ccz4.lib()
+
+
+def so_params(w=None, **kw):
+    base = dict(w.prm) if w is not None else {}
+    base.update(kw)
+    base["formulation"] = ccz4.FORMULATION_SO
+    return ccz4.params(**base)
+
+
+def oparams(prm):
+    return orc.Params(**{f: getattr(prm, f) for f, _ in ccz4.Params._fields_})
+
+
+def make_pair(n0, origin, extent, bc, prm, refined=(), kernel=ccz4.KERNEL_LDS):
+    ctx = ccz4.Context(n0, origin, extent, bc, prm, refined)
+    for prec in (ccz4.PREC_FP64, ccz4.PREC_MIXED):
+        ctx.set_kernel(prec, kernel)
+    m = orc.Mesh(n0, origin, extent, bc, refined)
+    assert np.array_equal(ctx.ids, m.ids)
+    return ctx, m
+
+
+def random_state(m, seed, frozen=False):
+    Q = m.zeros()
+    for p in range(m.np):
+        Q[p] = smooth_state(box_centers(m.geom[p, :3], m.geom[p, 3:]), seed, frozen_shift=frozen)
+    return Q
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("shift", [1, 0])
+def test_so_rhs_parity_random_states(kernel, shift):
+    prm = so_params(slicing=shift, shift=shift, kappa1=0.3, kappa3=0.5 * shift)
+    ctx, m = make_pair((2, 2, 1), (-0.4, 0.1, 0.2), (1.6, 1.6, 0.8), ccz4.BC_PERIODIC, prm, kernel=kernel)
+    Qo = random_state(m, 40 + shift, frozen=shift == 0)
+    m.fill_halos(Qo)
+    Qd = to_gpu(Qo)
+    kd = ctx.new_state(1.0)
+    ctx.rhs(Qd, kd)
+    ko = m.rhs(oparams(prm), Qo)
+    g = to_host(kd)
+    e = parity_error(g, ko)
+    assert e.max() <= 1e-12, (e.argmax(), e.max())
+    assert np.all(g[:, 3:12, 3:12, 3:12, AUX] == 0.0)
+    # the first-order right-hand side of the same state differs in Ghat and b only among the
+    # primaries (the red terms)
+    ctx_fo = ccz4.Context((2, 2, 1), (-0.4, 0.1, 0.2), (1.6, 1.6, 0.8), ccz4.BC_PERIODIC,
+                          ccz4.params(**{f: getattr(prm, f) for f, _ in ccz4.Params._fields_ if f != "formulation"}))
+    ctx_fo.set_kernel(ccz4.PREC_FP64, kernel)
+    kf = ctx_fo.new_state(0.0)
+    ctx_fo.rhs(Qd, kf)
+    f = to_host(kf)[:, 3:12, 3:12, 3:12]
+    same = list(range(0, 19))
+    np.testing.assert_array_equal(f[..., same], g[:, 3:12, 3:12, 3:12][..., same])
+
+
+@pytest.mark.parametrize("push", [False, True])
+def test_reconstruct_parity_and_push(push):
+    """Interior auxiliaries against the oracle's reconstruction; primaries untouched; with push,
+    the auxiliaries' face halos on a periodic mesh (all faces same-level) equal those of the
+    oracle's fill after its reconstruction, bit for bit."""
+    prm = so_params()
+    ctx, m = make_pair((3, 2, 2), (-0.4, 0.1, 0.2), (2.4, 1.6, 1.6), ccz4.BC_PERIODIC, prm)
+    Qo = random_state(m, 51)
+    m.fill_halos(Qo)
+    Qd = to_gpu(Qo)
+    ctx.reconstruct(Qd, push=push)
+    Ro = Qo.copy()
+    m.reconstruct(Ro)
+    g = to_host(Qd)
+    e = parity_error(g, Ro)
+    assert e.max() <= 1e-12, (e.argmax(), e.max())
+    np.testing.assert_array_equal(g[..., :25], Qo[..., :25])
+    np.testing.assert_array_equal(g[..., 58], Qo[..., 58])
+    if push:
+        # the pushed halo values are copies of the neighbours' new interior values: a plain
+        # same-level fill of the result changes nothing
+        Hd = to_gpu(g)
+        ctx.fill_halos(Hd)
+        H = to_host(Hd)
+        np.testing.assert_array_equal(np.where(SLABS[..., None], g, 0.0), np.where(SLABS[..., None], H, 0.0))
+        assert not np.array_equal(np.where(SLABS[..., None], g, 0.0)[..., AUX],
+                                  np.where(SLABS[..., None], Qo, 0.0)[..., AUX])
+    else:
+        # no halo is written
+        np.testing.assert_array_equal(np.where(SLABS[..., None], g, 0.0), np.where(SLABS[..., None], Qo, 0.0))
+
+
+def _so_steps(w, n0, prm, refined=(), steps=2, perturb=False, kernel=ccz4.KERNEL_LDS, push=True, graph=False):
+    ctx, m = make_pair(n0, w.origin, w.extent, w.bc, prm, refined, kernel=kernel)
+    Qo = m.zeros()
+    m.init(Qo, w.scenario, w.scen)
+    if perturb:
+        for p in range(m.np):
+            Qo[p, 3:12, 3:12, 3:12] += 1e-3 * smooth_state(box_centers(m.geom[p, :3], m.geom[p, 3:]), 52)[3:12, 3:12, 3:12]
+    m.set_background(Qo)
+    m.fill_halos(Qo)
+    m.reconstruct(Qo)
+    m.fill_halos(Qo)
+    Qd = to_gpu(Qo)
+    ctx.set_background(to_gpu(Qo))
+    bufs = (ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0))
+    pr = oparams(prm)
+    dt = w.dt()
+    sg = ccz4.StepGraph(ctx, Qd, bufs, dt) if graph else None
+    for _ in range(steps):
+        if sg is not None:
+            sg.launch()
+        else:
+            ctx.rk4_step_fused(Qd, dt, bufs, push=push)
+        Qo = m.rk4_step(pr, Qo, dt)
+    torch.cuda.synchronize()
+    if sg is not None:
+        sg.close()
+    return ctx, m, to_host(Qd), Qo
+
+
+@pytest.mark.parametrize("push", [True, False])
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_so_fused_steps_gauge_wave_match_oracle(kernel, push):
+    w = scenarios.config(1)
+    _, _, g, Qo = _so_steps(w, w.n0, so_params(w), steps=6, kernel=kernel, push=push)
+    e = parity_error(g, Qo)
+    assert e.max() <= 1e-11, (e.argmax(), e.max())
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_so_fused_steps_puncture_sommerfeld_match_oracle(kernel):
+    w = scenarios.config(2)
+    _, m, g, Qo = _so_steps(w, (2, 2, 2), so_params(w), steps=2, perturb=True, kernel=kernel)
+    e = parity_error(g, Qo)
+    assert e.max() <= 1e-11, (e.argmax(), e.max())
+
+
+def test_so_fused_steps_static_amr_match_oracle():
+    """Coarse-fine faces: the reconstruction's auxiliaries reach fine and coarse halos through
+    restriction and prolongation after each stage."""
+    w = scenarios.config(2)
+    refined = [(0, 1, 1, 1)]
+    _, m, g, Qo = _so_steps(w, (3, 3, 3), so_params(w), refined=refined, steps=2, perturb=True)
+    e = parity_error(g, Qo)
+    assert e.max() <= 1e-11, (e.argmax(), e.max())
+
+
+def test_so_step_graph_matches_oracle():
+    w = scenarios.config(2)
+    _, _, g, Qo = _so_steps(w, (2, 2, 2), so_params(w), steps=2, perturb=True, graph=True)
+    e = parity_error(g, Qo)
+    assert e.max() <= 1e-11, (e.argmax(), e.max())
+
+
+def test_reconstruct_rejects_bad_arguments():
+    ctx = ccz4.Context((1, 1, 1), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), ccz4.BC_PERIODIC, so_params())
+    Q = ctx.new_state(0.0)
+    with pytest.raises(ccz4.CCZ4Error):
+        ccz4.ccz4_reconstruct_aux(ctx.h, Q, 2)
+    with pytest.raises(ccz4.CCZ4Error):
+        ccz4.ccz4_reconstruct_aux(ctx.h, None, 0)
