@@ -99,10 +99,12 @@ def copy_bandwidth(nbytes=2**30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def run_gpu(args, w, precision):
+def run_gpu(args, w, precision, formulation=0):
     import torch
     from paper_2406_11626_amd import ccz4
-    ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, w.params(), w.refined)
+    prm = ccz4.params(**{**w.prm, "formulation": formulation})
+    ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, prm, w.refined)
+    so = ctx.second_order
     Q = ctx.new_state(0.0)
     ctx.init_patches(Q, w.scenario, w.scen)
     Q1, Q2, acc = ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0)
@@ -110,8 +112,11 @@ def run_gpu(args, w, precision):
     stream = torch.cuda.current_stream()
     order = ((Q, Q1), (Q1, Q2), (Q2, Q1), (Q1, Q))
     rest = ccz4.FILL_NEUMANN | ccz4.FILL_LEVELS
-    events = []
+    events, recon_events = [], []
     ctx.fill_halos(Q, stream)
+    if so:  # the auxiliaries of the initial data from its primaries
+        ctx.reconstruct(Q, True, stream)
+        ctx.fill_halos(Q, stream)
     tune_ms = ctx.autotune(Q, precision, reps=2) if args.autotune else None
     ctx.fill_halos(Q, stream)
 
@@ -127,6 +132,16 @@ def run_gpu(args, w, precision):
             if timed:
                 e1.record(stream)
                 events.append((s, e0, e1))
+            if so:
+                ctx.fill_halos_kinds(dst, rest, stream)
+                if timed:
+                    r0 = torch.cuda.Event(enable_timing=True)
+                    r1 = torch.cuda.Event(enable_timing=True)
+                    r0.record(stream)
+                ctx.reconstruct(dst, True, stream)
+                if timed:
+                    r1.record(stream)
+                    recon_events.append((r0, r1))
         ctx.fill_halos_kinds(Q, rest, stream)
 
     for _ in range(args.warmup):
@@ -161,7 +176,9 @@ def run_gpu(args, w, precision):
     kname = ("k_stage_lds" if kc & ccz4.KERNEL_LDS else "k_stage") + \
         ("<double>" if precision == ccz4.PREC_FP64 else "<float>") + \
         (" (plain block order)" if kc & ccz4.KERNEL_LINEAR_ORDER else "")
+    recon_ms = [a.elapsed_time(b) for a, b in recon_events]
     out = dict(wall=wall, wall_eager=wall_eager, tune_ms=tune_ms, cells=cells, patches=ctx.n_patches,
+               reconstruct_ms=sum(recon_ms) / len(recon_ms) if recon_ms else None,
                stage_ms=sum(stage_ms) / len(stage_ms),
                stage_bytes=sum(launch_bytes) / len(launch_bytes),
                stage_gbs=sum(launch_bytes) / (sum(stage_ms) * 1e-3) / 1e9, norms=norms, status=st,
@@ -169,6 +186,51 @@ def run_gpu(args, w, precision):
     del Q, Q1, Q2, acc
     ctx.close()
     torch.cuda.empty_cache()
+    return out
+
+
+def run_stability(args, w):
+    """First- against second-order formulation on the same workload, graph-launched steps until
+    t_end or the first non-finite value: L2 norms of the constraints (cells with r >= 1)
+    every `every` steps."""
+    import torch
+    from paper_2406_11626_amd import ccz4
+    dt = w.dt()
+    nsteps = int(round(args.t_end / dt))
+    every = max(1, int(round(args.sample_dt / dt)))
+    out = {}
+    for form, name in ((0, "first_order"), (1, "second_order")):
+        prm = ccz4.params(**{**w.prm, "formulation": form})
+        ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, prm, w.refined)
+        Q = ctx.new_state(0.0)
+        ctx.init_patches(Q, w.scenario, w.scen)
+        ctx.fill_halos(Q)
+        if form:
+            ctx.reconstruct(Q)
+            ctx.fill_halos(Q)
+        bufs = (ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0))
+        graph = ctx.step_graph(Q, bufs, dt)
+        hist = []
+        n0, _ = ctx.constraints(Q, r_excise=1.0)
+        hist.append((0.0, n0[0], n0[1], n0[2]))
+        t0 = time.perf_counter()
+        for i in range(1, nsteps + 1):
+            graph.launch()
+            if i % every == 0 or i == nsteps:
+                norms, _ = ctx.constraints(Q, r_excise=1.0)
+                hist.append((i * dt, norms[0], norms[1], norms[2]))
+                print(f"# {name} t = {i * dt:.3f}: L2(H) = {norms[0]:.3e}, L2(M) = {norms[1]:.3e}, "
+                      f"non-finite = {norms[2]:.0f}", file=sys.stderr, flush=True)
+                if norms[2] > 0 or not all(map(lambda v: v == v, norms[:2])):
+                    break
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        graph.close()
+        out[name] = dict(history=[dict(t=t, L2_H=h, L2_M=m, nonfinite=nf) for t, h, m, nf in hist],
+                         t_reached=hist[-1][0], finite=hist[-1][3] == 0, wall_s=wall)
+        del Q, bufs
+        ctx.close()
+        torch.cuda.empty_cache()
     return out
 
 
@@ -254,6 +316,12 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision run")
+    ap.add_argument("--no-so", action="store_true", help="skip the second-order-formulation run")
+    ap.add_argument("--stability", action="store_true",
+                    help="instead of timing: evolve the workload in both formulations up to --t-end and "
+                         "print the constraint norms")
+    ap.add_argument("--t-end", type=float, default=10.0)
+    ap.add_argument("--sample-dt", type=float, default=0.5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference kernel for the HBM byte counters)")
@@ -268,6 +336,10 @@ def main():
     from paper_2406_11626_amd import scenarios
     assert torch.cuda.is_available(), "no GPU"
     w = scenarios.config(args.config)
+    if args.stability:
+        r = run_stability(args, w)
+        print(json.dumps({"workload": w.name, "dt": w.dt(), "t_end": args.t_end, "r_excise": 1.0, **r}), flush=True)
+        return
     if args.config == 5:
         r = run_dynamic(args, w)
         print(json.dumps({
@@ -324,6 +396,13 @@ def main():
         vm = rm["cells"] * stages / rm["wall"]
         line["mixed"] = {"value": vm, "stage_avg_ms": rm["stage_ms"], "speedup_vs_fp64": vm / value,
                          "L2_H": rm["norms"][0], "L2_M": rm["norms"][1]}
+    if not args.no_so:
+        rs = run_gpu(args, w, 0, formulation=1)
+        vs = rs["cells"] * stages / rs["wall"]
+        line["second_order"] = {"value": vs, "ms_per_step": rs["wall"] * 1e3 / args.steps,
+                                "stage_avg_ms": rs["stage_ms"], "reconstruct_avg_ms": rs["reconstruct_ms"],
+                                "speedup_vs_first_order": vs / value,
+                                "L2_H": rs["norms"][0], "L2_M": rs["norms"][1]}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(line), flush=True)

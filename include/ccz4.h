@@ -59,7 +59,7 @@ enum { CCZ4_SCEN_GAUGE_WAVE = 0, CCZ4_SCEN_PUNCTURE = 1, CCZ4_SCEN_BL_BY = 2 };
 /* Parameters of App. B (kappa1..3, tau, e, c, mu, f, eta), the KO strength epsilon of
    App. D, the slicing function g(alpha) (harmonic: 1; 1+log: 2/alpha), the shift
    condition (frozen: beta, b, B do not evolve; Gamma-driver: s = 1) and the formulation
-   (Sec. 2): first order (all 58 variables evolve, with the red constraint-addition terms of
+   (Sec. 2.4): first order (all 58 variables evolve, with the red constraint-addition terms of
    App. B) or second order (the 24 primaries evolve without the red terms; the auxiliaries
    A, B, D, P are recomputed from the primaries after every update, ccz4_reconstruct_aux). */
 enum { CCZ4_FORMULATION_FIRST_ORDER = 0, CCZ4_FORMULATION_SECOND_ORDER = 1 };
@@ -173,7 +173,7 @@ enum { CCZ4_STAGE_FILL_SAME_LEVEL = 1 };
 ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double *Qs, const double *Qn,
                                double *acc, double *Qnext, int32_t precision, int32_t flags, void *stream);
 
-/* Second-order formulation, explicit gradient reconstruction (Sec. 2 and Algorithm 2): on every
+/* Second-order formulation, explicit gradient reconstruction (Sec. 3.2 and Algorithm 2): on every
    interior cell of every leaf, A_k = d_k alpha, B_k^i = d_k beta^i, D_kij = d_k gt_ij / 2 and
    P_k = d_k phi (eq. auxiliary-variables) from the central FD4 difference of the primaries.
    Q (device, a state of this context) is updated in place; the primaries' halos must be filled

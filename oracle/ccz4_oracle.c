@@ -708,7 +708,7 @@ void orc_rhs(const orc_mesh *m, const orc_params *pr, const double *Q, double *k
 }
 
 /* ----------------------------------------------------------------------------------------
- * Second-order formulation (Sec. 2, "explicit gradient reconstruction", and Algorithm 2):
+ * Second-order formulation (Sec. 2.4; Sec. 3.2, explicit gradient reconstruction; Algorithm 2):
  * after each update the auxiliaries are recomputed from the primaries with the central FD4
  * difference, by their definitions A_i = d_i alpha, B_k^i = d_k beta^i,
  * D_kij = d_k gt_ij / 2, P_i = d_i phi (eq. auxiliary-variables).  Interior cells of every

@@ -952,7 +952,7 @@ __global__ __launch_bounds__(256) void k_regrid(const double *__restrict__ Qo, d
     }
 }
 
-// Second-order formulation (Sec. 2, explicit gradient reconstruction; Algorithm 2): the
+// Second-order formulation (Sec. 3.2, explicit gradient reconstruction; Algorithm 2): the
 // auxiliaries from central FD4 differences of the primaries by their definitions,
 // A_k = d_k alpha, B_k^i = d_k beta^i, D_kij = d_k gt_ij / 2, P_k = d_k phi, on the interior
 // cells of every leaf.  One thread per cell, three work-groups per patch; the primaries'
@@ -971,6 +971,9 @@ __global__ __launch_bounds__(256) void k_reconstruct(double *__restrict__ Q, con
     int64_t pd[3];
     push_offsets(nbr, p, x, y, z, o, pd);
     const int stride[3] = {1, YS, ZS};
+    // every difference first, then every store: the stores go through the same pointer as the
+    // loads, so the compiler would not move a later load above an earlier store
+    double val[3][SPHI + 1];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double i12 = 1.0 / (12.0 * g.dx[a]);
@@ -978,26 +981,25 @@ __global__ __launch_bounds__(256) void k_reconstruct(double *__restrict__ Q, con
 #pragma unroll
         for (int v = 0; v <= SPHI; ++v) {
             const double *f = qb + v * CS + o;
-            const double d = (8.0 * (f[h] - f[-h]) - (f[2 * h] - f[-2 * h])) * i12;
-            int dst;
-            double val = d;
-            if (v < SALPHA) {
-                dst = SD + 6 * a + v;
-                val = 0.5 * d;
-            } else if (v == SALPHA) {
-                dst = SA + a;
-            } else if (v < SPHI) {
-                dst = SB + 3 * a + (v - SBETA);
-            } else {
-                dst = SP + a;
-            }
-            const int64_t e = (int64_t)dst * CS + o;
-            qb[e] = val;
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-                if (pd[b] != 0) qb[e + pd[b]] = val;
+            val[a][v] = (8.0 * (f[h] - f[-h]) - (f[2 * h] - f[-2 * h])) * i12;
         }
     }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int v = 0; v <= SPHI; ++v) {
+            // D_a(ij) = d_a gt_ij / 2, A_a = d_a alpha, B_a^i = d_a beta^i, P_a = d_a phi
+            const int dst = v < SALPHA ? SD + 6 * a + v
+                          : v == SALPHA ? SA + a
+                          : v < SPHI ? SB + 3 * a + (v - SBETA)
+                                     : SP + a;
+            const double u = v < SALPHA ? 0.5 * val[a][v] : val[a][v];
+            const int64_t e = (int64_t)dst * CS + o;
+            qb[e] = u;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (pd[k] != 0) qb[e + pd[k]] = u;
+        }
 }
 
 hipError_t launch_reconstruct(double *Q, const PatchGeom *geom, int32_t npatch, const int32_t *nbr, hipStream_t st)
