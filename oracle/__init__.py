@@ -42,13 +42,13 @@ class Params(ctypes.Structure):
         ("tau", ctypes.c_double), ("e", ctypes.c_double), ("c", ctypes.c_double),
         ("mu", ctypes.c_double), ("f", ctypes.c_double), ("eta", ctypes.c_double),
         ("ko_eps", ctypes.c_double), ("slicing", ctypes.c_int), ("shift", ctypes.c_int),
-        ("formulation", ctypes.c_int),
+        ("formulation", ctypes.c_int), ("advection", ctypes.c_int),
     ]
 
 
 def params(**kw):
     d = dict(kappa1=0.1, kappa2=0.0, kappa3=0.5, tau=1.0, e=1.0, c=1.0, mu=0.2, f=0.75,
-             eta=2.0, ko_eps=0.1, slicing=1, shift=1, formulation=0)
+             eta=2.0, ko_eps=0.1, slicing=1, shift=1, formulation=0, advection=0)
     d.update(kw)
     return Params(**d)
 
@@ -65,6 +65,7 @@ _rhs_point = _sig("orc_rhs_point", None, [_PP, _dp, _dp, _dp])
 _cons_point = _sig("orc_constraints_point", None, [_dp, _dp, _dp])
 _fd4 = _sig("orc_fd4", ctypes.c_double, [_dp, ctypes.c_double])
 _ko = _sig("orc_ko", ctypes.c_double, [_dp, ctypes.c_double, ctypes.c_double])
+_fd4_lop = _sig("orc_fd4_lop", ctypes.c_double, [_dp, ctypes.c_double, ctypes.c_int])
 _rhs_box = _sig("orc_rhs_box", None, [_PP, _dp, _dp, _dp])
 _cons_box = _sig("orc_constraints_box", None, [_dp, _dp, _dp])
 _mesh_create = _sig("orc_mesh_create", ctypes.c_void_p,
@@ -166,6 +167,10 @@ def fd4(v5, dx):
 
 def ko(v7, dx, eps):
     return _ko(_c(v7), dx, eps)
+
+
+def fd4_lop(v7, dx, right):
+    return _fd4_lop(_c(v7), dx, int(right))
 
 
 def rhs_box(pr, dx, box):

@@ -34,6 +34,12 @@ double orc_ko(const double *v, double dx, double eps)
            (v[0] - 6.0 * v[1] + 15.0 * v[2] - 20.0 * v[3] + 15.0 * v[4] - 6.0 * v[5] + v[6]);
 }
 
+double orc_fd4_lop(const double *v, double dx, int right)
+{
+    if (right) return (-3.0 * v[2] - 10.0 * v[3] + 18.0 * v[4] - 6.0 * v[5] + v[6]) / (12.0 * dx);
+    return (-v[0] + 6.0 * v[1] - 18.0 * v[2] + 10.0 * v[3] + 3.0 * v[4]) / (12.0 * dx);
+}
+
 static int frozen_slot(const orc_params *pr, int v)
 {
     /* beta^i (7-9), b^i (22-24), B_k^i (28-36) do not evolve with the static shift */
@@ -66,6 +72,24 @@ void orc_rhs_box(const orc_params *pr, const double dx[3], const double *box, do
                     }
                 }
                 orc_rhs_point(pr, q, dq, r);
+                /* Lopsided advection (App. D): in every equation of a differentiated slot the
+                   advection term is +beta^k d_k Q_v with the slot's own derivative (App. B; in the
+                   b equation the two Ghat advection terms cancel).  The algebra above used the
+                   central difference there; replace it by the lopsided one along each axis. */
+                if (pr->advection)
+                    for (v = 11; v <= 57; v++) {
+                        if (frozen_slot(pr, v) || (pr->formulation && v >= 25)) continue;
+                        for (a = 0; a < 3; a++) {
+                            const double be = q[7 + a];
+                            const int right = pr->advection == 1 ? be > 0.0 : !(be > 0.0);
+                            for (s = -3; s <= 3; s++) {
+                                int xx = x + (a == 0 ? s : 0), yy = y + (a == 1 ? s : 0),
+                                    zz = z + (a == 2 ? s : 0);
+                                w[s + 3] = box[cix(xx, yy, zz) * NV + v];
+                            }
+                            r[v] += be * (orc_fd4_lop(w, dx[a], right) - dq[a * NV + v]);
+                        }
+                    }
                 for (v = 0; v < 58; v++) {
                     double ko = 0;
                     if (frozen_slot(pr, v)) continue;

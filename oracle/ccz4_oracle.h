@@ -44,6 +44,10 @@ typedef struct {
     int formulation;               /* 0: first order (FO, all 58 evolve, red terms on);
                                       1: second order (SO, the 24 primaries evolve, red terms
                                       off, A, B, D, P reconstructed after every update) */
+    int advection;                 /* derivative of the advection terms beta^k d_k Q (App. D):
+                                      0: central FD4; 1: lopsided FD4, the stencil biased towards
+                                      +x_k where beta^k > 0 (upwind reading); 2: lopsided FD4 with
+                                      the pairing as printed (biased towards -x_k where beta^k > 0) */
 } orc_params;
 
 /* ---- pointwise algebra (App. B) ---- */
@@ -54,6 +58,9 @@ void orc_constraints_point(const double *q, const double *dq /* [3][59] */, doub
 /* ---- one-dimensional stencils (App. D) ---- */
 double orc_fd4(const double *v5 /* Q--,Q-,Q,Q+,Q++ */, double dx);
 double orc_ko(const double *v7 /* Q---..Q+++ */, double dx, double eps);
+/* the lopsided fourth-order first derivatives of App. D on Q---..Q+++: right = 1 uses
+   Q-..Q+++, right = 0 uses Q---..Q+ */
+double orc_fd4_lop(const double *v7, double dx, int right);
 
 /* ---- one patch box with filled halos ---- */
 void orc_rhs_box(const orc_params *pr, const double dx[3], const double *box, double *out);
