@@ -99,10 +99,10 @@ def copy_bandwidth(nbytes=2**30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def run_gpu(args, w, precision, formulation=0):
+def run_gpu(args, w, precision, formulation=0, advection=0):
     import torch
     from paper_2406_11626_amd import ccz4
-    prm = ccz4.params(**{**w.prm, "formulation": formulation})
+    prm = ccz4.params(**{**w.prm, "formulation": formulation, "advection": advection})
     ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, prm, w.refined)
     so = ctx.second_order
     Q = ctx.new_state(0.0)
@@ -317,6 +317,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision run")
     ap.add_argument("--no-so", action="store_true", help="skip the second-order-formulation run")
+    ap.add_argument("--no-lopsided", action="store_true", help="skip the lopsided-advection run")
     ap.add_argument("--stability", action="store_true",
                     help="instead of timing: evolve the workload in both formulations up to --t-end and "
                          "print the constraint norms")
@@ -403,6 +404,12 @@ def main():
                                 "stage_avg_ms": rs["stage_ms"], "reconstruct_avg_ms": rs["reconstruct_ms"],
                                 "speedup_vs_first_order": vs / value,
                                 "L2_H": rs["norms"][0], "L2_M": rs["norms"][1]}
+    if not args.no_lopsided:
+        rl = run_gpu(args, w, 0, advection=1)
+        vl = rl["cells"] * stages / rl["wall"]
+        line["lopsided_advection"] = {"value": vl, "ms_per_step": rl["wall"] * 1e3 / args.steps,
+                                      "stage_avg_ms": rl["stage_ms"], "speedup_vs_central": vl / value,
+                                      "L2_H": rl["norms"][0], "L2_M": rl["norms"][1]}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -61,12 +61,18 @@ enum { CCZ4_SCEN_GAUGE_WAVE = 0, CCZ4_SCEN_PUNCTURE = 1, CCZ4_SCEN_BL_BY = 2 };
    condition (frozen: beta, b, B do not evolve; Gamma-driver: s = 1) and the formulation
    (Sec. 2.4): first order (all 58 variables evolve, with the red constraint-addition terms of
    App. B) or second order (the 24 primaries evolve without the red terms; the auxiliaries
-   A, B, D, P are recomputed from the primaries after every update, ccz4_reconstruct_aux). */
+   A, B, D, P are recomputed from the primaries after every update, ccz4_reconstruct_aux), and
+   the derivative taken in the advection terms beta^k d_k Q (App. D): the central FD4 difference,
+   or one of the two lopsided fourth-order stencils chosen per axis by the sign of beta^k, either
+   biased towards +x_k where beta^k > 0 (the upwind reading of d_t Q = beta^k d_k Q + ...) or with
+   the pairing as printed (biased towards -x_k where beta^k > 0). */
 enum { CCZ4_FORMULATION_FIRST_ORDER = 0, CCZ4_FORMULATION_SECOND_ORDER = 1 };
+enum { CCZ4_ADVECTION_CENTRAL = 0, CCZ4_ADVECTION_LOPSIDED_UPWIND = 1, CCZ4_ADVECTION_LOPSIDED_PRINTED = 2 };
 typedef struct {
     double kappa1, kappa2, kappa3, tau, e, c, mu, f, eta, ko_eps;
     int32_t slicing, shift;
     int32_t formulation;
+    int32_t advection;
 } ccz4_params;
 
 /* Forest of n0[0] x n0[1] x n0[2] level-0 cubes over [origin, origin + extent], every cube

@@ -21,7 +21,25 @@ struct RhsParams {
     double kappa1, kappa2, kappa3, tau, e, c, mu, f, eta, ko_eps;
     int32_t slicing, shift;
     int32_t formulation;  // 0: first order (red terms on), 1: second order (red terms off, aux RHS 0)
+    int32_t advection;    // 0: central FD4 advection; 1: lopsided, biased towards +x_k where beta^k > 0;
+                          // 2: lopsided with the pairing as printed (towards -x_k where beta^k > 0)
 };
+
+// The lopsided fourth-order first derivatives of App. D, biased towards +x (points -1..+3) or
+// towards -x (points -3..+1), written as the central difference cen plus a fifth difference:
+//   right = cen + (-Q-- + 5Q- - 10Q + 10Q+ - 5Q++ + Q+++) / (12 dx),
+//   left  = cen + (-Q--- + 5Q-- - 10Q- + 10Q - 5Q+ + Q++) / (12 dx),
+// the second being the first mirrored; selecting the operands rather than the two results keeps
+// one expression per lane (i12 = 1 / (12 dx)).
+__device__ __forceinline__ double lop_from_central(double cen, bool right, double m3, double m2, double m1, double c0,
+                                                   double p1, double p2, double p3, double i12)
+{
+    const double u3 = right ? p3 : -m3, u2 = right ? p2 : -m2, u1 = right ? p1 : -m1, u0 = right ? c0 : -c0;
+    const double w1 = right ? m1 : -p1, w2 = right ? m2 : -p2;
+    return cen + (u3 - 5.0 * u2 + 10.0 * u1 - 10.0 * u0 + 5.0 * w1 - w2) * i12;
+}
+// which of the two the advection term takes along an axis with shift component be
+__device__ __forceinline__ bool lop_use_right(int32_t mode, double be) { return mode == 1 ? be > 0.0 : !(be > 0.0); }
 
 // derivative inputs: dq[a][v - 11] = d_a (slot v) for v = 11..57
 constexpr int NDIFF = 47;

@@ -273,6 +273,7 @@ RhsParams to_rhs(const ccz4_params *p)
     r.slicing = p->slicing;
     r.shift = p->shift;
     r.formulation = p->formulation;
+    r.advection = p->advection;
     return r;
 }
 
@@ -283,6 +284,8 @@ ccz4_status check_params(const ccz4_params *p)
     if (p->shift != 0 && p->shift != 1) return fail(CCZ4_EINVAL, "shift must be 0 or 1");
     if (p->formulation != CCZ4_FORMULATION_FIRST_ORDER && p->formulation != CCZ4_FORMULATION_SECOND_ORDER)
         return fail(CCZ4_EINVAL, "formulation must be 0 (first order) or 1 (second order)");
+    if (p->advection < CCZ4_ADVECTION_CENTRAL || p->advection > CCZ4_ADVECTION_LOPSIDED_PRINTED)
+        return fail(CCZ4_EINVAL, "advection must be 0 (central), 1 (lopsided, upwind) or 2 (lopsided, as printed)");
     if (!(p->tau > 0)) return fail(CCZ4_EINVAL, "tau must be > 0");
     return CCZ4_OK;
 }

@@ -296,7 +296,7 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk)
 #define CCZ4_RHS_WPE 1
 #endif
 
-template <typename T>
+template <typename T, int LOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WPE))) void k_rhs(const double *__restrict__ Q, double *__restrict__ K,
                                              const PatchGeom *__restrict__ geom, int32_t npatch,
                                              RhsParams prm, int32_t linear)
@@ -315,7 +315,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WP
         cr.i12[a] = 1.0 / (12.0 * g.dx[a]);
         cr.koc[a] = prm.ko_eps / (64.0 * g.dx[a]);
     }
-    RhsSink snk;
+    cr.adv = prm.advection;
+    RhsSink<LOP> snk;
     snk.so = prm.formulation;
     rhs_cell_phased<T>(cr, prm, snk);
 }
@@ -323,7 +324,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WP
 // Fused stage: the right-hand side of Qs folded slot by slot into stage s of RK4 (two-register
 // form) on the interior cells, with the projection of Q^{n+1} at s = 3.  Qs is read through the
 // stencils, Qn and acc pointwise; Qnext must differ from Qs (other cells still read Qs).
+template <int L>
 struct StageSink {
+    static constexpr int LOP = L;  // lopsided advection stencils in the phase functions
     const double *__restrict__ qn;
     double *__restrict__ acc;
     double *__restrict__ qx;
@@ -454,7 +457,7 @@ __device__ __forceinline__ void stage_ghost_face(int fi, int idx, int32_t s, dou
 }
 
 
-template <typename T>
+template <typename T, int LOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WPE))) void k_stage(
     const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
     const PatchGeom *__restrict__ geom, int32_t npatch, int32_t nb_slab, RhsParams prm, int32_t s, double dt,
@@ -479,7 +482,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WP
         cr.i12[a] = 1.0 / (12.0 * g.dx[a]);
         cr.koc[a] = prm.ko_eps / (64.0 * g.dx[a]);
     }
-    StageSink snk;
+    cr.adv = prm.advection;
+    StageSink<LOP> snk;
     snk.qn = Qn + (int64_t)p * PS;
     snk.acc = acc + (int64_t)p * PS;
     snk.qx = Qx + (int64_t)p * PS;
@@ -515,7 +519,7 @@ __device__ __forceinline__ void lds_cell_setup(double *lds, int sl, const PatchG
     o = boff(x, y, zl + 3 + 3 * sl);
 }
 
-template <typename T>
+template <typename T, int LOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rhs_lds(
     const double *__restrict__ Q, double *__restrict__ K, const PatchGeom *__restrict__ geom, int32_t npatch,
     RhsParams prm, int32_t linear)
@@ -534,11 +538,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     snk.kb = K + (int64_t)p * PS;
     snk.o = o;
     snk.so = prm.formulation;
-    rhs_slab_lds<T>(Q + (int64_t)p * PS, lds, sl, act, o, C, prm, snk);
+    rhs_slab_lds<T, LOP>(Q + (int64_t)p * PS, lds, sl, act, o, C, prm, snk);
 }
 
 struct LdsStageSink {
-    StageSink *st;
+    StageSink<0> *st;
     int o;
     __device__ __forceinline__ void put(int v, double r) { st->combine_at(o, v, r); }
     __device__ __forceinline__ void finish() { st->finish_at(o); }
@@ -584,7 +588,7 @@ struct LdsStageSink {
     }
 };
 
-template <typename T>
+template <typename T, int LOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_stage_lds(
     const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
     const PatchGeom *__restrict__ geom, int32_t npatch, int32_t nb_slab, RhsParams prm, int32_t s, double dt,
@@ -605,7 +609,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     int o;
     bool act;
     lds_cell_setup(lds, sl, g, prm, C, o, act);
-    StageSink ss;
+    StageSink<0> ss;
     ss.qn = Qn + (int64_t)p * PS;
     ss.acc = acc + (int64_t)p * PS;
     ss.qx = Qx + (int64_t)p * PS;
@@ -617,7 +621,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         push_offsets(nbr, p, cc % 9 + 3, (cc / 9) % 9 + 3, cc / 81 + 3 + 3 * sl, o, ss.pd);
     }
     LdsStageSink snk{&ss, o};
-    rhs_slab_lds<T>(Qs + (int64_t)p * PS, lds, sl, act, o, C, prm, snk);
+    rhs_slab_lds<T, LOP>(Qs + (int64_t)p * PS, lds, sl, act, o, C, prm, snk);
 }
 
 // Sommerfeld ghosts: one thread per (boundary face, slot, ghost cell)
@@ -1038,15 +1042,31 @@ hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t
     const int64_t nb = ((int64_t)npatch * 3 + 7) / 8 * 8;
     const int32_t lin = (variant & KV_LINEAR) ? 1 : 0;
     if (variant & KV_LDS) {
-        if (precision == 1)
-            hipLaunchKernelGGL(k_rhs_lds<float>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p, lin);
-        else
-            hipLaunchKernelGGL(k_rhs_lds<double>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p, lin);
+        const dim3 g((unsigned)nb), b(256);
+        if (p.advection) {
+            if (precision == 1)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<float, 1>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+            else
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<double, 1>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+        } else {
+            if (precision == 1)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<float, 0>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+            else
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<double, 0>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+        }
     } else {
-        if (precision == 1)
-            hipLaunchKernelGGL(k_rhs<float>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p, lin);
-        else
-            hipLaunchKernelGGL(k_rhs<double>, dim3((unsigned)nb), dim3(256), 0, st, Q, K, geom, npatch, p, lin);
+        const dim3 g((unsigned)nb), b(256);
+        if (p.advection) {
+            if (precision == 1)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs<float, 1>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+            else
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs<double, 1>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+        } else {
+            if (precision == 1)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs<float, 0>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+            else
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs<double, 0>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+        }
     }
     return hipGetLastError();
 }
@@ -1063,19 +1083,39 @@ hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn
     const int32_t ns = (int32_t)nb_slab;
     const int32_t lin = (variant & KV_LINEAR) ? 1 : 0;
     if (variant & KV_LDS) {
-        if (precision == 1)
-            hipLaunchKernelGGL(k_stage_lds<float>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                               ns, p, s, dt, bf, bg, nbr, lin);
-        else
-            hipLaunchKernelGGL(k_stage_lds<double>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom,
-                               npatch, ns, p, s, dt, bf, bg, nbr, lin);
+        const dim3 g((unsigned)nb), b(256);
+        if (p.advection) {
+            if (precision == 1)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<float, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
+                                   ns, p, s, dt, bf, bg, nbr, lin);
+            else
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<double, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
+                                   ns, p, s, dt, bf, bg, nbr, lin);
+        } else {
+            if (precision == 1)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<float, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
+                                   ns, p, s, dt, bf, bg, nbr, lin);
+            else
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<double, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
+                                   ns, p, s, dt, bf, bg, nbr, lin);
+        }
     } else {
-        if (precision == 1)
-            hipLaunchKernelGGL(k_stage<float>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
-                               p, s, dt, bf, bg, nbr, lin);
-        else
-            hipLaunchKernelGGL(k_stage<double>, dim3((unsigned)nb), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                               ns, p, s, dt, bf, bg, nbr, lin);
+        const dim3 g((unsigned)nb), b(256);
+        if (p.advection) {
+            if (precision == 1)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage<float, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
+                                   p, s, dt, bf, bg, nbr, lin);
+            else
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage<double, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
+                                   p, s, dt, bf, bg, nbr, lin);
+        } else {
+            if (precision == 1)
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage<float, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
+                                   p, s, dt, bf, bg, nbr, lin);
+            else
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage<double, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
+                                   p, s, dt, bf, bg, nbr, lin);
+        }
     }
     return hipGetLastError();
 }

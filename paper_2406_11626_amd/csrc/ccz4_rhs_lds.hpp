@@ -217,6 +217,7 @@ __device__ __forceinline__ void load_metric(const double *__restrict__ qp, int o
 struct SlotDeriv {
     double d[3];
     double k;
+    double a;  // advection beta^k d_k (central or lopsided), with the 4-argument form only
 };
 
 __device__ __forceinline__ SlotDeriv stencils(const LdsCell &c, int b)
@@ -225,6 +226,32 @@ __device__ __forceinline__ SlotDeriv stencils(const LdsCell &c, int b)
 #pragma unroll
     for (int a = 0; a < 3; ++a) r.d[a] = fd(c, b, a);
     r.k = ko(c, b);
+    r.a = 0.0;
+    CCZ4_PHASE_BARRIER();
+    return r;
+}
+
+// ... and the advection term with shift be: the central derivatives (LOP = 0), or the lopsided
+// stencils of App. D (LOP = 1, pairing `mode` as RhsParams::advection) from the same staged
+// points.  LOP is a template parameter so that the central kernel carries no lopsided code.
+template <int LOP>
+__device__ __forceinline__ SlotDeriv stencils(const LdsCell &c, int b, const double be[3], int32_t mode)
+{
+    SlotDeriv r;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r.d[a] = fd(c, b, a);
+    r.k = ko(c, b);
+    if constexpr (!LOP) {
+        r.a = be[0] * r.d[0] + be[1] * r.d[1] + be[2] * r.d[2];
+    } else {
+        double s[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            s[a] = lop_from_central(r.d[a], lop_use_right(mode, be[a]), lv(c, b, a, -3), lv(c, b, a, -2),
+                                    lv(c, b, a, -1), lv(c, b, a, 0), lv(c, b, a, 1), lv(c, b, a, 2), lv(c, b, a, 3),
+                                    c.i12[a]);
+        r.a = be[0] * s[0] + be[1] * s[1] + be[2] * s[2];
+    }
     CCZ4_PHASE_BARRIER();
     return r;
 }
@@ -258,7 +285,7 @@ __device__ constexpr int R4_OUT[24] = {SB, SB + 1, SB + 2, SB + 3, SB + 4, SB + 
 // together, and waits for both; the stores are then left in flight over the next barrier.
 // Right-hand side of the lane's cell of slab sl of the patch at qp.  Every lane of the
 // work-group must call this (staging and barriers); only lanes with act = true compute.
-template <typename T, typename Sink>
+template <typename T, int LOP, typename Sink>
 __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, double *lds, int sl, bool act, int o0,
                                              const LdsCell &C0, const RhsParams &p, Sink &snk)
 {
@@ -302,8 +329,8 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
             for (int l = 0; l < 3; ++l)
 #pragma unroll
                 for (int i = 0; i < 3; ++i) {
-                    const SlotDeriv sd = stencils(C, 6 + 3 * l + i);
-                    advkoB[3 * l + i] = gdrv ? dot3(be, sd.d) + sd.k : 0.0;
+                    const SlotDeriv sd = stencils<LOP>(C, 6 + 3 * l + i, be, p.advection);
+                    advkoB[3 * l + i] = gdrv ? sd.a + sd.k : 0.0;
 #pragma unroll
                     for (int k = 0; k < 3; ++k) dB[l][i][k] = sd.d[k];
                 }
@@ -349,8 +376,8 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
             double dA[6][3];
 #pragma unroll
             for (int s = 0; s < 6; ++s) {
-                const SlotDeriv sd = stencils(C, s);
-                advkoAt[s] = dot3(be, sd.d) + sd.k;
+                const SlotDeriv sd = stencils<LOP>(C, s, be, p.advection);
+                advkoAt[s] = sd.a + sd.k;
 #pragma unroll
                 for (int k = 0; k < 3; ++k) dA[s][k] = sd.d[k];
             }
@@ -433,9 +460,9 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
         }
 #pragma unroll
         for (int j = 0; j < 15; ++j) {
-            const SlotDeriv sd = stencils(C, j);
+            const SlotDeriv sd = stencils<LOP>(C, j, be, p.advection);
             dD_accumulate<T>(sd.d, j, ig, G1, H, U, E);
-            keep(ro2[j], dot3(be, sd.d) + static_cast<double>(partD[j / 6][j % 6]) + sd.k);
+            keep(ro2[j], sd.a + static_cast<double>(partD[j / 6][j % 6]) + sd.k);
         }
     }
 
@@ -465,9 +492,9 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
             load_metric<T>(qp, o, gd, igd, detg, g, ig);
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
-                const SlotDeriv sd = stencils(C, j);
+                const SlotDeriv sd = stencils<LOP>(C, j, be, p.advection);
                 dD_accumulate<T>(sd.d, 15 + j, ig, G1, H, U, E);
-                keep(ro3[j], dot3(be, sd.d) + static_cast<double>(partD[2][3 + j]) + sd.k);
+                keep(ro3[j], sd.a + static_cast<double>(partD[2][3 + j]) + sd.k);
             }
         }
         {  // ---- Ricci sector: At, K, Theta; the curl term of B
@@ -651,14 +678,14 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
                 }
             const T kap1 = cvt<T>(p.kappa1), kap2 = cvt<T>(p.kappa2);
             CCZ4_PHASE_BARRIER();
-            const SlotDeriv sK = stencils(C, 12);
-            keep(ro3[9], (dot3(be, sK.d) + static_cast<double>(-lapal + al * RpZ + al * Kt * (Kt - T(2) * Th * cc) -
+            const SlotDeriv sK = stencils<LOP>(C, 12, be, p.advection);
+            keep(ro3[9], (sK.a + static_cast<double>(-lapal + al * RpZ + al * Kt * (Kt - T(2) * Th * cc) -
                                                              T(3) * al * kap1 * (T(1) + kap2) * Th) +
                       sK.k));
             const T ee2 = cvt<T>(p.e * p.e);
             const T ZA = T(0.5) * phi2 * (dG[0] * A[0] + dG[1] * A[1] + dG[2] * A[2]);
-            const SlotDeriv sTh = stencils(C, 13);
-            keep(ro3[10], (dot3(be, sTh.d) +
+            const SlotDeriv sTh = stencils<LOP>(C, 13, be, p.advection);
+            keep(ro3[10], (sTh.a +
                                 static_cast<double>(T(0.5) * al * ee2 * (RpZ + T(2.0 / 3.0) * Kt * Kt - AA) -
                                                     al * Th * Kt * cc - ZA - al * kap1 * (T(2) + kap2) * Th) +
                       sTh.k));
@@ -766,8 +793,8 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
                     zb += zk * Bm[k][i];
                 }
                 t += T(2) * kap3 * (T(2.0 / 3.0) * u * trB - zb);
-                const SlotDeriv sG = stencils(C, 9 + i);
-                const double advG = dot3(be, sG.d);
+                const SlotDeriv sG = stencils<LOP>(C, 9 + i, be, p.advection);
+                const double advG = sG.a;
                 const double rG = advG + static_cast<double>(t);
                 keep(ro3[11 + i], rG + sG.k);
                 rGb[i] = rG - advG;
@@ -798,13 +825,13 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
                 T t = -al * al * ga * (dK - T(2) * cc * dTh) - al * ga * dtrA[k];
                 t += Bm[k][0] * A[0] + Bm[k][1] * A[1] + Bm[k][2] * A[2];
                 t += -ga_lin * theta_term * A[k];
-                const SlotDeriv sA = stencils(C, 6 + k);
-                keep(ro3[14 + k], dot3(be, sA.d) + static_cast<double>(t) + sA.k);
+                const SlotDeriv sA = stencils<LOP>(C, 6 + k, be, p.advection);
+                keep(ro3[14 + k], sA.a + static_cast<double>(t) + sA.k);
                 const T u = Bm[k][0] * P[0] + Bm[k][1] * P[1] + Bm[k][2] * P[2] + T(1.0 / 3.0) * (al * Kt - trB) * P[k];
                 const T phipart =
                     T(1.0 / 3.0) * (al * dK - sdBtr[k]) + T(1.0 / 3.0) * al * dtrA[k] + T(1.0 / 3.0) * Kt * A[k];
-                const SlotDeriv sP = stencils(C, 3 + k);
-                keep(ro3[17 + k], dot3(be, sP.d) + static_cast<double>(u) + phid * static_cast<double>(phipart) + sP.k);
+                const SlotDeriv sP = stencils<LOP>(C, 3 + k, be, p.advection);
+                keep(ro3[17 + k], sP.a + static_cast<double>(u) + phid * static_cast<double>(phipart) + sP.k);
             }
         }
     }
@@ -834,7 +861,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
             const T ff = cvt<T>(p.f);
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const SlotDeriv sb = stencils(C, i);
+                const SlotDeriv sb = stencils<LOP>(C, i, be, p.advection);
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     T t = ff * cvt<T>(sb.d[k]);
@@ -842,7 +869,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
                     t += curl[k][i];
                     keep(ro4[3 * k + i], advkoB[3 * k + i] + static_cast<double>(t));
                 }
-                keep(ro4[9 + i], rGb[i] + dot3(be, sb.d) - p.eta * q(SBB + i) + sb.k);
+                keep(ro4[9 + i], rGb[i] + sb.a - p.eta * q(SBB + i) + sb.k);
             }
         } else {
 #pragma unroll

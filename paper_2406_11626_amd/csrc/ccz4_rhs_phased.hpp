@@ -28,6 +28,7 @@ struct CellRef {
     int o;           // offset of the cell inside a slot box
     double i12[3];   // 1 / (12 dx_a)
     double koc[3];   // eps / (64 dx_a)
+    int adv;         // advection stencil (RhsParams::advection)
 };
 
 __device__ __forceinline__ constexpr int axis_stride(int a) { return a == 0 ? 1 : (a == 1 ? YS : ZS); }
@@ -66,15 +67,34 @@ __device__ __forceinline__ double ko(const CellRef &c, int v)
     return (kx + ky) + kz;
 }
 
+// derivative of slot v along axis a for the advection term: central (LOP = 0), or lopsided
+// (App. D; LOP = 1) by the sign of the shift component be with the pairing c.adv
+template <int LOP>
+__device__ __forceinline__ double fd_adv(const CellRef &c, int v, int a, double be)
+{
+    if constexpr (!LOP) {
+        return fd(c, v, a);
+    } else {
+        const double *f = c.qb + v * CS + c.o;
+        const int s = axis_stride(a);
+        return lop_from_central(fd(c, v, a), lop_use_right(c.adv, be), f[-3 * s], f[-2 * s], f[-s], f[0], f[s],
+                                f[2 * s], f[3 * s], c.i12[a]);
+    }
+}
+
 // advection beta^k d_k of slot v
+template <int LOP>
 __device__ __forceinline__ double adv(const CellRef &c, int v, const double be[3])
 {
-    return be[0] * fd(c, v, 0) + be[1] * fd(c, v, 1) + be[2] * fd(c, v, 2);
+    return be[0] * fd_adv<LOP>(c, v, 0, be[0]) + be[1] * fd_adv<LOP>(c, v, 1, be[1]) +
+           be[2] * fd_adv<LOP>(c, v, 2, be[2]);
 }
 
 // Output sinks: the plain right-hand side writes k = algebra + KO; the fused stage folds each
 // finished slot at once into the RK4 stage combine (see StageSink).
+template <int L>
 struct RhsSink {
+    static constexpr int LOP = L;  // lopsided advection stencils in the phase functions
     int so;  // second-order formulation: the auxiliaries' right-hand sides are 0
     __device__ __forceinline__ void put(const CellRef &c, int v, double alg)
     {
@@ -368,15 +388,15 @@ __device__ __forceinline__ void phase_ricci(Sink &snk, const CellRef &c, const R
             t += al * At[ij] * (Kt - T(2) * Th * cc);
             t += T(-2) * al * (At[sym(i, 0)] * Am[0][j] + At[sym(i, 1)] * Am[1][j] + At[sym(i, 2)] * Am[2][j]);
             const T tf = X[ij] - T(1.0 / 3.0) * g[ij] * trX;
-            snk.put(c, SAT + ij, adv(c, SAT + ij, be) + static_cast<double>(t) + phid * phid * static_cast<double>(tf));
+            snk.put(c, SAT + ij, adv<Sink::LOP>(c, SAT + ij, be) + static_cast<double>(t) + phid * phid * static_cast<double>(tf));
         }
     const T kap1 = cvt<T>(p.kappa1), kap2 = cvt<T>(p.kappa2);
-    snk.put(c, SK, adv(c, SK, be) + static_cast<double>(-lapal + al * RpZ + al * Kt * (Kt - T(2) * Th * cc) -
+    snk.put(c, SK, adv<Sink::LOP>(c, SK, be) + static_cast<double>(-lapal + al * RpZ + al * Kt * (Kt - T(2) * Th * cc) -
                                                         T(3) * al * kap1 * (T(1) + kap2) * Th));
     const T ee2 = cvt<T>(p.e * p.e);
     const T half_phi2 = T(0.5) * phi2;
     const T ZA = half_phi2 * (dG[0] * A[0] + dG[1] * A[1] + dG[2] * A[2]);
-    snk.put(c, STHETA, adv(c, STHETA, be) + static_cast<double>(T(0.5) * al * ee2 * (RpZ + T(2.0 / 3.0) * Kt * Kt - AA) -
+    snk.put(c, STHETA, adv<Sink::LOP>(c, STHETA, be) + static_cast<double>(T(0.5) * al * ee2 * (RpZ + T(2.0 / 3.0) * Kt * Kt - AA) -
                                                               al * Th * Kt * cc - ZA - al * kap1 * (T(2) + kap2) * Th));
     (void)bet;
 }
@@ -432,7 +452,7 @@ __device__ __forceinline__ void phase_B(Sink &snk, const CellRef &c, const RhsPa
 #pragma unroll
             for (int j = 0; j < 3; ++j) curl += ig[sym(i, j)] * (CmG[k][j] - cP[k][j]);
             t += a2mu * curl;
-            snk.put(c, SB + 3 * k + i, adv(c, SB + 3 * k + i, be) + static_cast<double>(t));
+            snk.put(c, SB + 3 * k + i, adv<Sink::LOP>(c, SB + 3 * k + i, be) + static_cast<double>(t));
         }
 }
 
@@ -548,10 +568,10 @@ __device__ __forceinline__ void phase_gamma(Sink &snk, const CellRef &c, const R
             zb += zk * Bm[k][i];
         }
         t += T(2) * kap3 * (T(2.0 / 3.0) * u * trB - zb);
-        const double advG = adv(c, SGHAT + i, be);
+        const double advG = adv<Sink::LOP>(c, SGHAT + i, be);
         const double rG = advG + static_cast<double>(t);
         snk.put(c, SGHAT + i, rG);
-        if (p.shift) snk.put(c, SBB + i, rG - advG + adv(c, SBB + i, be) - p.eta * ld(c, SBB + i));
+        if (p.shift) snk.put(c, SBB + i, rG - advG + adv<Sink::LOP>(c, SBB + i, be) - p.eta * ld(c, SBB + i));
         else snk.zero(c, SBB + i);
     }
 }
@@ -619,10 +639,10 @@ __device__ __forceinline__ void phase_AP(Sink &snk, const CellRef &c, const RhsP
         T t = -al * al * ga * (dK - T(2) * cc * dTh) - al * ga * dtrA[k];
         t += Bm[k][0] * A[0] + Bm[k][1] * A[1] + Bm[k][2] * A[2];
         t += -ga_lin * theta_term * A[k];
-        snk.put(c, SA + k, adv(c, SA + k, be) + static_cast<double>(t));
+        snk.put(c, SA + k, adv<Sink::LOP>(c, SA + k, be) + static_cast<double>(t));
         T u = Bm[k][0] * P[0] + Bm[k][1] * P[1] + Bm[k][2] * P[2] + T(1.0 / 3.0) * (al * Kt - trB) * P[k];
         const T phipart = T(1.0 / 3.0) * (al * dK - sdBtr[k]) + T(1.0 / 3.0) * al * dtrA[k] + T(1.0 / 3.0) * Kt * A[k];
-        snk.put(c, SP + k, adv(c, SP + k, be) + static_cast<double>(u) + phid * static_cast<double>(phipart));
+        snk.put(c, SP + k, adv<Sink::LOP>(c, SP + k, be) + static_cast<double>(u) + phid * static_cast<double>(phipart));
     }
 }
 
@@ -702,7 +722,7 @@ __device__ __forceinline__ void phase_D(Sink &snk, const CellRef &c0, const RhsP
                 for (int l = 0; l < 3; ++l) t += Bm[k][l] * D[l][ij] + Bm[j][l] * D[k][sym(l, i)] + Bm[i][l] * D[k][sym(l, j)];
                 t += T(-2.0 / 3.0) * trB * D[k][ij];
                 t += -A[k] * (At[ij] - T(1.0 / 3.0) * g[ij] * trAt);
-                snk.put(c, SD + 6 * k + ij, adv(c, SD + 6 * k + ij, be) + static_cast<double>(t));
+                snk.put(c, SD + 6 * k + ij, adv<Sink::LOP>(c, SD + 6 * k + ij, be) + static_cast<double>(t));
             }
         CCZ4_PHASE_BARRIER();
     }
