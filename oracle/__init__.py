@@ -80,6 +80,10 @@ _set_bg = _sig("orc_set_background", None, [ctypes.c_void_p, _dp])
 _fill = _sig("orc_fill_halos", None, [ctypes.c_void_p, _dp])
 _rhs = _sig("orc_rhs", None, [ctypes.c_void_p, _PP, _dp, _dp])
 _recon = _sig("orc_reconstruct_aux", None, [ctypes.c_void_p, _dp])
+_find_leaf = _sig("orc_find_leaf", ctypes.c_int64, [ctypes.c_void_p, _dp])
+_tr_sample = _sig("orc_tracer_sample", ctypes.c_int64,
+                  [ctypes.c_void_p, _dp, ctypes.c_int64, _dp, ctypes.c_int, _ip, _dp])
+_tr_advance = _sig("orc_tracer_advance", ctypes.c_int64, [ctypes.c_void_p, _dp, ctypes.c_int64, _dp, ctypes.c_double])
 _rhs_subset = _sig("orc_rhs_subset", None,
                    [ctypes.c_void_p, _PP, _dp, _dp, ctypes.c_int64, _i64p])
 _rk4 = _sig("orc_rk4_stage", ctypes.c_int,
@@ -251,6 +255,22 @@ class Mesh:
             sel = _c(subset, np.int64)
             _rhs_subset(self._h, ctypes.byref(pr), Q, k, sel.size, sel)
         return k
+
+    def find_leaf(self, x):
+        return int(_find_leaf(self._h, _c(x)))
+
+    def tracer_sample(self, Q, pos, slots):
+        """(n, len(slots)) trilinear samples at the points pos (n, 3); NaN outside the mesh."""
+        pos = _c(pos).reshape(-1, 3)
+        sl = np.ascontiguousarray(slots, dtype=np.int32)
+        out = np.zeros((pos.shape[0], sl.size))
+        _tr_sample(self._h, Q, pos.shape[0], pos, sl.size, sl, out)
+        return out
+
+    def tracer_advance(self, Q, pos, dt):
+        """One explicit Euler step of puncture trackers, in place on pos (n, 3) float64."""
+        assert pos.dtype == np.float64 and pos.flags.c_contiguous
+        return int(_tr_advance(self._h, Q, pos.shape[0], pos, dt))
 
     def reconstruct(self, Q):
         """Second-order formulation: the auxiliaries of every interior cell from FD4

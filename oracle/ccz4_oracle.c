@@ -732,6 +732,83 @@ void orc_rhs(const orc_mesh *m, const orc_params *pr, const double *Q, double *k
 }
 
 /* ----------------------------------------------------------------------------------------
+ * Tracers (Sec. 3.8): a point's value is the trilinear interpolation of the 2^3 cell centres
+ * around it in the leaf that holds it; puncture trackers (Sec. 4) move with velocity -beta by
+ * the explicit Euler rule x <- x + dt v.
+ * ---------------------------------------------------------------------------------------- */
+int64_t orc_find_leaf(const orc_mesh *m, const double x[3])
+{
+    int64_t p;
+    for (p = 0; p < m->np; p++) {
+        double org[3], dx[3];
+        int a, in = 1;
+        patch_geom(m, p, org, dx);
+        for (a = 0; a < 3; a++)
+            if (!(x[a] >= org[a] && x[a] < org[a] + PP * dx[a])) in = 0;
+        if (in) return p;
+    }
+    return -1;
+}
+
+/* trilinear weights: cell-centre coordinate u = (x - o)/dx - 1/2 in interior units */
+static int tracer_interp(const orc_mesh *m, const double *Q, const double x[3], int nslot, const int *slots,
+                         double *out)
+{
+    const int64_t p = orc_find_leaf(m, x);
+    double org[3], dx[3], t[3];
+    int i0[3], a, s, cx, cy, cz;
+    if (p < 0) return 0;
+    patch_geom(m, p, org, dx);
+    for (a = 0; a < 3; a++) {
+        const double u = (x[a] - org[a]) / dx[a] - 0.5;
+        const double f = floor(u);
+        i0[a] = (int)f + HH; /* box index of the lower centre: 2..11 */
+        t[a] = u - f;
+    }
+    const double *box = Q + p * (int64_t)ORC_BOXCELLS * NV;
+    for (s = 0; s < nslot; s++) {
+        double v = 0.0;
+        for (cz = 0; cz < 2; cz++)
+            for (cy = 0; cy < 2; cy++)
+                for (cx = 0; cx < 2; cx++) {
+                    const double w = (cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1]) * (cz ? t[2] : 1.0 - t[2]);
+                    v += w * box[cix(i0[0] + cx, i0[1] + cy, i0[2] + cz) * NV + slots[s]];
+                }
+        out[s] = v;
+    }
+    return 1;
+}
+
+int64_t orc_tracer_sample(const orc_mesh *m, const double *Q, int64_t n, const double *pos, int nslot,
+                          const int *slots, double *out)
+{
+    int64_t i, missing = 0;
+    int s;
+    for (i = 0; i < n; i++)
+        if (!tracer_interp(m, Q, pos + 3 * i, nslot, slots, out + i * nslot)) {
+            for (s = 0; s < nslot; s++) out[i * nslot + s] = NAN;
+            missing++;
+        }
+    return missing;
+}
+
+int64_t orc_tracer_advance(const orc_mesh *m, const double *Q, int64_t n, double *pos, double dt)
+{
+    static const int beta[3] = {7, 8, 9};
+    int64_t i, missing = 0;
+    int a;
+    for (i = 0; i < n; i++) {
+        double b[3];
+        if (!tracer_interp(m, Q, pos + 3 * i, 3, beta, b)) {
+            missing++;
+            continue;
+        }
+        for (a = 0; a < 3; a++) pos[3 * i + a] += dt * (-b[a]);
+    }
+    return missing;
+}
+
+/* ----------------------------------------------------------------------------------------
  * Second-order formulation (Sec. 2.4; Sec. 3.2, explicit gradient reconstruction; Algorithm 2):
  * after each update the auxiliaries are recomputed from the primaries with the central FD4
  * difference, by their definitions A_i = d_i alpha, B_k^i = d_k beta^i,

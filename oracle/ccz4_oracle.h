@@ -100,6 +100,18 @@ void orc_project_point(double *q);
 int64_t orc_constraints(const orc_mesh *m, const double *Q, double *HM /* [n][729][4] or NULL */,
                         double r_excise, double norms[3]);
 void orc_tag_indicator(const orc_mesh *m, const double *Q, double *ind /* [n][3] */);
+
+/* ---- tracers (Sec. 3.8) and puncture trackers (Sec. 4, puncture tracking) ---- */
+/* the leaf whose interior box [o, o + 9 dx) holds x, or -1 */
+int64_t orc_find_leaf(const orc_mesh *m, const double x[3]);
+/* trilinear interpolation of nslot slots at n points pos[n][3] from the 2^3 cell centres around
+   each (the leaf's filled halos supply the centres beyond its interior); out[n][nslot];
+   returns the number of points outside every leaf (their samples are NaN) */
+int64_t orc_tracer_sample(const orc_mesh *m, const double *Q, int64_t n, const double *pos, int nslot,
+                          const int *slots, double *out);
+/* one explicit Euler step of puncture trackers: x <- x + dt v with v = -beta(x) interpolated as
+   above; points outside every leaf stay; returns their number */
+int64_t orc_tracer_advance(const orc_mesh *m, const double *Q, int64_t n, double *pos, double dt);
 void orc_tag_refine(const orc_mesh *m, const double *Q, double theta_r, double theta_c,
                     int max_level, int8_t *tags);
 

@@ -1,0 +1,118 @@
+"""Pins of the oracle's tracers (Sec. 3.8: trilinear projection from the 2^3 nearest cell centres,
+explicit Euler motion) and puncture trackers (velocity -beta): exactness on multilinear fields,
+the closed-form error on a quadratic, cell-centre values, the leaf lookup on an AMR mesh checked
+geometrically, and Euler steps in constant and linear shift fields."""
+import numpy as np
+import pytest
+
+import oracle as orc
+from seeded_inputs import box_centers
+
+
+def amr_mesh():
+    return orc.Mesh((2, 2, 1), (-1.0, -1.0, -0.5), (2.0, 2.0, 1.0), 1, [(0, 0, 1, 0)])
+
+
+def fill_global(m, f, slot):
+    """Every box cell (halos included) of every leaf gets f at its centre."""
+    Q = m.zeros()
+    for p in range(m.np):
+        P = box_centers(m.geom[p, :3], m.geom[p, 3:])
+        Q[p, ..., slot] = f(P[..., 0], P[..., 1], P[..., 2])
+    return Q
+
+
+def interior_points(m, n, rng):
+    lo = np.array([-1.0, -1.0, -0.5])
+    return lo + rng.random((n, 3)) * np.array([2.0, 2.0, 1.0]) * 0.999
+
+
+def test_find_leaf_matches_geometry():
+    m = amr_mesh()
+    rng = np.random.default_rng(0)
+    for x in interior_points(m, 300, rng):
+        p = m.find_leaf(x)
+        assert p >= 0
+        o, dx = m.geom[p, :3], m.geom[p, 3:]
+        assert np.all(x >= o) and np.all(x < o + 9 * dx)
+        others = [q for q in range(m.np) if q != p and np.all(x >= m.geom[q, :3]) and
+                  np.all(x < m.geom[q, :3] + 9 * m.geom[q, 3:])]
+        assert not others
+    assert m.find_leaf(np.array([5.0, 0.0, 0.0])) == -1
+
+
+def test_trilinear_exact_on_multilinear_fields():
+    m = amr_mesh()
+    rng = np.random.default_rng(1)
+    c = rng.normal(size=8)
+
+    def f(x, y, z):
+        return c[0] + c[1] * x + c[2] * y + c[3] * z + c[4] * x * y + c[5] * x * z + c[6] * y * z + c[7] * x * y * z
+
+    Q = fill_global(m, f, 17)
+    pts = interior_points(m, 400, rng)
+    out = m.tracer_sample(Q, pts, [17])
+    np.testing.assert_allclose(out[:, 0], f(pts[:, 0], pts[:, 1], pts[:, 2]), rtol=0, atol=1e-13)
+
+
+def test_trilinear_error_closed_form_on_a_quadratic():
+    """For f = x^2 the trilinear interpolant between centres x_i and x_i + h errs by exactly
+    h^2 t (1 - t) at x = x_i + t h."""
+    m = amr_mesh()
+    Q = fill_global(m, lambda x, y, z: x * x, 6)
+    rng = np.random.default_rng(2)
+    pts = interior_points(m, 200, rng)
+    out = m.tracer_sample(Q, pts, [6])[:, 0]
+    for x, v in zip(pts, out):
+        p = m.find_leaf(x)
+        h = m.geom[p, 3]
+        u = (x[0] - m.geom[p, 0]) / h - 0.5
+        t = u - np.floor(u)
+        assert abs(v - (x[0] ** 2 + h * h * t * (1 - t))) < 1e-13
+
+
+def test_samples_at_cell_centres_are_cell_values():
+    m = amr_mesh()
+    rng = np.random.default_rng(3)
+    Q = rng.normal(size=m.zeros().shape)
+    for p in (0, 3, m.np - 1):
+        P = box_centers(m.geom[p, :3], m.geom[p, 3:])
+        for idx in ((3, 3, 3), (7, 4, 11), (11, 11, 11)):
+            x = P[idx]
+            out = m.tracer_sample(Q, x[None, :], [0, 25, 58])
+            np.testing.assert_allclose(out[0], Q[p][idx][[0, 25, 58]], rtol=0, atol=1e-14)
+
+
+def test_points_outside_give_nan_and_do_not_move():
+    m = amr_mesh()
+    Q = m.zeros()
+    pos = np.array([[0.1, 0.2, 0.0], [3.0, 0.0, 0.0]])
+    out = m.tracer_sample(Q, pos, [7])
+    assert np.isfinite(out[0, 0]) and np.isnan(out[1, 0])
+    before = pos.copy()
+    assert m.tracer_advance(Q, pos, 0.1) == 1
+    assert np.array_equal(pos[1], before[1])
+
+
+def test_euler_step_in_constant_and_linear_shift():
+    """Puncture trackers move with -beta: x <- x - dt beta(x).  A constant shift moves every
+    tracer by -dt beta; a linear shift beta = M x + b is interpolated exactly, so one step gives
+    x - dt (M x + b)."""
+    m = amr_mesh()
+    rng = np.random.default_rng(4)
+    M = rng.normal(size=(3, 3)) * 0.3
+    b = rng.normal(size=3) * 0.1
+    Q = m.zeros()
+    for p in range(m.np):
+        P = box_centers(m.geom[p, :3], m.geom[p, 3:])
+        Q[p, ..., 7:10] = P @ M.T + b
+    pos = interior_points(m, 50, rng) * 0.8
+    x0 = pos.copy()
+    dt = 0.05
+    assert m.tracer_advance(Q, pos, dt) == 0
+    np.testing.assert_allclose(pos, x0 - dt * (x0 @ M.T + b), rtol=0, atol=1e-14)
+    Qc = m.zeros()
+    Qc[..., 7:10] = b
+    pos = x0.copy()
+    m.tracer_advance(Qc, pos, dt)
+    np.testing.assert_allclose(pos, x0 - dt * b, rtol=0, atol=1e-15)
