@@ -83,6 +83,8 @@ _recon = _sig("orc_reconstruct_aux", None, [ctypes.c_void_p, _dp])
 _find_leaf = _sig("orc_find_leaf", ctypes.c_int64, [ctypes.c_void_p, _dp])
 _tr_sample = _sig("orc_tracer_sample", ctypes.c_int64,
                   [ctypes.c_void_p, _dp, ctypes.c_int64, _dp, ctypes.c_int, _ip, _dp])
+_tag_tracers = _sig("orc_tag_tracers", None, [ctypes.c_void_p, ctypes.c_int64, _dp, ctypes.c_int, _dp, ctypes.c_int,
+                                              _i8p])
 _tr_advance = _sig("orc_tracer_advance", ctypes.c_int64, [ctypes.c_void_p, _dp, ctypes.c_int64, _dp, ctypes.c_double])
 _rhs_subset = _sig("orc_rhs_subset", None,
                    [ctypes.c_void_p, _PP, _dp, _dp, ctypes.c_int64, _i64p])
@@ -271,6 +273,13 @@ class Mesh:
         """One explicit Euler step of puncture trackers, in place on pos (n, 3) float64."""
         assert pos.dtype == np.float64 and pos.flags.c_contiguous
         return int(_tr_advance(self._h, Q, pos.shape[0], pos, dt))
+
+    def tag_tracers(self, pos, radii, max_level):
+        pos = _c(pos).reshape(-1, 3)
+        r = _c(radii)
+        tags = np.zeros(self.np, dtype=np.int8)
+        _tag_tracers(self._h, pos.shape[0], pos, r.size, r, int(max_level), tags)
+        return tags
 
     def reconstruct(self, Q):
         """Second-order formulation: the auxiliaries of every interior cell from FD4

@@ -808,6 +808,51 @@ int64_t orc_tracer_advance(const orc_mesh *m, const double *Q, int64_t n, double
     return missing;
 }
 
+/* distance from the nearest of n points to the closed cube [lo, lo + L] */
+static double cube_distance(const double lo[3], const double L[3], int64_t n, const double *pos)
+{
+    double best = HUGE_VAL;
+    int64_t i;
+    int a;
+    for (i = 0; i < n; i++) {
+        double d2 = 0.0;
+        for (a = 0; a < 3; a++) {
+            const double x = pos[3 * i + a];
+            const double c = x < lo[a] ? lo[a] : (x > lo[a] + L[a] ? lo[a] + L[a] : x);
+            d2 += (c - x) * (c - x);
+        }
+        if (sqrt(d2) < best) best = sqrt(d2);
+    }
+    return best;
+}
+
+void orc_tag_tracers(const orc_mesh *m, int64_t n, const double *pos, int nrad, const double *radii, int max_level,
+                     int8_t *tags)
+{
+    int64_t p;
+    int a;
+    for (p = 0; p < m->np; p++) {
+        const int lev = m->id[4 * p];
+        double lo[3], L[3];
+        tags[p] = 0;
+        for (a = 0; a < 3; a++) {
+            L[a] = m->extent[a] / lev_n(m, lev, a);
+            lo[a] = m->origin[a] + L[a] * m->id[4 * p + 1 + a];
+        }
+        if (lev < max_level && lev < nrad && cube_distance(lo, L, n, pos) <= radii[lev]) {
+            tags[p] = 1;
+            continue;
+        }
+        if (lev >= 1) {
+            for (a = 0; a < 3; a++) {
+                L[a] = m->extent[a] / lev_n(m, lev - 1, a);
+                lo[a] = m->origin[a] + L[a] * (m->id[4 * p + 1 + a] / 3);
+            }
+            if (lev - 1 >= nrad || cube_distance(lo, L, n, pos) > radii[lev - 1]) tags[p] = -1;
+        }
+    }
+}
+
 /* ----------------------------------------------------------------------------------------
  * Second-order formulation (Sec. 2.4; Sec. 3.2, explicit gradient reconstruction; Algorithm 2):
  * after each update the auxiliaries are recomputed from the primaries with the central FD4

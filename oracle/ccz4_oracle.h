@@ -112,6 +112,14 @@ int64_t orc_tracer_sample(const orc_mesh *m, const double *Q, int64_t n, const d
 /* one explicit Euler step of puncture trackers: x <- x + dt v with v = -beta(x) interpolated as
    above; points outside every leaf stay; returns their number */
 int64_t orc_tracer_advance(const orc_mesh *m, const double *Q, int64_t n, double *pos, double dt);
+/* Tracker-based refinement tags (Sec. 3, refinement by coordinates): with R_l = radii[l],
+   a leaf of level l < min(max_level, nrad) whose cube lies within R_l of a tracer gets REFINE (1);
+   a leaf of level l >= 1 whose parent cube lies farther than R_(l-1) from every tracer gets
+   COARSEN (-1); every other leaf KEEP (0).  Distances are from the tracer to the nearest point
+   of the closed cube.  A mesh refined by concentric spheres of these radii around the tracers
+   is a fixed point (all KEEP). */
+void orc_tag_tracers(const orc_mesh *m, int64_t n, const double *pos, int nrad, const double *radii, int max_level,
+                     int8_t *tags);
 void orc_tag_refine(const orc_mesh *m, const double *Q, double theta_r, double theta_c,
                     int max_level, int8_t *tags);
 

@@ -116,3 +116,50 @@ def test_euler_step_in_constant_and_linear_shift():
     pos = x0.copy()
     m.tracer_advance(Qc, pos, dt)
     np.testing.assert_allclose(pos, x0 - dt * b, rtol=0, atol=1e-15)
+
+
+def sphere_mesh(centres, radii):
+    from paper_2406_11626_amd import scenarios
+    n0, origin, extent = (4, 4, 2), (-2.0, -2.0, -1.0), (4.0, 4.0, 2.0)
+    ref = scenarios.sphere_refinement(n0, origin, extent, centres, radii)
+    return orc.Mesh(n0, origin, extent, 1, ref), ref
+
+
+def test_tracker_tags_fixed_point_of_sphere_refinement():
+    """A mesh refined by spheres of radii R_l around the tracers is left as it is."""
+    centres = [(0.31, -0.12, 0.07), (-0.6, 0.5, -0.1)]
+    radii = [0.9, 0.25]
+    m, _ = sphere_mesh(centres, radii)
+    assert m.ids[:, 0].max() == 2
+    tags = m.tag_tracers(np.array(centres), radii, 2)
+    assert np.all(tags == 0)
+
+
+def test_tracker_tags_follow_a_moved_tracer():
+    """Move the tracer: the plan of the tags reproduces the sphere refinement around the new
+    position (the tag rule refines and coarsens exactly the cubes that differ)."""
+    radii = [0.9, 0.25]
+    m, _ = sphere_mesh([(0.31, -0.12, 0.07)], radii)
+    new = (0.55, 0.1, 0.07)
+    _, want = sphere_mesh([new], radii)
+    cur = m
+    for _ in range(3):  # refinement proceeds one level per regrid
+        tags = cur.tag_tracers(np.array([new]), radii, 2)
+        plan = cur.regrid_plan(tags, 2)
+        cur = orc.Mesh((4, 4, 2), (-2.0, -2.0, -1.0), (4.0, 4.0, 2.0), 1, [tuple(c) for c in plan])
+    assert {tuple(int(v) for v in c) for c in plan} == {tuple(c) for c in want}
+    assert np.all(cur.tag_tracers(np.array([new]), radii, 2) == 0)
+
+
+def test_tracker_tags_respect_max_level_and_far_leaves():
+    """With the tracer moved more than R_0 + a cube diagonal away from every refined cube, every
+    fine leaf is asked to coarsen and nothing near the tracer's old place refines."""
+    radii = [0.3, 0.1]
+    m, _ = sphere_mesh([(0.31, -0.12, 0.07)], radii)
+    assert m.ids[:, 0].max() == 2
+    far = np.array([[-1.95, 1.95, -0.95]])
+    tags = m.tag_tracers(far, radii, 2)
+    lev = m.ids[:, 0]
+    assert np.all(tags[lev > 0] == -1)          # every fine leaf's parent is now far away
+    t1 = m.tag_tracers(far, radii, 0)            # max_level 0: nothing is refined
+    assert not np.any(t1 == 1)
