@@ -190,6 +190,30 @@ ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double
    pointer or unknown flags. */
 ccz4_status ccz4_reconstruct_aux(ccz4_ctx *ctx, double *Q, int32_t flags, void *stream);
 
+/* Tracers (Sec. 3.8, data probes).  For each of n points pos[n][3] (device, float64), the leaf
+   whose interior box [o, o + 9 dx) holds it, then for each of the nslots slots (host array, values
+   0..58) the trilinear interpolation of the 2^3 cell centres around the point; the leaf's halos
+   supply the centres beyond its interior, so Q's halos must be filled.  out[n][nslots] (device).
+   A point outside every leaf samples NaN.  n = 0 does nothing.  EINVAL on NULL pointers, n < 0,
+   nslots outside 1..59 or a slot outside 0..58. */
+ccz4_status ccz4_tracers_sample(ccz4_ctx *ctx, const double *Q, int64_t n, const double *pos, int32_t nslots,
+                                const int32_t *slots, double *out, void *stream);
+
+/* Puncture trackers (Sec. 4: tracers moved by the reversed shift).  One explicit Euler step of the
+   Sec. 3.8 rule x <- x + dt v with v = -beta(x), beta interpolated as in ccz4_tracers_sample; pos
+   (device) is updated in place; a point outside every leaf stays.  Q's halos must be filled. */
+ccz4_status ccz4_tracers_advance(ccz4_ctx *ctx, const double *Q, int64_t n, double *pos, double dt, void *stream);
+
+/* Refinement tags by coordinates (Sec. 3, dynamic refinement based on coordinates): with the
+   per-level radii r[0..nradii-1] (host), a leaf of level l < min(max_level, nradii) whose closed
+   cube lies within r[l] of one of the n tracers pos[n][3] (device) is tagged REFINE (1); a leaf of
+   level l >= 1 whose parent cube lies farther than r[l-1] from every tracer COARSEN (-1); every
+   other leaf KEEP (0).  tags[n_patches] (device, int8), in the form ccz4_regrid_plan takes once
+   copied to the host.  A mesh refined by spheres of these radii around the tracers is a fixed
+   point.  EINVAL on NULL pointers or nradii outside 0..16. */
+ccz4_status ccz4_tag_tracers(ccz4_ctx *ctx, int64_t n, const double *pos, int32_t nradii, const double *radii,
+                             int32_t max_level, int8_t *tags, void *stream);
+
 /* Launch configuration of ccz4_rhs and ccz4_rhs_rk4_stage, per precision (CCZ4_PREC_FP64 or
    CCZ4_PREC_MIXED): CCZ4_KERNEL_PHASED or CCZ4_KERNEL_LDS, optionally with
    CCZ4_KERNEL_LINEAR_ORDER added.  Both kernels evaluate the same right-hand side (App. B algebra,

@@ -84,6 +84,9 @@ def lib():
             "ccz4_rk4_stage": (i32, [P, i32, f64, P, P, P, P, P]),
             "ccz4_rhs_rk4_stage": (i32, [P, i32, f64, P, P, P, P, i32, i32, P]),
             "ccz4_reconstruct_aux": (i32, [P, P, i32, P]),
+            "ccz4_tracers_sample": (i32, [P, P, i64, P, i32, P, P, P]),
+            "ccz4_tracers_advance": (i32, [P, P, i64, P, f64, P]),
+            "ccz4_tag_tracers": (i32, [P, i64, P, i32, P, i32, P, P]),
             "ccz4_fill_halos_kinds": (i32, [P, P, i32, P]),
             "ccz4_plan_counts": (i32, [P, ctypes.POINTER(i64)]),
             "ccz4_constraints": (i32, [P, P, P, f64, P, P]),
@@ -217,6 +220,22 @@ def ccz4_rk4_stage(h, s, dt, Qn, k, acc, Qnext, stream=None):
 
 def ccz4_reconstruct_aux(h, Q, flags=0, stream=None):
     return _check(lib().ccz4_reconstruct_aux(h, _ptr(Q), int(flags), _stream(stream)))
+
+
+def ccz4_tracers_sample(h, Q, pos, slots, out, stream=None):
+    sl = (ctypes.c_int32 * len(slots))(*[int(v) for v in slots])
+    return _check(lib().ccz4_tracers_sample(h, _ptr(Q), int(pos.shape[0]) if pos is not None else 0, _ptr(pos),
+                                            len(slots), ctypes.cast(sl, ctypes.c_void_p), _ptr(out), _stream(stream)))
+
+
+def ccz4_tracers_advance(h, Q, pos, dt, stream=None):
+    return _check(lib().ccz4_tracers_advance(h, _ptr(Q), int(pos.shape[0]), _ptr(pos), float(dt), _stream(stream)))
+
+
+def ccz4_tag_tracers(h, pos, radii, max_level, tags, stream=None):
+    r = (ctypes.c_double * max(1, len(radii)))(*[float(v) for v in radii])
+    return _check(lib().ccz4_tag_tracers(h, int(pos.shape[0]), _ptr(pos), len(radii), ctypes.cast(r, ctypes.c_void_p),
+                                         int(max_level), _ptr(tags), _stream(stream)))
 
 
 def ccz4_rhs_rk4_stage(h, s, dt, Qs, Qn, acc, Qnext, precision=PREC_FP64, flags=0, stream=None):
@@ -382,6 +401,27 @@ class Context:
         differences of the primaries (whose halos must be filled); with push, also into the
         same-level neighbours' face halos."""
         ccz4_reconstruct_aux(self.h, Q, STAGE_FILL_SAME_LEVEL if push else 0, stream)
+
+    def tracers_sample(self, Q, pos, slots, stream=None):
+        """(n, len(slots)) float64 device tensor: trilinear samples at the points pos (n, 3) float64
+        device tensor; NaN outside the mesh."""
+        import torch
+        out = torch.empty((pos.shape[0], len(slots)), dtype=torch.float64, device=pos.device)
+        ccz4_tracers_sample(self.h, Q, pos, slots, out, stream)
+        return out
+
+    def tracers_advance(self, Q, pos, dt, stream=None):
+        """Puncture trackers: one explicit Euler step with velocity -beta, in place on pos."""
+        ccz4_tracers_advance(self.h, Q, pos, dt, stream)
+
+    def tag_tracers(self, pos, radii, max_level, tags=None, stream=None):
+        """int8 device tensor of refinement tags by coordinates (REFINE near the tracers, COARSEN
+        where the parent cube is far from all of them)."""
+        import torch
+        if tags is None:
+            tags = torch.empty(self.n_patches, dtype=torch.int8, device="cuda")
+        ccz4_tag_tracers(self.h, pos, radii, max_level, tags, stream)
+        return tags
 
     @property
     def second_order(self):

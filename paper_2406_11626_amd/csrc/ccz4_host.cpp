@@ -83,6 +83,8 @@ struct ccz4_ctx {
     std::vector<std::array<int, 4>> refined;  // refined cubes of the forest (lev, i, j, k)
     std::unordered_map<uint64_t, int> index;  // leaf key -> leaf index
     std::vector<PatchGeom> geom;
+    std::vector<TrackBox> tbox;           // cubes of the leaves and of their parents
+    DevBuf<TrackBox> d_tbox;
     std::vector<FaceTask> ph_copy, ph_neu, ph_res, ph_pro;  // fill tasks by kind (restrict before prolong)
     std::vector<int32_t> nbr;                 // [leaf][6] same-level face neighbour or -1
     std::vector<BoundaryFace> bface;
@@ -166,6 +168,19 @@ ccz4_status build_plan(ccz4_ctx *c, const ccz4_grid_desc *g)
             const double L = c->extent[a] / level_n(c, pg.level, a);
             pg.org[a] = c->origin[a] + L * leaves[p][1 + a];
             pg.dx[a] = L / PN;
+        }
+    }
+    c->tbox.resize(leaves.size());
+    for (size_t p = 0; p < leaves.size(); ++p) {
+        TrackBox &b = c->tbox[p];
+        const int lev = leaves[p][0];
+        b.level = lev;
+        b.pad = 0;
+        for (int a = 0; a < 3; ++a) {
+            b.L[a] = c->extent[a] / level_n(c, lev, a);
+            b.lo[a] = c->origin[a] + b.L[a] * leaves[p][1 + a];
+            b.pL[a] = lev > 0 ? c->extent[a] / level_n(c, lev - 1, a) : 0.0;
+            b.plo[a] = lev > 0 ? c->origin[a] + b.pL[a] * (leaves[p][1 + a] / 3) : 0.0;
         }
     }
     // face tasks
@@ -341,6 +356,7 @@ ccz4_status ccz4_create(ccz4_ctx **out, const ccz4_grid_desc *g, const ccz4_para
     const int64_t nblk = constraints_blocks((int32_t)c->leaf.size());
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = c->d_geom.upload(c->geom);
+    if (e == hipSuccess) e = c->d_tbox.upload(c->tbox);
     if (e == hipSuccess) e = c->d_phc.upload(c->ph_copy);
     if (e == hipSuccess) e = c->d_phn.upload(c->ph_neu);
     if (e == hipSuccess) e = c->d_phr.upload(c->ph_res);
@@ -368,6 +384,7 @@ void ccz4_destroy(ccz4_ctx *c)
     if (!c) return;
     (void)hipDeviceSynchronize();
     c->d_geom.release();
+    c->d_tbox.release();
     c->d_phc.release();
     c->d_phn.release();
     c->d_phr.release();
@@ -544,6 +561,57 @@ ccz4_status ccz4_reconstruct_aux(ccz4_ctx *c, double *Q, int32_t flags, void *st
     if (flags & ~CCZ4_STAGE_FILL_SAME_LEVEL) return fail(CCZ4_EINVAL, "unknown reconstruction flags");
     HIP_TRY(launch_reconstruct(Q, c->d_geom.p, (int32_t)c->leaf.size(),
                                (flags & CCZ4_STAGE_FILL_SAME_LEVEL) ? c->d_nbr.p : nullptr, S(stream)));
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_tracers_sample(ccz4_ctx *c, const double *Q, int64_t n, const double *pos, int32_t nslots,
+                                const int32_t *slots, double *out, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    if (n < 0 || n > INT32_MAX) return fail(CCZ4_EINVAL, "bad number of tracers");
+    if (n == 0) return CCZ4_OK;
+    ccz4_status st = check_ptr(Q, "Q");
+    if (st) return st;
+    if (!pos || !out || !slots) return fail(CCZ4_EINVAL, "pos, slots or out is NULL");
+    if (nslots < 1 || nslots > NV) return fail(CCZ4_EINVAL, "nslots must be 1..59");
+    TracerSlots sl;
+    sl.n = nslots;
+    for (int s = 0; s < nslots; ++s) {
+        if (slots[s] < 0 || slots[s] >= NV) return fail(CCZ4_EINVAL, "slot out of range");
+        sl.v[s] = slots[s];
+    }
+    HIP_TRY(launch_tracers(Q, c->d_geom.p, (int32_t)c->leaf.size(), n, const_cast<double *>(pos), sl, out, 0.0, 0,
+                           S(stream)));
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_tracers_advance(ccz4_ctx *c, const double *Q, int64_t n, double *pos, double dt, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    if (n < 0 || n > INT32_MAX) return fail(CCZ4_EINVAL, "bad number of tracers");
+    if (!std::isfinite(dt)) return fail(CCZ4_EINVAL, "dt must be finite");
+    if (n == 0) return CCZ4_OK;
+    ccz4_status st = check_ptr(Q, "Q");
+    if (st) return st;
+    if (!pos) return fail(CCZ4_EINVAL, "pos is NULL");
+    TracerSlots sl;
+    sl.n = 0;
+    HIP_TRY(launch_tracers(Q, c->d_geom.p, (int32_t)c->leaf.size(), n, pos, sl, nullptr, dt, 1, S(stream)));
+    return CCZ4_OK;
+}
+
+ccz4_status ccz4_tag_tracers(ccz4_ctx *c, int64_t n, const double *pos, int32_t nradii, const double *radii,
+                             int32_t max_level, int8_t *tags, void *stream)
+{
+    if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
+    if (n < 0) return fail(CCZ4_EINVAL, "bad number of tracers");
+    if (!tags || (n > 0 && !pos)) return fail(CCZ4_EINVAL, "pos or tags is NULL");
+    if (nradii < 0 || nradii > MAX_TRACK_LEVELS || (nradii > 0 && !radii))
+        return fail(CCZ4_EINVAL, "nradii must be 0..16 with radii given");
+    TrackRadii R;
+    R.n = nradii;
+    for (int l = 0; l < MAX_TRACK_LEVELS; ++l) R.r[l] = l < nradii ? radii[l] : 0.0;
+    HIP_TRY(launch_tag_tracers(c->d_tbox.p, (int32_t)c->leaf.size(), n, pos, R, max_level, tags, S(stream)));
     return CCZ4_OK;
 }
 

@@ -1013,6 +1013,121 @@ hipError_t launch_reconstruct(double *Q, const PatchGeom *geom, int32_t npatch, 
     return hipGetLastError();
 }
 
+// Tracers (Sec. 3.8): one work-group per point.  The lanes test a strided share of the leaves for
+// the one whose interior box [o, o + 9 dx) holds the point; then each of the requested slots is
+// the trilinear interpolation of the 2^3 cell centres around the point (box indices 2..12, the
+// leaf's filled halos supplying the outermost ones).  advance: the point moves by dt * (-beta)
+// (puncture tracker, explicit Euler).  A point outside every leaf samples NaN and stays.
+__global__ __launch_bounds__(256) void k_tracers(const double *__restrict__ Q, const PatchGeom *__restrict__ geom,
+                                                 int32_t npatch, double *__restrict__ pos, TracerSlots sl,
+                                                 double *__restrict__ out, double dt, int32_t advance)
+{
+    __shared__ int leaf;
+    __shared__ double beta[3];
+    const int64_t i = blockIdx.x;
+    if (threadIdx.x == 0) leaf = -1;
+    __syncthreads();
+    const double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+    for (int p = (int)threadIdx.x; p < npatch; p += (int)blockDim.x) {
+        const PatchGeom g = geom[p];
+        bool in = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) in = in && x[a] >= g.org[a] && x[a] < g.org[a] + 9.0 * g.dx[a];
+        if (in) leaf = p;  // leaves do not overlap: one lane at most
+    }
+    __syncthreads();
+    const int p = leaf;
+    const int nout = advance ? 3 : sl.n;
+    const int t = (int)threadIdx.x;
+    if (t < nout) {
+        const int v = advance ? SBETA + t : sl.v[t];
+        double val = __builtin_nan("");
+        if (p >= 0) {
+            const PatchGeom g = geom[p];
+            int i0[3];
+            double w[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double u = (x[a] - g.org[a]) / g.dx[a] - 0.5;
+                const double f = floor(u);
+                i0[a] = (int)f + 3;
+                w[a] = u - f;
+            }
+            const double *b = Q + (int64_t)p * PS + v * CS;
+            val = 0.0;
+#pragma unroll
+            for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+                for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+                    for (int cx = 0; cx < 2; ++cx) {
+                        const double wt = (cx ? w[0] : 1.0 - w[0]) * (cy ? w[1] : 1.0 - w[1]) * (cz ? w[2] : 1.0 - w[2]);
+                        val += wt * b[boff(i0[0] + cx, i0[1] + cy, i0[2] + cz)];
+                    }
+        }
+        if (advance) beta[t] = val;
+        else out[i * sl.n + t] = val;
+    }
+    if (advance) {
+        __syncthreads();
+        if (t == 0 && p >= 0)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) pos[3 * i + a] = x[a] + dt * (-beta[a]);
+    }
+}
+
+hipError_t launch_tracers(const double *Q, const PatchGeom *geom, int32_t npatch, int64_t n, double *pos,
+                          const TracerSlots &sl, double *out, double dt, int32_t advance, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tracers, dim3((unsigned)n), dim3(256), 0, st, Q, geom, npatch, pos, sl, out, dt, advance);
+    return hipGetLastError();
+}
+
+// Tracker-based refinement (refinement by coordinates): REFINE a leaf of level l < min(max_level,
+// radii.n) whose closed cube lies within r[l] of a tracer; COARSEN a leaf of level >= 1 whose parent
+// cube lies farther than r[l - 1] from every tracer; KEEP otherwise.  One lane per leaf.
+__device__ __forceinline__ double cube_distance(const double lo[3], const double L[3], int64_t n,
+                                                const double *__restrict__ pos)
+{
+    double best = __builtin_huge_val();
+    for (int64_t i = 0; i < n; ++i) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double x = pos[3 * i + a];
+            const double c = x < lo[a] ? lo[a] : (x > lo[a] + L[a] ? lo[a] + L[a] : x);
+            d2 += (c - x) * (c - x);
+        }
+        best = fmin(best, sqrt(d2));
+    }
+    return best;
+}
+
+__global__ __launch_bounds__(256) void k_tag_tracers(const TrackBox *__restrict__ box, int32_t npatch, int64_t n,
+                                                     const double *__restrict__ pos, TrackRadii R, int32_t max_level,
+                                                     int8_t *__restrict__ tags)
+{
+    const int p = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (p >= npatch) return;
+    const TrackBox b = box[p];
+    int8_t t = 0;
+    if (b.level < max_level && b.level < R.n && cube_distance(b.lo, b.L, n, pos) <= R.r[b.level])
+        t = 1;
+    else if (b.level >= 1 && (b.level - 1 >= R.n || cube_distance(b.plo, b.pL, n, pos) > R.r[b.level - 1]))
+        t = -1;
+    tags[p] = t;
+}
+
+hipError_t launch_tag_tracers(const TrackBox *box, int32_t npatch, int64_t n, const double *pos, const TrackRadii &R,
+                              int32_t max_level, int8_t *tags, hipStream_t st)
+{
+    if (npatch <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tag_tracers, dim3((unsigned)((npatch + 255) / 256)), dim3(256), 0, st, box, npatch, n, pos, R,
+                       max_level, tags);
+    return hipGetLastError();
+}
+
 hipError_t launch_regrid(const double *Qo, double *Qn, const RegridTask *tasks, int32_t n, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;

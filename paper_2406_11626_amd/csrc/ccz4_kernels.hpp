@@ -31,6 +31,10 @@ hipError_t launch_rk4(int32_t s, double dt, const double *Qn, const double *K, d
                       int32_t npatch, const BoundaryFace *bf, int32_t nbf, hipStream_t st);
 hipError_t launch_regrid(const double *Qo, double *Qn, const RegridTask *tasks, int32_t n, hipStream_t st);
 hipError_t launch_reconstruct(double *Q, const PatchGeom *geom, int32_t npatch, const int32_t *nbr, hipStream_t st);
+hipError_t launch_tracers(const double *Q, const PatchGeom *geom, int32_t npatch, int64_t n, double *pos,
+                          const TracerSlots &sl, double *out, double dt, int32_t advance, hipStream_t st);
+hipError_t launch_tag_tracers(const TrackBox *box, int32_t npatch, int64_t n, const double *pos, const TrackRadii &R,
+                              int32_t max_level, int8_t *tags, hipStream_t st);
 int64_t constraints_blocks(int32_t npatch);
 hipError_t launch_constraints(const double *Q, double *HM, const PatchGeom *geom, int32_t npatch,
                               double r_excise, double *part, double *out3, hipStream_t st);

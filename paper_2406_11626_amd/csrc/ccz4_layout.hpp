@@ -62,4 +62,24 @@ struct PatchGeom {
     int32_t level, pad;
 };
 
+// A leaf's cube and its parent's cube (lower corner and edge lengths, the parent's only for
+// level >= 1), for refinement tags by coordinates
+struct TrackBox {
+    double lo[3], L[3], plo[3], pL[3];
+    int32_t level, pad;
+};
+
+// Slots sampled by tracers (passed by value)
+struct TracerSlots {
+    int32_t n;
+    int32_t v[NV];
+};
+
+// Per-level radii of tracker-based refinement (passed by value)
+constexpr int MAX_TRACK_LEVELS = 16;
+struct TrackRadii {
+    int32_t n;
+    double r[MAX_TRACK_LEVELS];
+};
+
 }  // namespace ccz4

@@ -1,0 +1,102 @@
+"""GPU parity of tracers, puncture trackers and refinement tags by coordinates against the
+oracle: trilinear samples at random points of a static AMR mesh (NaN outside), several Euler
+steps of trackers in a random shift field, and the REFINE / KEEP / COARSEN tags around moved
+tracers on a sphere-refined mesh (integers: bit-exact)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import oracle as orc  # noqa: E402
+from gpu_helpers import to_gpu  # noqa: E402
+from paper_2406_11626_amd import ccz4, scenarios  # noqa: E402
+from seeded_inputs import box_centers, smooth_state  # noqa: E402
+
+N0, ORIGIN, EXTENT = (3, 3, 2), (-1.5, -1.5, -1.0), (3.0, 3.0, 2.0)
+REFINED = [(0, 1, 1, 0), (0, 1, 1, 1)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ccz4.lib()
+
+
+def pair(refined=REFINED):
+    ctx = ccz4.Context(N0, ORIGIN, EXTENT, ccz4.BC_NEUMANN, ccz4.params(), refined)
+    m = orc.Mesh(N0, ORIGIN, EXTENT, ccz4.BC_NEUMANN, refined)
+    assert np.array_equal(ctx.ids, m.ids)
+    return ctx, m
+
+
+def state(m, seed):
+    Q = m.zeros()
+    for p in range(m.np):
+        Q[p] = smooth_state(box_centers(m.geom[p, :3], m.geom[p, 3:]), seed)
+    m.fill_halos(Q)
+    return Q
+
+
+def points(n, seed, outside=0):
+    rng = np.random.default_rng(seed)
+    P = np.array(ORIGIN) + rng.random((n, 3)) * np.array(EXTENT) * 0.999
+    if outside:
+        P[:outside] += np.array([5.0, 0.0, 0.0])
+    return P
+
+
+def test_tracer_samples_match_oracle():
+    ctx, m = pair()
+    Qo = state(m, 70)
+    pts = points(500, 1, outside=3)
+    slots = [0, 6, 7, 10, 17, 25, 40, 57, 58]
+    want = m.tracer_sample(Qo, pts, slots)
+    got = ctx.tracers_sample(to_gpu(Qo), torch.tensor(pts, device="cuda"), slots).cpu().numpy()
+    assert np.array_equal(np.isnan(got), np.isnan(want)) and np.isnan(got[:3]).all()
+    ok = ~np.isnan(want)
+    assert np.abs(got[ok] - want[ok]).max() <= 1e-13 * np.abs(want[ok]).max()
+
+
+def test_tracker_euler_steps_match_oracle():
+    ctx, m = pair()
+    Qo = state(m, 71)
+    Qd = to_gpu(Qo)
+    pos = points(64, 2, outside=1) * 0.6
+    pos[0] = [7.0, 0.0, 0.0]
+    pd = torch.tensor(pos, device="cuda")
+    for _ in range(5):
+        m.tracer_advance(Qo, pos, 0.05)
+        ctx.tracers_advance(Qd, pd, 0.05)
+    got = pd.cpu().numpy()
+    assert np.array_equal(got[0], [7.0, 0.0, 0.0])
+    assert np.abs(got - pos).max() <= 1e-14 * max(1.0, np.abs(pos).max())
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tracker_tags_match_oracle(seed):
+    radii = [0.8, 0.3]
+    centres = [(0.2, -0.1, 0.05), (-0.4, 0.3, -0.2)]
+    ref = scenarios.sphere_refinement(N0, ORIGIN, EXTENT, centres, radii)
+    ctx, m = pair(ref)
+    rng = np.random.default_rng(seed)
+    moved = np.array(centres) + rng.normal(size=(2, 3)) * 0.3 * seed
+    want = m.tag_tracers(moved, radii, 2)
+    got = ctx.tag_tracers(torch.tensor(moved, device="cuda"), radii, 2).cpu().numpy()
+    assert np.array_equal(got, want)
+    if seed == 0:
+        assert np.all(got == 0)  # the sphere refinement around the tracers is a fixed point
+    else:
+        assert (got == 1).any() or (got == -1).any()
+
+
+def test_tracer_arguments_are_checked():
+    ctx, _ = pair()
+    Q = ctx.new_state(0.0)
+    pos = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(ccz4.CCZ4Error):
+        ccz4.ccz4_tracers_sample(ctx.h, Q, pos, [59], torch.empty((2, 1), dtype=torch.float64, device="cuda"))
+    with pytest.raises(ccz4.CCZ4Error):
+        ccz4.ccz4_tag_tracers(ctx.h, pos, [0.1] * 17, 2, torch.empty(ctx.n_patches, dtype=torch.int8, device="cuda"))
