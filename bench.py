@@ -234,6 +234,46 @@ def run_stability(args, w):
     return out
 
 
+def run_tracker(args):
+    """Puncture trackers (tracers moved by -beta with explicit Euler, one step per RK4 step) in the
+    binary-puncture data, second-order formulation, graph-launched steps up to t_end; the tracker
+    positions and the count of non-finite cells every sample_dt."""
+    import torch
+    from paper_2406_11626_amd import ccz4, scenarios
+    w = scenarios.binary_tracking()
+    prm = ccz4.params(**{**w.prm, "formulation": ccz4.FORMULATION_SO})
+    ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, prm, w.refined)
+    Q = ctx.new_state(0.0)
+    ctx.init_patches(Q, w.scenario, w.scen)
+    ctx.fill_halos(Q)
+    ctx.reconstruct(Q)
+    ctx.fill_halos(Q)
+    bufs = (ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0))
+    dt = w.dt()
+    graph = ctx.step_graph(Q, bufs, dt)
+    pos = torch.tensor([[3.0, 0.0, 0.0], [-3.0, 0.0, 0.0]], dtype=torch.float64, device="cuda")
+    nsteps = int(round(args.t_end / dt))
+    every = max(1, int(round(args.sample_dt / dt)))
+    track = [dict(t=0.0, pos=pos.cpu().numpy().tolist(), nonfinite=0.0)]
+    t0 = time.perf_counter()
+    for i in range(1, nsteps + 1):
+        graph.launch()
+        ctx.tracers_advance(Q, pos, dt)
+        if i % every == 0 or i == nsteps:
+            norms, _ = ctx.constraints(Q)
+            p = pos.cpu().numpy()
+            track.append(dict(t=i * dt, pos=p.tolist(), nonfinite=norms[2]))
+            print(f"# t = {i * dt:.2f}: trackers {p[0].round(4).tolist()} {p[1].round(4).tolist()}, "
+                  f"non-finite = {norms[2]:.0f}", file=sys.stderr, flush=True)
+            if norms[2] > 0:
+                break
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    graph.close()
+    return dict(workload=w.name, leaves=ctx.n_patches, dt=dt, formulation="second order", t_end=args.t_end,
+                wall_s=wall, ms_per_step=wall * 1e3 / max(1, i), track=track)
+
+
 def run_dynamic(args, w):
     """Binary puncture with dynamic AMR: a regrid by the plain criterion every 10 steps.  The
     thresholds are fixed once from the indicator at t = 0 (its 99.5th and 30th percentiles over
@@ -321,6 +361,8 @@ def main():
     ap.add_argument("--stability", action="store_true",
                     help="instead of timing: evolve the workload in both formulations up to --t-end and "
                          "print the constraint norms")
+    ap.add_argument("--tracker", action="store_true",
+                    help="instead of timing: puncture trackers in the binary-puncture data up to --t-end")
     ap.add_argument("--t-end", type=float, default=10.0)
     ap.add_argument("--sample-dt", type=float, default=0.5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -337,6 +379,9 @@ def main():
     from paper_2406_11626_amd import scenarios
     assert torch.cuda.is_available(), "no GPU"
     w = scenarios.config(args.config)
+    if args.tracker:
+        print(json.dumps(run_tracker(args)), flush=True)
+        return
     if args.stability:
         r = run_stability(args, w)
         print(json.dumps({"workload": w.name, "dt": w.dt(), "t_end": args.t_end, "r_excise": 1.0, **r}), flush=True)

@@ -101,3 +101,13 @@ def config(n):
                         (16, 16, 16), (-12.0,) * 3, (24.0,) * 3, ccz4.BC_SOMMERFELD, BLACK_HOLE, ccz4.SCEN_BL_BY, scen,
                         20, refined=ref)
     raise ValueError(n)
+
+
+def binary_tracking(radii=(2.0,)):
+    """The binary-puncture data of configuration 5 (masses 0.5 at (+-3, 0, 0), Bowen-York momenta
+    (0, +-0.095, 0)) on [-12, 12]^3 with a static refinement of the given radii around the two
+    punctures: the workload of the puncture-tracker run."""
+    w = config(5)
+    ref = sphere_refinement(w.n0, w.origin, w.extent, [(3.0, 0.0, 0.0), (-3.0, 0.0, 0.0)], list(radii))
+    return Workload(f"binary puncture on [-12,12]^3, static refinement r = {list(radii)} around the punctures",
+                    w.n0, w.origin, w.extent, w.bc, BLACK_HOLE, w.scenario, w.scen, 20, refined=ref)
