@@ -80,6 +80,7 @@ _set_bg = _sig("orc_set_background", None, [ctypes.c_void_p, _dp])
 _fill = _sig("orc_fill_halos", None, [ctypes.c_void_p, _dp])
 _rhs = _sig("orc_rhs", None, [ctypes.c_void_p, _PP, _dp, _dp])
 _recon = _sig("orc_reconstruct_aux", None, [ctypes.c_void_p, _dp])
+_set_transfer = _sig("orc_mesh_set_transfer", None, [ctypes.c_void_p, ctypes.c_int])
 _find_leaf = _sig("orc_find_leaf", ctypes.c_int64, [ctypes.c_void_p, _dp])
 _tr_sample = _sig("orc_tracer_sample", ctypes.c_int64,
                   [ctypes.c_void_p, _dp, ctypes.c_int64, _dp, ctypes.c_int, _ip, _dp])
@@ -280,6 +281,11 @@ class Mesh:
         tags = np.zeros(self.np, dtype=np.int8)
         _tag_tracers(self._h, pos.shape[0], pos, r.size, r, int(max_level), tags)
         return tags
+
+    def set_transfer(self, transfer):
+        """0: the App. E coarse-fine operators as printed; 1: injection restriction and quadratic
+        prolongation."""
+        _set_transfer(self._h, int(transfer))
 
     def reconstruct(self, Q):
         """Second-order formulation: the auxiliaries of every interior cell from FD4

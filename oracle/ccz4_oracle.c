@@ -148,7 +148,10 @@ struct orc_mesh {
     int *id;       /* leaves: lev,i,j,k */
     double *bg;    /* Sommerfeld background: one full box per leaf touching the boundary */
     int64_t *bgix; /* leaf -> background box index or -1 */
+    int transfer;  /* coarse-fine operators: 0 as printed in App. E, 1 higher order */
 };
+
+void orc_mesh_set_transfer(orc_mesh *m, int transfer) { m->transfer = transfer; }
 
 static int lev_n(const orc_mesh *m, int lev, int a)
 {
@@ -543,6 +546,25 @@ static void fill_face_restrict(const orc_mesh *m, double *Q, int64_t p, int a, i
             ci[b2] = 3 * ni[b2] + u2;
             kids[u2][u1] = find_leaf(m, lev + 1, ci[0], ci[1], ci[2]);
         }
+    if (m->transfer == 1) {
+        /* injection: coarse halo layer c_{2+L} at normal distance (L - 1/2) coarse cells from
+           the face = (3L - 3/2) fine cells: fine interior depth 3L - 1; tangentially the
+           middle fine cell 3u + 1 of the three under coarse cell u */
+        for (L = 1; L <= 3; L++)
+            for (u2 = 0; u2 < PP; u2++)
+                for (u1 = 0; u1 < PP; u1++) {
+                    const int Fa = 3 * u1 + 1, Fb = 3 * u2 + 1;
+                    int cf[3];
+                    cf[b1] = HH + Fa % PP;
+                    cf[b2] = HH + Fb % PP;
+                    cf[a] = layer_coord(-side, 3 * L - 1);
+                    c[b1] = HH + u1;
+                    c[b2] = HH + u2;
+                    c[a] = layer_coord(side, -L);
+                    memcpy(cellp(Q, p, c), cellp(Q, kids[Fb / PP][Fa / PP], cf), sizeof(double) * NV);
+                }
+        return;
+    }
     for (L = 1; L <= 3; L++)           /* coarse halo layer c_{2+L} */
         for (u2 = 0; u2 < PP; u2++)    /* coarse tangential index along b2 */
             for (u1 = 0; u1 < PP; u1++) {
@@ -588,6 +610,53 @@ static void fill_face_prolong(const orc_mesh *m, double *Q, int64_t p, int a, in
     /* position of this fine patch inside the coarse face: fine index minus 3 * coarse index */
     o1 = ni[b1] - 3 * m->id[4 * cp + 1 + b1];
     o2 = ni[b2] - 3 * m->id[4 * cp + 1 + b2];
+    if (m->transfer == 1) {
+        /* three-point Lagrange quadratics.  Tangentially: fine cell F sits at coarse coordinate
+           u = (F + 1/2)/3 - 1/2; the three coarse centres l-1, l, l+1 with l the nearest, kept
+           inside 1..p-2.  Along the normal: fine ghost L sits at (1/2 - (L - 1/2)/3) coarse
+           cells from the centre of c2 towards the face, interpolated from c1, c2, c3. */
+        for (L = 1; L <= 3; L++) {
+            const double sn = 0.5 - (L - 0.5) / 3.0;
+            double wn[3];
+            wn[0] = sn * (sn - 1.0) / 2.0;
+            wn[1] = 1.0 - sn * sn;
+            wn[2] = sn * (sn + 1.0) / 2.0;
+            for (t2 = 0; t2 < PP; t2++)
+                for (t1 = 0; t1 < PP; t1++) {
+                    double acc[NV], w1[3], w2[3], s1, s2;
+                    int k1, k2, kn, j1, j2;
+                    const double u1 = (PP * o1 + t1 + 0.5) / 3.0 - 0.5, u2 = (PP * o2 + t2 + 0.5) / 3.0 - 0.5;
+                    j1 = (int)floor(u1 + 0.5);
+                    j2 = (int)floor(u2 + 0.5);
+                    if (j1 < 1) j1 = 1;
+                    if (j1 > PP - 2) j1 = PP - 2;
+                    if (j2 < 1) j2 = 1;
+                    if (j2 > PP - 2) j2 = PP - 2;
+                    s1 = u1 - j1;
+                    s2 = u2 - j2;
+                    w1[0] = s1 * (s1 - 1.0) / 2.0; w1[1] = 1.0 - s1 * s1; w1[2] = s1 * (s1 + 1.0) / 2.0;
+                    w2[0] = s2 * (s2 - 1.0) / 2.0; w2[1] = 1.0 - s2 * s2; w2[2] = s2 * (s2 + 1.0) / 2.0;
+                    memset(acc, 0, sizeof(acc));
+                    for (kn = 0; kn < 3; kn++)          /* c1, c2, c3 */
+                        for (k2 = 0; k2 < 3; k2++)
+                            for (k1 = 0; k1 < 3; k1++) {
+                                const double w = wn[kn] * w2[k2] * w1[k1];
+                                int cc[3];
+                                cc[b1] = HH + j1 - 1 + k1;
+                                cc[b2] = HH + j2 - 1 + k2;
+                                /* c1, c2: coarse interior depth 2, 1 from the shared face; c3: halo 1 */
+                                cc[a] = kn < 2 ? layer_coord(-side, 2 - kn) : layer_coord(-side, -1);
+                                const double *src = cellp(Q, cp, cc);
+                                for (v = 0; v < NV; v++) acc[v] += w * src[v];
+                            }
+                    c[b1] = HH + t1;
+                    c[b2] = HH + t2;
+                    c[a] = layer_coord(side, -L);
+                    memcpy(cellp(Q, p, c), acc, sizeof(acc));
+                }
+        }
+        return;
+    }
     for (L = 1; L <= 3; L++) {        /* fine ghost layer L -> f_{3-L} */
         const int frow = 3 - L;
         for (t2 = 0; t2 < PP; t2++)

@@ -74,6 +74,14 @@ enum { ORC_BC_PERIODIC = 0, ORC_BC_NEUMANN = 1, ORC_BC_SOMMERFELD = 2 };
 orc_mesh *orc_mesh_create(const int n0[3], const double origin[3], const double extent[3],
                           int bc, int n_refined, const int *refined /* [n][4]: lev,i,j,k */);
 void orc_mesh_destroy(orc_mesh *m);
+/* Coarse-fine halo operators.  0: App. E as printed (P_par x P_par x P_perp linear, R_avg x
+   R_avg x R_perp average and linear extrapolation).  1: higher order (the paper's suggested
+   remedy for reflections at refinement boundaries, Sec. 5.2): restriction injects the fine cell
+   whose centre coincides with the coarse halo centre (tangentially the middle of three fine
+   cells, along the normal the fine interior depth 2, 5 or 8), and prolongation interpolates
+   with three-point Lagrange quadratics along each axis (coarse layers c1, c2 and the restricted
+   c3 along the normal).  Both reproduce quadratic fields exactly. */
+void orc_mesh_set_transfer(orc_mesh *m, int transfer);
 int64_t orc_mesh_npatches(const orc_mesh *m);
 /* per leaf: lev, i, j, k */
 void orc_mesh_patch_ids(const orc_mesh *m, int *ids /* [n][4] */);
