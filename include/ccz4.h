@@ -68,11 +68,20 @@ enum { CCZ4_SCEN_GAUGE_WAVE = 0, CCZ4_SCEN_PUNCTURE = 1, CCZ4_SCEN_BL_BY = 2 };
    the pairing as printed (biased towards -x_k where beta^k > 0). */
 enum { CCZ4_FORMULATION_FIRST_ORDER = 0, CCZ4_FORMULATION_SECOND_ORDER = 1 };
 enum { CCZ4_ADVECTION_CENTRAL = 0, CCZ4_ADVECTION_LOPSIDED_UPWIND = 1, CCZ4_ADVECTION_LOPSIDED_PRINTED = 2 };
+/* transfer selects the coarse-fine halo operators of every fill: the App. E operators as printed
+   (linear P_par x P_par x P_perp prolongation, R_avg x R_avg x R_perp restriction by average and
+   linear extrapolation), or higher-order ones (the remedy the paper names for reflections at
+   refinement boundaries): restriction injects the fine cell whose centre coincides with the
+   coarse halo centre, prolongation interpolates with three-point Lagrange quadratics along each
+   axis (coarse layers c1, c2 and the restricted c3 along the normal); both reproduce quadratic
+   fields exactly.  Regrid transfers are unaffected. */
+enum { CCZ4_TRANSFER_APP_E = 0, CCZ4_TRANSFER_HIGHER_ORDER = 1 };
 typedef struct {
     double kappa1, kappa2, kappa3, tau, e, c, mu, f, eta, ko_eps;
     int32_t slicing, shift;
     int32_t formulation;
     int32_t advection;
+    int32_t transfer;
 } ccz4_params;
 
 /* Forest of n0[0] x n0[1] x n0[2] level-0 cubes over [origin, origin + extent], every cube

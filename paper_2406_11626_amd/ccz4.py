@@ -18,6 +18,7 @@ BC_PERIODIC, BC_NEUMANN, BC_SOMMERFELD = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 FORMULATION_FO, FORMULATION_SO = 0, 1
 ADVECTION_CENTRAL, ADVECTION_LOPSIDED_UPWIND, ADVECTION_LOPSIDED_PRINTED = 0, 1, 2
+TRANSFER_APP_E, TRANSFER_HIGHER_ORDER = 0, 1
 KERNEL_PHASED, KERNEL_LDS, KERNEL_LINEAR_ORDER = 0, 1, 2
 FILL_SAME_LEVEL, FILL_NEUMANN, FILL_LEVELS, FILL_ALL = 1, 2, 4, 7
 STAGE_FILL_SAME_LEVEL = 1
@@ -37,7 +38,7 @@ class Params(ctypes.Structure):
         ("tau", ctypes.c_double), ("e", ctypes.c_double), ("c", ctypes.c_double),
         ("mu", ctypes.c_double), ("f", ctypes.c_double), ("eta", ctypes.c_double),
         ("ko_eps", ctypes.c_double), ("slicing", ctypes.c_int32), ("shift", ctypes.c_int32),
-        ("formulation", ctypes.c_int32), ("advection", ctypes.c_int32),
+        ("formulation", ctypes.c_int32), ("advection", ctypes.c_int32), ("transfer", ctypes.c_int32),
     ]
 
 
@@ -52,9 +53,10 @@ def params(**kw):
     """Black-hole defaults of the paper (kappa1 = 0.1, kappa3 = 0.5, e = c = tau = 1, mu = 0.2,
     f = 0.75), eta = 2, KO 0.1, 1+log slicing, Gamma-driver shift, first-order formulation
     (formulation=FORMULATION_SO for the second-order one), central advection (advection=
-    ADVECTION_LOPSIDED_UPWIND or ADVECTION_LOPSIDED_PRINTED for App. D's lopsided stencils)."""
+    ADVECTION_LOPSIDED_UPWIND or ADVECTION_LOPSIDED_PRINTED for App. D's lopsided stencils), the
+    App. E coarse-fine operators (transfer=TRANSFER_HIGHER_ORDER for injection and quadratics)."""
     d = dict(kappa1=0.1, kappa2=0.0, kappa3=0.5, tau=1.0, e=1.0, c=1.0, mu=0.2, f=0.75,
-             eta=2.0, ko_eps=0.1, slicing=1, shift=1, formulation=0, advection=0)
+             eta=2.0, ko_eps=0.1, slicing=1, shift=1, formulation=0, advection=0, transfer=0)
     d.update(kw)
     return Params(**d)
 

@@ -23,6 +23,7 @@ struct RhsParams {
     int32_t formulation;  // 0: first order (red terms on), 1: second order (red terms off, aux RHS 0)
     int32_t advection;    // 0: central FD4 advection; 1: lopsided, biased towards +x_k where beta^k > 0;
                           // 2: lopsided with the pairing as printed (towards -x_k where beta^k > 0)
+    int32_t transfer;     // coarse-fine halo operators: 0 as printed in App. E; 1 injection + quadratic
 };
 
 // The lopsided fourth-order first derivatives of App. D, biased towards +x (points -1..+3) or

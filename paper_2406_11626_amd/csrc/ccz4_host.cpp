@@ -289,6 +289,7 @@ RhsParams to_rhs(const ccz4_params *p)
     r.shift = p->shift;
     r.formulation = p->formulation;
     r.advection = p->advection;
+    r.transfer = p->transfer;
     return r;
 }
 
@@ -301,6 +302,8 @@ ccz4_status check_params(const ccz4_params *p)
         return fail(CCZ4_EINVAL, "formulation must be 0 (first order) or 1 (second order)");
     if (p->advection < CCZ4_ADVECTION_CENTRAL || p->advection > CCZ4_ADVECTION_LOPSIDED_PRINTED)
         return fail(CCZ4_EINVAL, "advection must be 0 (central), 1 (lopsided, upwind) or 2 (lopsided, as printed)");
+    if (p->transfer != CCZ4_TRANSFER_APP_E && p->transfer != CCZ4_TRANSFER_HIGHER_ORDER)
+        return fail(CCZ4_EINVAL, "transfer must be 0 (App. E operators) or 1 (higher order)");
     if (!(p->tau > 0)) return fail(CCZ4_EINVAL, "tau must be > 0");
     return CCZ4_OK;
 }
@@ -475,11 +478,11 @@ ccz4_status ccz4_fill_halos_kinds(ccz4_ctx *c, double *Q, int32_t kinds, void *s
     ccz4_status st = check_ptr(Q, "Q");
     if (st) return st;
     if (kinds & ~CCZ4_FILL_ALL) return fail(CCZ4_EINVAL, "unknown fill kinds");
-    if (kinds & CCZ4_FILL_SAME_LEVEL) HIP_TRY(launch_fill(Q, c->d_phc.p, (int32_t)c->ph_copy.size(), S(stream)));
-    if (kinds & CCZ4_FILL_NEUMANN) HIP_TRY(launch_fill(Q, c->d_phn.p, (int32_t)c->ph_neu.size(), S(stream)));
+    if (kinds & CCZ4_FILL_SAME_LEVEL) HIP_TRY(launch_fill(Q, c->d_phc.p, (int32_t)c->ph_copy.size(), c->prm.transfer, S(stream)));
+    if (kinds & CCZ4_FILL_NEUMANN) HIP_TRY(launch_fill(Q, c->d_phn.p, (int32_t)c->ph_neu.size(), c->prm.transfer, S(stream)));
     if (kinds & CCZ4_FILL_LEVELS) {
-        HIP_TRY(launch_fill(Q, c->d_phr.p, (int32_t)c->ph_res.size(), S(stream)));
-        HIP_TRY(launch_fill(Q, c->d_php.p, (int32_t)c->ph_pro.size(), S(stream)));
+        HIP_TRY(launch_fill(Q, c->d_phr.p, (int32_t)c->ph_res.size(), c->prm.transfer, S(stream)));
+        HIP_TRY(launch_fill(Q, c->d_php.p, (int32_t)c->ph_pro.size(), c->prm.transfer, S(stream)));
     }
     return CCZ4_OK;
 }
@@ -719,15 +722,15 @@ ccz4_status ccz4_step_graph_create(ccz4_ctx *c, double *Qn, double *Q1, double *
     for (int s = 0; s < 4 && e == hipSuccess; ++s) {
         e = launch_stage(s, dt, src[s], Qn, acc, dst[s], c->d_geom.p, np, c->prm, precision, c->kernel[precision],
                          c->d_bf.p, c->d_bg.p, nbf, c->d_nbr.p, cs);
-        if (e == hipSuccess) e = launch_fill(dst[s], c->d_phn.p, (int32_t)c->ph_neu.size(), cs);
-        if (e == hipSuccess) e = launch_fill(dst[s], c->d_phr.p, (int32_t)c->ph_res.size(), cs);
-        if (e == hipSuccess) e = launch_fill(dst[s], c->d_php.p, (int32_t)c->ph_pro.size(), cs);
+        if (e == hipSuccess) e = launch_fill(dst[s], c->d_phn.p, (int32_t)c->ph_neu.size(), c->prm.transfer, cs);
+        if (e == hipSuccess) e = launch_fill(dst[s], c->d_phr.p, (int32_t)c->ph_res.size(), c->prm.transfer, cs);
+        if (e == hipSuccess) e = launch_fill(dst[s], c->d_php.p, (int32_t)c->ph_pro.size(), c->prm.transfer, cs);
         if (c->prm.formulation == CCZ4_FORMULATION_SECOND_ORDER) {
             // Algorithm 2: the auxiliaries of the new state from its primaries, then their halos
             if (e == hipSuccess) e = launch_reconstruct(dst[s], c->d_geom.p, np, c->d_nbr.p, cs);
-            if (e == hipSuccess) e = launch_fill(dst[s], c->d_phn.p, (int32_t)c->ph_neu.size(), cs);
-            if (e == hipSuccess) e = launch_fill(dst[s], c->d_phr.p, (int32_t)c->ph_res.size(), cs);
-            if (e == hipSuccess) e = launch_fill(dst[s], c->d_php.p, (int32_t)c->ph_pro.size(), cs);
+            if (e == hipSuccess) e = launch_fill(dst[s], c->d_phn.p, (int32_t)c->ph_neu.size(), c->prm.transfer, cs);
+            if (e == hipSuccess) e = launch_fill(dst[s], c->d_phr.p, (int32_t)c->ph_res.size(), c->prm.transfer, cs);
+            if (e == hipSuccess) e = launch_fill(dst[s], c->d_php.p, (int32_t)c->ph_pro.size(), c->prm.transfer, cs);
         }
     }
     hipError_t e2 = hipStreamEndCapture(cs, &g->graph);

@@ -195,7 +195,7 @@ __device__ __forceinline__ void ppar(int F, int &l, double &w0, double &w1)
 constexpr int SB8 = 8;
 
 __global__ __launch_bounds__(256) void k_fill(double *__restrict__ Q, const FaceTask *__restrict__ tasks,
-                                              int32_t ntask)
+                                              int32_t ntask, int32_t transfer)
 {
     const int ti = blockIdx.x;
     const int idx = threadIdx.x;
@@ -204,10 +204,17 @@ __global__ __launch_bounds__(256) void k_fill(double *__restrict__ Q, const Face
     int L, t1, t2;
     slab_coords(tk.axis, idx, L, t1, t2);
     double *dst = Q + (int64_t)tk.patch * PS + slab_off(tk.axis, ghost_c(tk.side, L), t1, t2);
-    if (tk.kind == FK_COPY || tk.kind == FK_NEUMANN) {
-        const double *src = tk.kind == FK_COPY
-                                ? Q + (int64_t)tk.src[0] * PS + slab_off(tk.axis, depth_c(-tk.side, L), t1, t2)
-                                : Q + (int64_t)tk.patch * PS + slab_off(tk.axis, depth_c(tk.side, 1), t1, t2);
+    const bool inject = tk.kind == FK_RESTRICT && transfer == 1;
+    if (tk.kind == FK_COPY || tk.kind == FK_NEUMANN || inject) {
+        // copies; with the higher-order operators the restriction is one too: coarse ghost c_{2+L}
+        // takes the fine cell with the same centre, tangentially the middle of the three fine
+        // cells under it, along the normal the fine interior depth 3L - 1
+        const int F1 = 3 * t1 + 1, F2 = 3 * t2 + 1;
+        const double *src =
+            tk.kind == FK_COPY ? Q + (int64_t)tk.src[0] * PS + slab_off(tk.axis, depth_c(-tk.side, L), t1, t2)
+            : inject ? Q + (int64_t)tk.src[(F2 / 9) * 3 + F1 / 9] * PS +
+                           slab_off(tk.axis, depth_c(-tk.side, 3 * L - 1), F1 % 9, F2 % 9)
+                     : Q + (int64_t)tk.patch * PS + slab_off(tk.axis, depth_c(tk.side, 1), t1, t2);
         for (int v0 = 0; v0 < NV; v0 += SB8) {
             double r[SB8];
 #pragma unroll
@@ -240,6 +247,41 @@ __global__ __launch_bounds__(256) void k_fill(double *__restrict__ Q, const Face
                 for (int n = 0; n < 9; ++n) sum += kid[v * CS + off[m][n]];
                 acc += wf[m] * (sum * (1.0 / 9.0));
             }
+            dst[v * CS] = acc;
+        }
+    } else if (transfer == 1) {  // FK_PROLONG, higher order
+        // three-point Lagrange quadratics along every axis.  Tangentially fine cell F sits at
+        // coarse coordinate u = (F + 1/2)/3 - 1/2, taken from the coarse centres l-1, l, l+1 with
+        // l the nearest one kept in 1..7; along the normal fine ghost L sits s = 1/2 - (L - 1/2)/3
+        // coarse cells from c2 towards the face, taken from c1, c2 and the restricted c3.
+        const double *cp = Q + (int64_t)tk.src[0] * PS;
+        const double sn = 0.5 - (L - 0.5) / 3.0;
+        const double wn[3] = {sn * (sn - 1.0) / 2.0, 1.0 - sn * sn, sn * (sn + 1.0) / 2.0};
+        const int cn[3] = {depth_c(-tk.side, 2), depth_c(-tk.side, 1), ghost_c(-tk.side, 1)};
+        int j[2];
+        double w[2][3];
+        const int F[2] = {9 * tk.o1 + t1, 9 * tk.o2 + t2};
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const double u = (F[d] + 0.5) / 3.0 - 0.5;
+            int l = (int)floor(u + 0.5);
+            l = l < 1 ? 1 : (l > 7 ? 7 : l);
+            const double s = u - l;
+            j[d] = l;
+            w[d][0] = s * (s - 1.0) / 2.0;
+            w[d][1] = 1.0 - s * s;
+            w[d][2] = s * (s + 1.0) / 2.0;
+        }
+        for (int v = 0; v < NV; ++v) {
+            const double *c = cp + v * CS;
+            double acc = 0.0;
+#pragma unroll
+            for (int kn = 0; kn < 3; ++kn)
+#pragma unroll
+                for (int k2 = 0; k2 < 3; ++k2)
+#pragma unroll
+                    for (int k1 = 0; k1 < 3; ++k1)
+                        acc += wn[kn] * w[1][k2] * w[0][k1] * c[slab_off(tk.axis, cn[kn], j[0] - 1 + k1, j[1] - 1 + k2)];
             dst[v * CS] = acc;
         }
     } else {  // FK_PROLONG
@@ -1144,10 +1186,10 @@ hipError_t launch_init(double *Q, const PatchGeom *geom, const uint8_t *bmask, i
     return hipGetLastError();
 }
 
-hipError_t launch_fill(double *Q, const FaceTask *tasks, int32_t ntask, hipStream_t st)
+hipError_t launch_fill(double *Q, const FaceTask *tasks, int32_t ntask, int32_t transfer, hipStream_t st)
 {
     if (ntask <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill, dim3(ntask), dim3(256), 0, st, Q, tasks, ntask);
+    hipLaunchKernelGGL(k_fill, dim3(ntask), dim3(256), 0, st, Q, tasks, ntask, transfer);
     return hipGetLastError();
 }
 

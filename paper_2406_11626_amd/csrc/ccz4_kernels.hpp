@@ -13,7 +13,7 @@ struct InitArgs {
 
 hipError_t launch_init(double *Q, const PatchGeom *geom, const uint8_t *bmask, int32_t npatch, int32_t scen,
                        const InitArgs &a, hipStream_t st);
-hipError_t launch_fill(double *Q, const FaceTask *tasks, int32_t ntask, hipStream_t st);
+hipError_t launch_fill(double *Q, const FaceTask *tasks, int32_t ntask, int32_t transfer, hipStream_t st);
 // right-hand side / fused stage launch configurations: bit 0 selects the LDS-staged kernel (else
 // the phased one), bit 1 the plain block order (else the XCD-grouped order)
 enum KernelVariant : int32_t { KV_PHASED = 0, KV_LDS = 1, KV_LINEAR = 2, KV_COUNT = 4 };

@@ -53,4 +53,7 @@ def test_argument_errors_without_gpu():
     bad = ccz4.params(formulation=2)
     assert L.ccz4_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(bad)) == ccz4.CCZ4_EINVAL
     assert b"formulation" in L.ccz4_last_error()
+    for bad, word in ((ccz4.params(advection=3), b"advection"), (ccz4.params(transfer=2), b"transfer")):
+        assert L.ccz4_create(ctypes.byref(h), ctypes.byref(g), ctypes.byref(bad)) == ccz4.CCZ4_EINVAL
+        assert word in L.ccz4_last_error()
     ccz4.ccz4_destroy(None)
