@@ -190,17 +190,24 @@ def run_gpu(args, w, precision, formulation=0, advection=0):
 
 
 def run_stability(args, w):
-    """First- against second-order formulation on the same workload, graph-launched steps until
-    t_end or the first non-finite value: L2 norms of the constraints (cells with r >= 1)
-    every `every` steps."""
+    """First- against second-order formulation on the same workload (or, with
+    --stability-transfer, the second-order formulation with the App. E against the higher-order
+    coarse-fine operators), graph-launched steps until t_end or the first non-finite value: L2
+    norms of the constraints (cells with r >= 1) every sample_dt."""
     import torch
     from paper_2406_11626_amd import ccz4
     dt = w.dt()
     nsteps = int(round(args.t_end / dt))
     every = max(1, int(round(args.sample_dt / dt)))
     out = {}
-    for form, name in ((0, "first_order"), (1, "second_order")):
-        prm = ccz4.params(**{**w.prm, "formulation": form})
+    if args.stability_transfer:  # second order with the App. E and the higher-order operators
+        variants = ((dict(formulation=1, transfer=0), "second_order_app_e_transfer"),
+                    (dict(formulation=1, transfer=1), "second_order_higher_order_transfer"))
+    else:
+        variants = ((dict(formulation=0), "first_order"), (dict(formulation=1), "second_order"))
+    for over, name in variants:
+        form = over["formulation"]
+        prm = ccz4.params(**{**w.prm, **over})
         ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, prm, w.refined)
         Q = ctx.new_state(0.0)
         ctx.init_patches(Q, w.scenario, w.scen)
@@ -363,6 +370,9 @@ def main():
                          "print the constraint norms")
     ap.add_argument("--tracker", action="store_true",
                     help="instead of timing: puncture trackers in the binary-puncture data up to --t-end")
+    ap.add_argument("--stability-transfer", action="store_true",
+                    help="with --stability: second order with the App. E against the higher-order coarse-fine "
+                         "operators")
     ap.add_argument("--t-end", type=float, default=10.0)
     ap.add_argument("--sample-dt", type=float, default=0.5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
