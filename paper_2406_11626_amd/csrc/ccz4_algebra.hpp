@@ -258,305 +258,6 @@ __device__ __forceinline__ void compute_geo(const double *__restrict__ q, const 
 
 }
 
-// First-order CCZ4 right-hand side of one cell (before Kreiss-Oliger dissipation).
-template <typename T>
-__device__ void ccz4_algebra(const double *__restrict__ q, const double (*__restrict__ dq)[NDIFF],
-                             const RhsParams &p, double *__restrict__ out)
-{
-    Geo<T> G;
-    compute_geo<T>(q, dq, G);
-    const double detg = G.detg, phid = G.phid, iphid = G.iphid;
-    const T(&g)[6] = G.g; const T(&ig)[6] = G.ig; const T(&At)[6] = G.At; const T(&D)[3][6] = G.D;
-    const T(&B)[3][3] = G.B; const T(&A)[3] = G.A; const T(&be)[3] = G.be; const T(&Gh)[3] = G.Gh;
-    const T(&bb)[3] = G.bb; const T al = G.al, Kt = G.Kt, Th = G.Th, K0 = G.K0;
-    const T(&Pphi)[3] = G.Pphi; const T(&Dup)[3][6] = G.Dup; const T(&Gt)[3][6] = G.Gt;
-    const T(&Gtv)[3] = G.Gtv; const T(&Wl)[3] = G.Wl; const T(&Gam)[3][6] = G.Gam; const T(&U)[3][3] = G.U;
-    const T(&Ric)[6] = G.Ric;
-    auto dv = [&](int a, int slot) -> T { return cvt<T>(dq[a][slot - DOFF]); };
-
-    const T kap1 = cvt<T>(p.kappa1), kap2 = cvt<T>(p.kappa2), kap3 = cvt<T>(p.kappa3);
-    const T cc = cvt<T>(p.c), ee2 = cvt<T>(p.e * p.e), mu = cvt<T>(p.mu), ff = cvt<T>(p.f),
-            eta = cvt<T>(p.eta);
-    const bool onelog = p.slicing == 1;
-    const bool gdrv = p.shift == 1;
-    const T ga = onelog ? T(2) / al : T(1);
-    const T ga_lin = onelog ? T(2) : T(2) * al;   // 2 alpha g + alpha^2 g'
-    const T trB = B[0][0] + B[1][1] + B[2][2];
-
-    // ---------------- Z4 quantities
-    // d_k Gt^i = -2 D_k^jl Gt^i_jl - 2 D_k^in W_n + gt^in F_kn,
-    // F_kn = gt^jl (d_k D_jln + d_j D_kln) - (gt^jl (d_k D_njl + d_n D_kjl))/2
-    T dGt[3][3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        T F[3];
-#pragma unroll
-        for (int n = 0; n < 3; ++n) {
-            T f = T(0);
-#pragma unroll
-            for (int jj = 0; jj < 3; ++jj)
-#pragma unroll
-                for (int l = 0; l < 3; ++l)
-                    f += ig[sym(jj, l)] * (dv(k, SD + 6 * jj + sym(l, n)) + dv(jj, SD + 6 * k + sym(l, n)));
-            F[n] = f - T(0.5) * (U[k][n] + U[n][k]);
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            T t = T(0);
-#pragma unroll
-            for (int s = 0; s < 6; ++s) t += (s == 0 || s == 3 || s == 5 ? T(1) : T(2)) * Dup[k][s] * Gt[i][s];
-            t = T(-2) * t;
-            t += T(-2) * (Dup[k][sym(i, 0)] * Wl[0] + Dup[k][sym(i, 1)] * Wl[1] + Dup[k][sym(i, 2)] * Wl[2]);
-            t += ig[sym(i, 0)] * F[0] + ig[sym(i, 1)] * F[1] + ig[sym(i, 2)] * F[2];
-            dGt[k][i] = t;
-        }
-    }
-    T dG[3];  // Ghat - Gt
-#pragma unroll
-    for (int i = 0; i < 3; ++i) dG[i] = Gh[i] - Gtv[i];
-    T Zl[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) Zl[i] = T(0.5) * (g[sym(i, 0)] * dG[0] + g[sym(i, 1)] * dG[1] + g[sym(i, 2)] * dG[2]);
-    const T phi = cvt<T>(phid);
-    const T phi2 = cvt<T>(phid * phid);
-    T Zu[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) Zu[i] = T(0.5) * phi2 * dG[i];
-    // nabla_i Z_j
-    T nZ[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            T t = D[i][sym(j, 0)] * dG[0] + D[i][sym(j, 1)] * dG[1] + D[i][sym(j, 2)] * dG[2];
-#pragma unroll
-            for (int l = 0; l < 3; ++l)
-                t += T(0.5) * g[sym(j, l)] * (dv(i, SGHAT + l) - dGt[i][l]) - Gam[l][sym(i, j)] * Zl[l];
-            nZ[i][j] = t;
-        }
-    // nabla_i nabla_j alpha
-    T DDa[6];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j)
-            DDa[sym(i, j)] = T(0.5) * (dv(i, SA + j) + dv(j, SA + i)) -
-                             (Gam[0][sym(i, j)] * A[0] + Gam[1][sym(i, j)] * A[1] + Gam[2][sym(i, j)] * A[2]);
-    // traces with the conformal metric
-    auto trace = [&](const T *X) -> T {
-        return ig[0] * X[0] + ig[3] * X[3] + ig[5] * X[5] + T(2) * (ig[1] * X[1] + ig[2] * X[2] + ig[4] * X[4]);
-    };
-    T Xs[6];  // -nabla nabla alpha + alpha (R_ij + 2 nabla_(i Z_j))
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j) {
-            const int ij = sym(i, j);
-            Xs[ij] = -DDa[ij] + al * (Ric[ij] + nZ[i][j] + nZ[j][i]);
-        }
-    T RZs[6];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j) RZs[sym(i, j)] = Ric[sym(i, j)] + nZ[i][j] + nZ[j][i];
-    const T RpZ = phi2 * trace(RZs);
-    const T trX = trace(Xs);
-    const T lapal = phi2 * trace(DDa);
-    const T trAt = trace(At);
-
-    // At^ij, At_ij At^ij
-    T Am[3][3];  // gt^ik At_kj
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-            Am[i][j] = ig[sym(i, 0)] * At[sym(0, j)] + ig[sym(i, 1)] * At[sym(1, j)] + ig[sym(i, 2)] * At[sym(2, j)];
-    T Aup[6];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j)
-            Aup[sym(i, j)] = Am[i][0] * ig[sym(0, j)] + Am[i][1] * ig[sym(1, j)] + Am[i][2] * ig[sym(2, j)];
-    T AA = T(0);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) AA += Am[i][j] * Am[j][i];
-
-    // derivative traces: trdAt_k = gt^nm d_k At_nm ; DA_k = D_k^nm At_nm ; sdBtr_k = d_(k B_l)^l
-    T trdAt[3], DA[3], sdBtr[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        T dA6[6];
-#pragma unroll
-        for (int s = 0; s < 6; ++s) dA6[s] = dv(k, SAT + s);
-        trdAt[k] = trace(dA6);
-        DA[k] = Dup[k][0] * At[0] + Dup[k][3] * At[3] + Dup[k][5] * At[5] +
-                T(2) * (Dup[k][1] * At[1] + Dup[k][2] * At[2] + Dup[k][4] * At[4]);
-        T t = T(0);
-#pragma unroll
-        for (int l = 0; l < 3; ++l) t += dv(k, SB + 3 * l + l) + dv(l, SB + 3 * k + l);
-        sdBtr[k] = T(0.5) * t;
-    }
-    const T sfac = gdrv ? T(1) : T(0);
-
-    // ---------------- gt_ij
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j) {
-            const int ij = sym(i, j);
-            T t = T(2) * (be[0] * D[0][ij] + be[1] * D[1][ij] + be[2] * D[2][ij]);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) t += g[sym(k, i)] * B[j][k] + g[sym(k, j)] * B[i][k];
-            t += T(-2.0 / 3.0) * g[ij] * trB;
-            t += T(-2) * al * (At[ij] - T(1.0 / 3.0) * g[ij] * trAt);
-            out[SG + ij] = static_cast<double>(t) - (detg - 1.0) / p.tau * q[SG + ij];
-        }
-    // ---------------- alpha
-    const T thetaterm = Kt - K0 - T(2) * cc * Th;
-    out[SALPHA] = static_cast<double>(be[0] * A[0] + be[1] * A[1] + be[2] * A[2] - al * al * ga * thetaterm);
-    // ---------------- beta^i
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-        out[SBETA + i] = gdrv ? static_cast<double>(be[0] * B[0][i] + be[1] * B[1][i] + be[2] * B[2][i] + ff * bb[i]) : 0.0;
-    // ---------------- phi (phi factor applied in double)
-    out[SPHI] = q[SBETA] * q[SP] + q[SBETA + 1] * q[SP + 1] + q[SBETA + 2] * q[SP + 2] +
-                phid * static_cast<double>((al * Kt - trB) * T(1.0 / 3.0));
-    // ---------------- At_ij
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = i; j < 3; ++j) {
-            const int ij = sym(i, j);
-            T t = be[0] * dv(0, SAT + ij) + be[1] * dv(1, SAT + ij) + be[2] * dv(2, SAT + ij);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) t += At[sym(k, i)] * B[j][k] + At[sym(k, j)] * B[i][k];
-            t += T(-2.0 / 3.0) * At[ij] * trB;
-            t += al * At[ij] * (Kt - T(2) * Th * cc);
-            t += T(-2) * al * (At[sym(i, 0)] * Am[0][j] + At[sym(i, 1)] * Am[1][j] + At[sym(i, 2)] * Am[2][j]);
-            const T tf = Xs[ij] - T(1.0 / 3.0) * g[ij] * trX;
-            out[SAT + ij] = static_cast<double>(t) + phid * phid * static_cast<double>(tf);
-        }
-    // ---------------- K
-    out[SK] = static_cast<double>(be[0] * dv(0, SK) + be[1] * dv(1, SK) + be[2] * dv(2, SK) - lapal + al * RpZ +
-                                  al * Kt * (Kt - T(2) * Th * cc) - T(3) * al * kap1 * (T(1) + kap2) * Th);
-    // ---------------- Theta
-    out[STHETA] = static_cast<double>(be[0] * dv(0, STHETA) + be[1] * dv(1, STHETA) + be[2] * dv(2, STHETA) +
-                                      T(0.5) * al * ee2 * (RpZ + T(2.0 / 3.0) * Kt * Kt - AA) - al * Th * Kt * cc -
-                                      (Zu[0] * A[0] + Zu[1] * A[1] + Zu[2] * A[2]) - al * kap1 * (T(2) + kap2) * Th);
-    // ---------------- Ghat^i and b^i
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        T t = be[0] * dv(0, SGHAT + i) + be[1] * dv(1, SGHAT + i) + be[2] * dv(2, SGHAT + i);
-        T u = T(0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const T igik = ig[sym(i, k)];
-            t += T(2) * al * igik * dv(k, STHETA);
-            if (!p.formulation) t += T(2) * al * igik * (trdAt[k] - T(2) * DA[k]);  // constraint additions
-            t += T(-4.0 / 3.0) * al * igik * dv(k, SK);
-            t += sfac * T(1.0 / 3.0) * igik * sdBtr[k];
-            t += T(-2) * igik * (Th * A[k] + T(2.0 / 3.0) * al * Kt * Zl[k]);
-            t += T(-2) * al * kap1 * igik * Zl[k];
-            u += igik * Zl[k];
-#pragma unroll
-            for (int l = 0; l < 3; ++l) t += ig[sym(k, l)] * T(0.5) * (dv(k, SB + 3 * l + i) + dv(l, SB + 3 * k + i));
-        }
-        t += T(2.0 / 3.0) * Gtv[i] * trB - (Gtv[0] * B[0][i] + Gtv[1] * B[1][i] + Gtv[2] * B[2][i]);
-        T ga2 = Gt[i][0] * Aup[0] + Gt[i][3] * Aup[3] + Gt[i][5] * Aup[5] +
-                T(2) * (Gt[i][1] * Aup[1] + Gt[i][2] * Aup[2] + Gt[i][4] * Aup[4]);
-        ga2 -= T(3) * (Aup[sym(i, 0)] * Pphi[0] + Aup[sym(i, 1)] * Pphi[1] + Aup[sym(i, 2)] * Pphi[2]);
-        t += T(2) * al * ga2;
-        t += T(-2) * (Aup[sym(i, 0)] * A[0] + Aup[sym(i, 1)] * A[1] + Aup[sym(i, 2)] * A[2]);
-        // 2 kappa3 (2/3 gt^ij Z_j trB - gt^jk Z_j B_k^i)
-        T zb = T(0);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const T zk = ig[sym(k, 0)] * Zl[0] + ig[sym(k, 1)] * Zl[1] + ig[sym(k, 2)] * Zl[2];
-            zb += zk * B[k][i];
-        }
-        t += T(2) * kap3 * (T(2.0 / 3.0) * u * trB - zb);
-        out[SGHAT + i] = static_cast<double>(t);
-        const T bt = be[0] * (dv(0, SBB + i) - dv(0, SGHAT + i)) + be[1] * (dv(1, SBB + i) - dv(1, SGHAT + i)) +
-                     be[2] * (dv(2, SBB + i) - dv(2, SGHAT + i)) - eta * bb[i];
-        out[SBB + i] = gdrv ? static_cast<double>(t + bt) : 0.0;
-    }
-    // ---------------- A_k
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        T t = be[0] * dv(0, SA + k) + be[1] * dv(1, SA + k) + be[2] * dv(2, SA + k);
-        t += -al * al * ga * (dv(k, SK) - T(2) * cc * dv(k, STHETA));
-        t += -al * ga * (trdAt[k] - T(2) * DA[k]);                          // constraint additions
-        t += B[k][0] * A[0] + B[k][1] * A[1] + B[k][2] * A[2];
-        t += -ga_lin * thetaterm * A[k];
-        out[SA + k] = static_cast<double>(t);
-    }
-    // ---------------- B_k^i
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            if (!gdrv) {
-                out[SB + 3 * k + i] = 0.0;
-                continue;
-            }
-            T t = be[0] * dv(0, SB + 3 * k + i) + be[1] * dv(1, SB + 3 * k + i) + be[2] * dv(2, SB + 3 * k + i);
-            t += ff * dv(k, SBB + i);
-            t += B[k][0] * B[0][i] + B[k][1] * B[1][i] + B[k][2] * B[2][i];
-            // curl terms: -alpha^2 mu gt^ij (d_k P_j - d_j P_k)/phi + alpha^2 mu gt^ij gt^nl (d_k D_ljn - d_l D_kjn)
-            T cP = T(0), cD = T(0);
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                cP += ig[sym(i, j)] * cvt<T>((dq[k][SP - DOFF + j] - dq[j][SP - DOFF + k]) * iphid);
-                T s = T(0);
-#pragma unroll
-                for (int n = 0; n < 3; ++n)
-#pragma unroll
-                    for (int l = 0; l < 3; ++l)
-                        s += ig[sym(n, l)] * (dv(k, SD + 6 * l + sym(j, n)) - dv(l, SD + 6 * k + sym(j, n)));
-                cD += ig[sym(i, j)] * s;
-            }
-            t += al * al * mu * (cD - cP);
-            out[SB + 3 * k + i] = static_cast<double>(t);
-        }
-    // ---------------- D_kij
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = i; j < 3; ++j) {
-                const int ij = sym(i, j);
-                T t = be[0] * dv(0, SD + 6 * k + ij) + be[1] * dv(1, SD + 6 * k + ij) + be[2] * dv(2, SD + 6 * k + ij);
-                T sb = T(0);
-#pragma unroll
-                for (int m = 0; m < 3; ++m)
-                    sb += g[sym(m, i)] * (dv(k, SB + 3 * j + m) + dv(j, SB + 3 * k + m)) +
-                          g[sym(m, j)] * (dv(k, SB + 3 * i + m) + dv(i, SB + 3 * k + m));
-                t += sfac * (T(0.25) * sb - T(1.0 / 3.0) * g[ij] * sdBtr[k]);
-                t += -al * dv(k, SAT + ij);
-                t += al * T(1.0 / 3.0) * g[ij] * (trdAt[k] - T(2) * DA[k]);    // constraint additions
-#pragma unroll
-                for (int l = 0; l < 3; ++l)
-                    t += B[k][l] * D[l][ij] + B[j][l] * D[k][sym(l, i)] + B[i][l] * D[k][sym(l, j)];
-                t += T(-2.0 / 3.0) * trB * D[k][ij];
-                t += -A[k] * (At[ij] - T(1.0 / 3.0) * g[ij] * trAt);
-                out[SD + 6 * k + ij] = static_cast<double>(t);
-            }
-    // ---------------- P_k (phi factors applied in double)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        T t = be[0] * dv(0, SP + k) + be[1] * dv(1, SP + k) + be[2] * dv(2, SP + k);
-        t += B[k][0] * cvt<T>(q[SP]) + B[k][1] * cvt<T>(q[SP + 1]) + B[k][2] * cvt<T>(q[SP + 2]);
-        t += T(1.0 / 3.0) * (al * Kt - trB) * cvt<T>(q[SP + k]);
-        const T phipart = T(1.0 / 3.0) * (al * dv(k, SK) - sdBtr[k]) + T(1.0 / 3.0) * al * (trdAt[k] - T(2) * DA[k]) +
-                          T(1.0 / 3.0) * Kt * A[k];
-        out[SP + k] = static_cast<double>(t) + phid * static_cast<double>(phipart);
-    }
-    out[SK0] = 0.0;
-}
-
 // Hamiltonian and momentum constraints of one cell (App. B):
 //   H = phi^2 gt^ij R_ij + 2/3 K^2 - At_ij At^ij,
 //   M_i = gt^kl d_k At_li - Am^l_m Gt^m_li - Gt^m At_im - 3 P^k At_ik / phi - 2/3 d_i K,
