@@ -41,6 +41,13 @@ def stage_bytes_per_cell(s):
     return QS_BYTES_PER_CELL + STREAM_BYTES_PER_CELL[s]
 
 
+# Standalone right-hand side, bytes per interior cell: the 58 evolved slots over the interior and
+# face halos (2187 cell-vectors per 729 cells) plus K_0 pointwise, and the 59 slots of k written.
+RHS_BYTES_PER_CELL = QS_BYTES_PER_CELL + 8 * NV
+# the same with every cell-vector read once (no halo duplication): the ideal lower bound
+RHS_IDEAL_BYTES_PER_CELL = 2 * 8 * NV
+
+
 def stage_bytes(s, cells, same_level_faces):
     return stage_bytes_per_cell(s) * cells + HALO_BYTES_PER_FACE * same_level_faces
 
@@ -169,15 +176,28 @@ def run_gpu(args, w, precision, formulation=0, advection=0):
     graph.close()
     cells = ctx.n_patches * 729
     nsame = ctx.plan_counts()["same_level"]
+    # the standalone right-hand side on the final state (its own kernel, same launch configuration)
+    rhs_ms = None
+    if precision == ccz4.PREC_FP64 and not so:
+        kbuf = ctx.new_state(0.0)
+        ctx.rhs(Q, kbuf, precision, stream)
+        r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        r0.record(stream)
+        for _ in range(5):
+            ctx.rhs(Q, kbuf, precision, stream)
+        r1.record(stream)
+        torch.cuda.synchronize()
+        rhs_ms = r0.elapsed_time(r1) / 5
+        del kbuf
     stage_ms = [a.elapsed_time(b) for _, a, b in events]
     launch_bytes = [stage_bytes(s, cells, nsame) for s, _, _ in events]
     norms, st = ctx.constraints(Q, r_excise=1.0)
     kc = ctx.get_kernel(precision)
     kname = ("k_stage_lds" if kc & ccz4.KERNEL_LDS else "k_stage") + \
-        ("<double>" if precision == ccz4.PREC_FP64 else "<float>") + \
+        ("<double, " if precision == ccz4.PREC_FP64 else "<float, ") + ("1>" if advection else "0>") + \
         (" (plain block order)" if kc & ccz4.KERNEL_LINEAR_ORDER else "")
     recon_ms = [a.elapsed_time(b) for a, b in recon_events]
-    out = dict(wall=wall, wall_eager=wall_eager, tune_ms=tune_ms, cells=cells, patches=ctx.n_patches,
+    out = dict(wall=wall, wall_eager=wall_eager, tune_ms=tune_ms, cells=cells, patches=ctx.n_patches, rhs_ms=rhs_ms,
                reconstruct_ms=sum(recon_ms) / len(recon_ms) if recon_ms else None,
                stage_ms=sum(stage_ms) / len(stage_ms),
                stage_bytes=sum(launch_bytes) / len(launch_bytes),
@@ -447,6 +467,14 @@ def main():
                      "algorithmic_bytes_per_launch": r64["stage_bytes"]},
         "constraints_after": {"L2_H": r64["norms"][0], "L2_M": r64["norms"][1], "nonfinite": r64["norms"][2]},
     }
+    if r64["rhs_ms"]:
+        rb = RHS_BYTES_PER_CELL * r64["cells"]
+        gbs = rb / (r64["rhs_ms"] * 1e-3) / 1e9
+        line["rhs_kernel"] = {"kernel": r64["kernel"].replace("k_stage", "k_rhs"), "avg_ms": r64["rhs_ms"],
+                              "algorithmic_bytes_per_launch": rb, "achieved": gbs, "unit": "GB/s",
+                              "frac": gbs / HBM_PEAK_GBS, "frac_of_copy": gbs / copy_gbs,
+                              "frac_ideal_bytes": RHS_IDEAL_BYTES_PER_CELL * r64["cells"] /
+                              (r64["rhs_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
     if not args.no_mixed:
         rm = run_gpu(args, w, 1)
         vm = rm["cells"] * stages / rm["wall"]
