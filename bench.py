@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 NV = 59
 # Fused stage, bytes per interior cell.  Q_s: the 58 evolved slots with interior + face halos
 # (2187 cell-vectors per 729 cells) and K_0 pointwise.  Streamed, per stage s:
@@ -53,6 +54,7 @@ def stage_bytes(s, cells, same_level_faces):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_lds_puncture16_hbm_traffic.md")
+FLOPS_FILE = os.path.join(ROOT, "profiles", "k_stage_lds_puncture16_fp64_ops.md")
 
 
 def kernel_source_digest():
@@ -67,24 +69,49 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(config):
-    """HBM bytes per launch of the fused stage kernel from the committed counter summary, or None
-    when there is none, when it covers another workload, or when the kernel sources have changed
-    since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def _profile_record(path, config):
+    """The "- key: value" lines of a committed counter summary, or None when there is none, when it
+covers another workload, or when the kernel sources have changed since the counters were taken."""
+    if not os.path.exists(path):
         return None
     rec = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for ln in f:
             if ln.startswith("- ") and ":" in ln:
                 k, v = ln[2:].split(":", 1)
                 rec[k.strip()] = v.strip().strip("`")
     if rec.get("source_sha256") != kernel_source_digest() or rec.get("workload_config") != str(config):
         return None
+    return rec
+
+
+def _record_float(rec, key):
     try:
-        return float(rec["hbm_bytes_per_launch"])
+        return float(rec[key]) if rec is not None else None
     except (KeyError, ValueError):
         return None
+
+
+def measured_traffic(config):
+    """HBM bytes per launch of the fused stage kernel from the committed counter summary."""
+    return _record_float(_profile_record(TRAFFIC_FILE, config), "hbm_bytes_per_launch")
+
+
+def measured_fp64_ops(config):
+    """FP64 operations per launch of the fused stage kernel and of the standalone right-hand side
+    (64 lanes x (ADD + MUL + 2 FMA + TRANS) wave instructions) from the committed counter summary."""
+    rec = _profile_record(FLOPS_FILE, config)
+    return _record_float(rec, "fp64_ops_per_stage_launch"), _record_float(rec, "fp64_ops_per_rhs_launch")
+
+
+def fp64_rate(ops, avg_ms):
+    """Achieved FP64 rate of a kernel from its counted operations per launch and its live average
+    launch duration, against the FP64 vector peak; None without a valid counter summary."""
+    if ops is None or not avg_ms:
+        return None
+    t = ops / (avg_ms * 1e-3) / 1e12
+    return {"ops_per_launch": ops, "achieved": t, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": t / FP64_PEAK_TFLOPS}
 
 
 def copy_bandwidth(nbytes=2**30, reps=10):
@@ -441,6 +468,7 @@ def main():
     stages = 4 * args.steps
     value = r64["cells"] * stages / r64["wall"]
     traffic = measured_traffic(args.config)
+    ops_stage, ops_rhs = measured_fp64_ops(args.config)
     copy_gbs = copy_bandwidth()
     line = {
         "metric": "CCZ4 cell-updates/s per RK4 stage (FP64 vs mixed), % of FP64/HBM roofline",
@@ -464,7 +492,8 @@ def main():
                      "frac": r64["stage_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": r64["kernel"], "avg_ms": r64["stage_ms"],
                      "copy_gbs": copy_gbs, "frac_of_copy": r64["stage_gbs"] / copy_gbs,
-                     "algorithmic_bytes_per_launch": r64["stage_bytes"]},
+                     "algorithmic_bytes_per_launch": r64["stage_bytes"],
+                     "fp64": fp64_rate(ops_stage, r64["stage_ms"])},
         "constraints_after": {"L2_H": r64["norms"][0], "L2_M": r64["norms"][1], "nonfinite": r64["norms"][2]},
     }
     if r64["rhs_ms"]:
@@ -474,7 +503,8 @@ def main():
                               "algorithmic_bytes_per_launch": rb, "achieved": gbs, "unit": "GB/s",
                               "frac": gbs / HBM_PEAK_GBS, "frac_of_copy": gbs / copy_gbs,
                               "frac_ideal_bytes": RHS_IDEAL_BYTES_PER_CELL * r64["cells"] /
-                              (r64["rhs_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                              (r64["rhs_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "fp64": fp64_rate(ops_rhs, r64["rhs_ms"])}
     if not args.no_mixed:
         rm = run_gpu(args, w, 1)
         vm = rm["cells"] * stages / rm["wall"]
