@@ -49,8 +49,32 @@ RHS_BYTES_PER_CELL = QS_BYTES_PER_CELL + 8 * NV
 RHS_IDEAL_BYTES_PER_CELL = 2 * 8 * NV
 
 
-def stage_bytes(s, cells, same_level_faces):
-    return stage_bytes_per_cell(s) * cells + HALO_BYTES_PER_FACE * same_level_faces
+def stage_bytes(s, cells, pushed_faces):
+    """Algorithmic bytes of one fused stage launch with pushed_faces same-level face halos written
+    (a stage that reads some same-level halos from the neighbours reads the same cell-vectors as
+    one that reads its own halos)."""
+    return stage_bytes_per_cell(s) * cells + HALO_BYTES_PER_FACE * pushed_faces
+
+
+def same_level_faces_per_axis(ctx):
+    """Number of leaf faces per axis whose neighbour across the face is a leaf of the same level
+    (each counted from both sides), from the context's leaf table (level, i, j, k)."""
+    from paper_2406_11626_amd import ccz4
+    ids = [tuple(int(v) for v in r) for r in ctx.ids]
+    leaves = set(ids)
+    count = [0, 0, 0]
+    for lev, *c in ids:
+        n = [v * 3 ** lev for v in ctx.n0]
+        for a in range(3):
+            for d in (-1, 1):
+                q = list(c)
+                q[a] += d
+                if ctx.bc == ccz4.BC_PERIODIC:
+                    q[a] %= n[a]
+                elif not 0 <= q[a] < n[a]:
+                    continue
+                count[a] += (lev, *q) in leaves
+    return count
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_lds_puncture16_hbm_traffic.md")
@@ -162,10 +186,11 @@ def run_gpu(args, w, precision, formulation=0, advection=0):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-            ctx.rhs_rk4_stage(s, dt, src, Q, acc, dst, precision, ccz4.STAGE_FILL_SAME_LEVEL, stream)
+            fl = ctx.step_stage_flags(s, precision)
+            ctx.rhs_rk4_stage(s, dt, src, Q, acc, dst, precision, fl, stream)
             if timed:
                 e1.record(stream)
-                events.append((s, e0, e1))
+                events.append((s, e0, e1, fl))
             if so:
                 ctx.fill_halos_kinds(dst, rest, stream)
                 if timed:
@@ -202,7 +227,12 @@ def run_gpu(args, w, precision, formulation=0, advection=0):
     wall = time.perf_counter() - t0
     graph.close()
     cells = ctx.n_patches * 729
-    nsame = ctx.plan_counts()["same_level"]
+    faces = same_level_faces_per_axis(ctx)
+    assert sum(faces) == ctx.plan_counts()["same_level"]
+
+    def pushed(fl):
+        return sum(faces) if fl & ccz4.STAGE_FILL_SAME_LEVEL else (
+            faces[0] if fl & ccz4.STAGE_FILL_SAME_LEVEL_X else 0)
     # the standalone right-hand side on the final state (its own kernel, same launch configuration)
     rhs_ms = None
     if precision == ccz4.PREC_FP64 and not so:
@@ -216,8 +246,8 @@ def run_gpu(args, w, precision, formulation=0, advection=0):
         torch.cuda.synchronize()
         rhs_ms = r0.elapsed_time(r1) / 5
         del kbuf
-    stage_ms = [a.elapsed_time(b) for _, a, b in events]
-    launch_bytes = [stage_bytes(s, cells, nsame) for s, _, _ in events]
+    stage_ms = [a.elapsed_time(b) for _, a, b, _ in events]
+    launch_bytes = [stage_bytes(s, cells, pushed(fl)) for s, _, _, fl in events]
     norms, st = ctx.constraints(Q, r_excise=1.0)
     kc = ctx.get_kernel(precision)
     kname = ("k_stage_lds" if kc & ccz4.KERNEL_LDS else "k_stage") + \

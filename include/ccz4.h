@@ -174,19 +174,35 @@ ccz4_status ccz4_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double *Qn
 /* Fused stage.  One launch over every leaf of every level: the right-hand
    side of Qs exactly as ccz4_rhs computes it, folded slot by slot into stage s of RK4 exactly as
    ccz4_rk4_stage combines it (interior cells and Sommerfeld ghosts; projection at s = 3), without
-   storing the right-hand side.  Qs needs filled halos.  Qnext must not alias Qs (other cells
-   still read it), may alias Qn only at s = 3; acc aliases none of them.  A step is
-   s = 0: (Qn -> Q1), 1: (Q1 -> Q2), 2: (Q2 -> Q1), 3: (Q1 -> Qn), each after a halo fill.
-   flags: 0, or CCZ4_STAGE_FILL_SAME_LEVEL: the stage also writes every new interior value that
-   lies within three layers of a face shared with a same-level leaf into that leaf's face halo
-   of Qnext (what CCZ4_FILL_SAME_LEVEL would copy there afterwards), so that before the next
-   stage only ccz4_fill_halos_kinds(NEUMANN | LEVELS) remains; Qnext's halos are then complete
-   once that runs.  EINVAL on unknown flags.  In the second-order formulation the interior
-   slots of A, B, D, P in acc and Qnext are not written: after the halo fill of Qnext, call
-   ccz4_reconstruct_aux on it (and fill again). */
-enum { CCZ4_STAGE_FILL_SAME_LEVEL = 1 };
+   storing the right-hand side.  Qnext must not alias Qs (other cells still read it), may alias
+   Qn only at s = 3; acc aliases none of them.  acc is a state-sized accumulator private to this
+   call: its layout (interior cells slab by slab, then the Sommerfeld ghost slabs, so that every
+   access covers whole cache lines) is not the state layout, and only s = 0 needs no prior
+   contents; it is not interchangeable with the acc of ccz4_rk4_stage.  A step is
+   s = 0: (Qn -> Q1), 1: (Q1 -> Q2), 2: (Q2 -> Q1), 3: (Q1 -> Qn).  flags, any combination of:
+     CCZ4_STAGE_FILL_SAME_LEVEL: the stage also writes every new interior value that lies within
+       three layers of a face shared with a same-level leaf into that leaf's face halo of Qnext
+       (what CCZ4_FILL_SAME_LEVEL would copy there afterwards);
+     CCZ4_STAGE_FILL_SAME_LEVEL_X: the same for the faces normal to x only;
+     CCZ4_STAGE_GATHER_SAME_LEVEL: the stage reads every y and z face halo of Qs that a same-level
+       leaf covers straight from that leaf's interior, so those halos of Qs need not be filled
+       (all other halos must be).  LDS kernel only (EINVAL if the context's kernel for this
+       precision is the phased one).
+   Without GATHER, Qs needs filled halos.  EINVAL on unknown flags.  In the second-order
+   formulation the interior slots of A, B, D, P in acc and Qnext are not written: after the halo
+   fill of Qnext, call ccz4_reconstruct_aux on it (and fill again). */
+enum { CCZ4_STAGE_FILL_SAME_LEVEL = 1, CCZ4_STAGE_GATHER_SAME_LEVEL = 2, CCZ4_STAGE_FILL_SAME_LEVEL_X = 4 };
 ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double *Qs, const double *Qn,
                                double *acc, double *Qnext, int32_t precision, int32_t flags, void *stream);
+
+/* The flags the step graph passes to stage s (0..3) with the context's current kernel for this
+   precision, into *flags (host).  First-order formulation with the LDS kernel: GATHER at every
+   stage, FILL_SAME_LEVEL_X at s = 0..2 and FILL_SAME_LEVEL at s = 3 (between stages only the
+   x-face halos are copied; the y and z ones are read from the neighbours, and the step leaves
+   complete halos).  Otherwise FILL_SAME_LEVEL at every stage.  Between stages only
+   ccz4_fill_halos_kinds(NEUMANN | LEVELS) is needed either way, and Qn must enter the step with
+   filled halos.  EINVAL on a NULL pointer, bad precision or stage. */
+ccz4_status ccz4_step_stage_flags(ccz4_ctx *ctx, int32_t precision, int32_t s, int32_t *flags);
 
 /* Second-order formulation, explicit gradient reconstruction (Sec. 3.2 and Algorithm 2): on every
    interior cell of every leaf, A_k = d_k alpha, B_k^i = d_k beta^i, D_kij = d_k gt_ij / 2 and
@@ -237,19 +253,19 @@ typedef enum { CCZ4_KERNEL_PHASED = 0, CCZ4_KERNEL_LDS = 1, CCZ4_KERNEL_LINEAR_O
 ccz4_status ccz4_set_kernel(ccz4_ctx *ctx, int32_t precision, int32_t kernel);
 ccz4_status ccz4_get_kernel(const ccz4_ctx *ctx, int32_t precision, int32_t *kernel);
 
-/* Autotuner: times one fused stage (s = 1, with CCZ4_STAGE_FILL_SAME_LEVEL) of every launch
-   configuration (0..3 above) on this context's mesh, `reps` launches each after one warm-up,
+/* Autotuner: times one fused stage (s = 1, with the flags ccz4_step_stage_flags gives that
+   configuration) of every launch configuration (0..3 above) on this context's mesh, `reps` launches each after one warm-up,
    with events on `stream`, and selects the fastest for `precision`.  Q: a state with filled
    halos (read only); acc and Qx: state-sized scratch (overwritten).  ms (host, may be NULL)
    receives the four average launch times in milliseconds.  Synchronises `stream`. */
 ccz4_status ccz4_autotune(ccz4_ctx *ctx, const double *Q, double *acc, double *Qx, int32_t precision,
                           int32_t reps, double *ms, void *stream);
 
-/* A fused RK4 step captured as a HIP graph: the four stages of ccz4_rhs_rk4_stage with
-   CCZ4_STAGE_FILL_SAME_LEVEL, (Qn -> Q1), (Q1 -> Q2), (Q2 -> Q1), (Q1 -> Qn), each followed by
-   ccz4_fill_halos_kinds(NEUMANN | LEVELS) of its output (in the second-order formulation then
-   ccz4_reconstruct_aux with CCZ4_STAGE_FILL_SAME_LEVEL and the same fill again), with the launch configuration current at
-   creation.  Buffers and dt are fixed at creation; Qn must enter each launch with all halos filled
+/* A fused RK4 step captured as a HIP graph: the four stages of ccz4_rhs_rk4_stage with the
+   flags of ccz4_step_stage_flags, (Qn -> Q1), (Q1 -> Q2), (Q2 -> Q1), (Q1 -> Qn), each followed
+   by ccz4_fill_halos_kinds(NEUMANN | LEVELS) of its output (in the second-order formulation then
+   ccz4_reconstruct_aux with CCZ4_STAGE_FILL_SAME_LEVEL and the same fill again), with the launch
+   configuration current at creation.  Buffers and dt are fixed at creation; Qn must enter each launch with all halos filled
    and leaves with them filled.  The graph uses the context's tables: destroy it before the
    context.  Launch is asynchronous on `stream`. */
 typedef struct ccz4_graph ccz4_graph;

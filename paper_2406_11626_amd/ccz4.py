@@ -21,7 +21,7 @@ ADVECTION_CENTRAL, ADVECTION_LOPSIDED_UPWIND, ADVECTION_LOPSIDED_PRINTED = 0, 1,
 TRANSFER_APP_E, TRANSFER_HIGHER_ORDER = 0, 1
 KERNEL_PHASED, KERNEL_LDS, KERNEL_LINEAR_ORDER = 0, 1, 2
 FILL_SAME_LEVEL, FILL_NEUMANN, FILL_LEVELS, FILL_ALL = 1, 2, 4, 7
-STAGE_FILL_SAME_LEVEL = 1
+STAGE_FILL_SAME_LEVEL, STAGE_GATHER_SAME_LEVEL, STAGE_FILL_SAME_LEVEL_X = 1, 2, 4
 MLP_NIN, MLP_NH, MLP_NOUT, MLP_NPARAM = 81, 64, 3, 9603
 SCEN_GAUGE_WAVE, SCEN_PUNCTURE, SCEN_BL_BY = 0, 1, 2
 
@@ -85,6 +85,7 @@ def lib():
             "ccz4_rhs": (i32, [P, P, P, i32, P]),
             "ccz4_rk4_stage": (i32, [P, i32, f64, P, P, P, P, P]),
             "ccz4_rhs_rk4_stage": (i32, [P, i32, f64, P, P, P, P, i32, i32, P]),
+            "ccz4_step_stage_flags": (i32, [P, i32, i32, ctypes.POINTER(i32)]),
             "ccz4_reconstruct_aux": (i32, [P, P, i32, P]),
             "ccz4_tracers_sample": (i32, [P, P, i64, P, i32, P, P, P]),
             "ccz4_tracers_advance": (i32, [P, P, i64, P, f64, P]),
@@ -252,6 +253,12 @@ def ccz4_set_kernel(h, precision, kernel):
 def ccz4_get_kernel(h, precision):
     out = ctypes.c_int32(-1)
     _check(lib().ccz4_get_kernel(h, int(precision), ctypes.byref(out)))
+    return out.value
+
+
+def ccz4_step_stage_flags(h, precision, s):
+    out = ctypes.c_int32(0)
+    _check(lib().ccz4_step_stage_flags(h, int(precision), int(s), ctypes.byref(out)))
     return out.value
 
 
@@ -480,11 +487,16 @@ class Context:
     def get_kernel(self, precision):
         return ccz4_get_kernel(self.h, precision)
 
+    def step_stage_flags(self, s, precision=PREC_FP64):
+        return ccz4_step_stage_flags(self.h, precision, s)
+
     def rk4_step_fused(self, Qn, dt, bufs, precision=PREC_FP64, stream=None, push=True):
         """One RK4 step in place on Qn with the fused stage kernel; bufs = (Q1, Q2, acc).
-        With push (default) every stage writes the same-level face halos of its output, so only
-        Neumann and coarse-fine faces are filled between stages; Qn must enter with all halos
-        filled (ccz4_fill_halos once after the initial data) and leaves with them filled."""
+        With push (default) the stages handle the same-level halos themselves, with the flags of
+        ccz4_step_stage_flags (read from the neighbours, or written into them), so only Neumann
+        and coarse-fine faces are filled between stages; Qn must enter with all halos filled
+        (ccz4_fill_halos once after the initial data) and leaves with them filled.  Without push
+        every halo is filled before each stage."""
         Q1, Q2, acc = bufs
         order = ((Qn, Q1), (Q1, Q2), (Q2, Q1), (Q1, Qn))
         rest = FILL_NEUMANN | FILL_LEVELS
@@ -492,7 +504,7 @@ class Context:
             if push:
                 if s > 0:
                     self.fill_halos_kinds(src, rest, stream)
-                self.rhs_rk4_stage(s, dt, src, Qn, acc, dst, precision, STAGE_FILL_SAME_LEVEL, stream)
+                self.rhs_rk4_stage(s, dt, src, Qn, acc, dst, precision, self.step_stage_flags(s, precision), stream)
                 if self.second_order:  # Algorithm 2: the auxiliaries of the new state
                     self.fill_halos_kinds(dst, rest, stream)
                     self.reconstruct(dst, True, stream)

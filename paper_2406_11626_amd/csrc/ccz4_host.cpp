@@ -532,6 +532,38 @@ ccz4_status ccz4_rk4_stage(ccz4_ctx *c, int32_t s, double dt, const double *Qn, 
     return CCZ4_OK;
 }
 
+// Halo handling of stage s of a fused step with kernel variant v.  The LDS kernel reads the
+// same-level y and z face halos of its input straight from the neighbours, so stages 0..2 copy
+// only the x-face halos, and stage 3 copies all of them, leaving Q^{n+1} with complete halos.
+// The second-order formulation copies every face after every stage (the reconstruction reads the
+// primaries' halos), and so does the phased kernel (it reads its own halos).
+static int32_t step_stage_flags(const ccz4_ctx *c, int32_t v, int32_t s)
+{
+    if (!(v & KV_LDS) || c->prm.formulation == CCZ4_FORMULATION_SECOND_ORDER) return CCZ4_STAGE_FILL_SAME_LEVEL;
+    return CCZ4_STAGE_GATHER_SAME_LEVEL | (s == 3 ? CCZ4_STAGE_FILL_SAME_LEVEL : CCZ4_STAGE_FILL_SAME_LEVEL_X);
+}
+
+// One fused stage launch with the halo handling of `flags` (validated by the caller).
+static hipError_t launch_stage_flags(const ccz4_ctx *c, int32_t s, double dt, const double *Qs, const double *Qn,
+                                     double *acc, double *Qx, int32_t precision, int32_t variant, int32_t flags,
+                                     hipStream_t st)
+{
+    const bool push = flags & (CCZ4_STAGE_FILL_SAME_LEVEL | CCZ4_STAGE_FILL_SAME_LEVEL_X);
+    const int32_t axes = (flags & CCZ4_STAGE_FILL_SAME_LEVEL) ? 7 : 1;
+    return launch_stage(s, dt, Qs, Qn, acc, Qx, c->d_geom.p, (int32_t)c->leaf.size(), c->prm, precision, variant,
+                        c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(), push ? c->d_nbr.p : nullptr, axes,
+                        (flags & CCZ4_STAGE_GATHER_SAME_LEVEL) ? c->d_nbr.p : nullptr, st);
+}
+
+ccz4_status ccz4_step_stage_flags(ccz4_ctx *c, int32_t precision, int32_t s, int32_t *flags)
+{
+    if (!c || !flags) return fail(CCZ4_EINVAL, "ctx or flags is NULL");
+    if (precision != CCZ4_PREC_FP64 && precision != CCZ4_PREC_MIXED) return fail(CCZ4_EINVAL, "bad precision");
+    if (s < 0 || s > 3) return fail(CCZ4_EINVAL, "stage must be 0..3");
+    *flags = step_stage_flags(c, c->kernel[precision], s);
+    return CCZ4_OK;
+}
+
 ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *c, int32_t s, double dt, const double *Qs, const double *Qn, double *acc,
                                double *Qnext, int32_t precision, int32_t flags, void *stream)
 {
@@ -544,15 +576,16 @@ ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *c, int32_t s, double dt, const double *
     if (!st) st = check_ptr(Qnext, "Qnext");
     if (st) return st;
     if (precision != CCZ4_PREC_FP64 && precision != CCZ4_PREC_MIXED) return fail(CCZ4_EINVAL, "bad precision");
-    if (flags & ~CCZ4_STAGE_FILL_SAME_LEVEL) return fail(CCZ4_EINVAL, "unknown stage flags");
+    if (flags & ~(CCZ4_STAGE_FILL_SAME_LEVEL | CCZ4_STAGE_GATHER_SAME_LEVEL | CCZ4_STAGE_FILL_SAME_LEVEL_X))
+        return fail(CCZ4_EINVAL, "unknown stage flags");
+    if ((flags & CCZ4_STAGE_GATHER_SAME_LEVEL) && !(c->kernel[precision] & KV_LDS))
+        return fail(CCZ4_EINVAL, "CCZ4_STAGE_GATHER_SAME_LEVEL needs the LDS kernel");
     if (Qnext == Qs) return fail(CCZ4_EINVAL, "Qnext must not alias Qs");
     if (s < 3 && Qnext == Qn) return fail(CCZ4_EINVAL, "Qnext may alias Qn only at s = 3");
     if (acc == Qs || acc == Qn || acc == Qnext) return fail(CCZ4_EINVAL, "acc must not alias the states");
     if (!c->bface.empty() && !c->bg_valid)
         return fail(CCZ4_ESTATE, "Sommerfeld background not set (call ccz4_init_patches or ccz4_set_background)");
-    HIP_TRY(launch_stage(s, dt, Qs, Qn, acc, Qnext, c->d_geom.p, (int32_t)c->leaf.size(), c->prm, precision,
-                         c->kernel[precision], c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(),
-                         (flags & CCZ4_STAGE_FILL_SAME_LEVEL) ? c->d_nbr.p : nullptr, S(stream)));
+    HIP_TRY(launch_stage_flags(c, s, dt, Qs, Qn, acc, Qnext, precision, c->kernel[precision], flags, S(stream)));
     return CCZ4_OK;
 }
 
@@ -659,10 +692,9 @@ ccz4_status ccz4_autotune(ccz4_ctx *c, const double *Q, double *acc, double *Qx,
     int32_t pick = c->kernel[precision];
     const double dt = 1e-3;
     for (int32_t v = 0; v < KV_COUNT && he == hipSuccess; ++v) {
-        auto stage = [&]() {
-            return launch_stage(1, dt, Q, Q, acc, Qx, c->d_geom.p, (int32_t)c->leaf.size(), c->prm, precision, v,
-                                c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(), c->d_nbr.p, S(stream));
-        };
+        // the middle stage of a step as the step graph runs it with this variant
+        const int32_t fl = step_stage_flags(c, v, 1);
+        auto stage = [&]() { return launch_stage_flags(c, 1, dt, Q, Q, acc, Qx, precision, v, fl, S(stream)); };
         he = stage();  // warm-up
         if (he == hipSuccess) he = hipEventRecord(e0, S(stream));
         for (int r = 0; r < reps && he == hipSuccess; ++r) he = stage();
@@ -717,11 +749,11 @@ ccz4_status ccz4_step_graph_create(ccz4_ctx *c, double *Qn, double *Q1, double *
         return fail(CCZ4_ENOMEM, "graph");
     }
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    const int32_t np = (int32_t)c->leaf.size(), nbf = (int32_t)c->bface.size();
+    const int32_t np = (int32_t)c->leaf.size();
     double *src[4] = {Qn, Q1, Q2, Q1}, *dst[4] = {Q1, Q2, Q1, Qn};
     for (int s = 0; s < 4 && e == hipSuccess; ++s) {
-        e = launch_stage(s, dt, src[s], Qn, acc, dst[s], c->d_geom.p, np, c->prm, precision, c->kernel[precision],
-                         c->d_bf.p, c->d_bg.p, nbf, c->d_nbr.p, cs);
+        const int32_t fl = step_stage_flags(c, c->kernel[precision], s);
+        e = launch_stage_flags(c, s, dt, src[s], Qn, acc, dst[s], precision, c->kernel[precision], fl, cs);
         if (e == hipSuccess) e = launch_fill(dst[s], c->d_phn.p, (int32_t)c->ph_neu.size(), c->prm.transfer, cs);
         if (e == hipSuccess) e = launch_fill(dst[s], c->d_phr.p, (int32_t)c->ph_res.size(), c->prm.transfer, cs);
         if (e == hipSuccess) e = launch_fill(dst[s], c->d_php.p, (int32_t)c->ph_pro.size(), c->prm.transfer, cs);

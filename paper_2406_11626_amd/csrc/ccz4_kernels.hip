@@ -376,6 +376,7 @@ struct StageSink {
     int so;  // second-order formulation: the auxiliaries are left alone (reconstructed afterwards)
     double dt;
     double carry[12];  // s = 3: gt_ij and At_ij of Q^{n+1}, projected in finish()
+    int oc;            // the cell's index in a slot of the accumulator (acc_cell)
     int64_t pd[3];     // offsets (doubles, from this cell) of its copies in same-level neighbours'
                        // face halos of Q_next along each axis, 0 for none
 
@@ -394,13 +395,13 @@ struct StageSink {
         const int e = v * CS + o;
         if (s == 0) {
             const double q0 = qn[e];
-            acc[e] = q0 + (1.0 / 6.0) * dt * r;
+            acc[v * CS + oc] = q0 + (1.0 / 6.0) * dt * r;
             out(e, q0 + 0.5 * dt * r);
         } else if (s < 3) {
-            acc[e] = acc[e] + (1.0 / 3.0) * dt * r;
+            acc[v * CS + oc] = acc[v * CS + oc] + (1.0 / 3.0) * dt * r;
             out(e, qn[e] + (s == 1 ? 0.5 : 1.0) * dt * r);
         } else {
-            const double val = acc[e] + (1.0 / 6.0) * dt * r;
+            const double val = acc[v * CS + oc] + (1.0 / 6.0) * dt * r;
             if (v < 6) carry[v] = val;
             else if (v >= SAT && v < SAT + 6) carry[v - SAT + 6] = val;
             else out(e, val);
@@ -432,13 +433,13 @@ struct StageSink {
 // of a face whose neighbour nbr[6p + 2a + (side > 0)] is a leaf of the same level appears in that
 // neighbour's ghost layer at box coordinate c_a - 9 (side +1) or c_a + 9 (side -1).  0: no copy.
 __device__ __forceinline__ void push_offsets(const int32_t *__restrict__ nbr, int p, int x, int y, int z, int o,
-                                             int64_t pd[3])
+                                             int64_t pd[3], int axes = 7)
 {
     const int c[3] = {x, y, z};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         pd[a] = 0;
-        if (!nbr) continue;
+        if (!nbr || !((axes >> a) & 1)) continue;
         const int side = c[a] >= 9 ? 1 : (c[a] <= 5 ? -1 : 0);
         if (side == 0) continue;
         const int np = nbr[p * 6 + 2 * a + (side > 0 ? 1 : 0)];
@@ -485,15 +486,16 @@ __device__ __forceinline__ void stage_ghost_face(int fi, int idx, int32_t s, dou
             r = -cadv * (qL - Qs[base + v * CS + oi]) - cdmp * (qL - B[v * NFACE]);
         }
         const int64_t e = base + v * CS + og;
+        const int64_t ea = base + v * CS + acc_ghost(f.axis, f.side, idx);
         if (s == 0) {
             const double q0 = Qn[e];
-            acc[e] = q0 + (1.0 / 6.0) * dt * r;
+            acc[ea] = q0 + (1.0 / 6.0) * dt * r;
             Qx[e] = q0 + 0.5 * dt * r;
         } else if (s < 3) {
-            acc[e] = acc[e] + (1.0 / 3.0) * dt * r;
+            acc[ea] = acc[ea] + (1.0 / 3.0) * dt * r;
             Qx[e] = Qn[e] + (s == 1 ? 0.5 : 1.0) * dt * r;
         } else {
-            Qx[e] = acc[e] + (1.0 / 6.0) * dt * r;
+            Qx[e] = acc[ea] + (1.0 / 6.0) * dt * r;
         }
     }
 }
@@ -504,7 +506,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WP
     const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
     const PatchGeom *__restrict__ geom, int32_t npatch, int32_t nb_slab, RhsParams prm, int32_t s, double dt,
     const BoundaryFace *__restrict__ bf, const double *__restrict__ bg, const int32_t *__restrict__ nbr,
-    int32_t linear)
+    int32_t paxes, int32_t linear)
 {
     if ((int32_t)blockIdx.x >= nb_slab) {
         stage_ghost_face((int)blockIdx.x - nb_slab, threadIdx.x, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, prm.shift == 0);
@@ -532,7 +534,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WP
     snk.s = s;
     snk.so = prm.formulation;
     snk.dt = dt;
-    push_offsets(nbr, p, c % 9 + 3, (c / 9) % 9 + 3, c / 81 + 3, cr.o, snk.pd);
+    snk.oc = acc_cell((int)(lb % 3), (int)threadIdx.x);
+    push_offsets(nbr, p, c % 9 + 3, (c / 9) % 9 + 3, c / 81 + 3, cr.o, snk.pd, paxes);
     rhs_cell_phased<T>(cr, prm, snk);
 }
 
@@ -580,7 +583,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     snk.kb = K + (int64_t)p * PS;
     snk.o = o;
     snk.so = prm.formulation;
-    rhs_slab_lds<T, LOP>(Q + (int64_t)p * PS, lds, sl, act, o, C, prm, snk);
+    const HaloSrc hs{{0, 0, 0, 0}};
+    rhs_slab_lds<T, LOP>(Q + (int64_t)p * PS, lds, sl, act, o, C, prm, snk, hs);
 }
 
 struct LdsStageSink {
@@ -600,7 +604,7 @@ struct LdsStageSink {
             if (st->so && aux_slot(slots[j])) continue;
             const int e = slots[j] * CS + o;
             a[j] = s < 3 ? st->qn[e] : 0.0;
-            b[j] = s > 0 ? st->acc[e] : 0.0;
+            b[j] = s > 0 ? st->acc[slots[j] * CS + st->oc] : 0.0;
         }
     }
     template <int N>
@@ -615,10 +619,10 @@ struct LdsStageSink {
             if (st->so && aux_slot(v)) continue;
             const int e = v * CS + o;
             if (s == 0) {
-                st->acc[e] = a[j] + (1.0 / 6.0) * dt * r[j];
+                st->acc[v * CS + st->oc] = a[j] + (1.0 / 6.0) * dt * r[j];
                 st->out(e, a[j] + 0.5 * dt * r[j]);
             } else if (s < 3) {
-                st->acc[e] = b[j] + (1.0 / 3.0) * dt * r[j];
+                st->acc[v * CS + st->oc] = b[j] + (1.0 / 3.0) * dt * r[j];
                 st->out(e, a[j] + (s == 1 ? 0.5 : 1.0) * dt * r[j]);
             } else {
                 const double val = b[j] + (1.0 / 6.0) * dt * r[j];
@@ -635,7 +639,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
     const PatchGeom *__restrict__ geom, int32_t npatch, int32_t nb_slab, RhsParams prm, int32_t s, double dt,
     const BoundaryFace *__restrict__ bf, const double *__restrict__ bg, const int32_t *__restrict__ nbr,
-    int32_t linear)
+    int32_t paxes, const int32_t *__restrict__ gnbr, int32_t linear)
 {
     __shared__ double lds[LDS_DOUBLES];
     if ((int32_t)blockIdx.x >= nb_slab) {
@@ -658,12 +662,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     ss.s = s;
     ss.so = prm.formulation;
     ss.dt = dt;
+    ss.oc = acc_cell(sl, act ? (int)threadIdx.x : 242);
     {
         const int cc = act ? (int)threadIdx.x : 242;
-        push_offsets(nbr, p, cc % 9 + 3, (cc / 9) % 9 + 3, cc / 81 + 3 + 3 * sl, o, ss.pd);
+        push_offsets(nbr, p, cc % 9 + 3, (cc / 9) % 9 + 3, cc / 81 + 3 + 3 * sl, o, ss.pd, paxes);
     }
     LdsStageSink snk{&ss, o};
-    rhs_slab_lds<T, LOP>(Qs + (int64_t)p * PS, lds, sl, act, o, C, prm, snk);
+    HaloSrc hs;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {  // faces y-, y+, z-, z+
+        const int n = gnbr ? gnbr[p * 6 + 2 + f] : -1;
+        hs.d[f] = n >= 0 ? (int64_t)(n - p) * PS + ((f & 1) ? -9 : 9) * (f < 2 ? YS : ZS) : 0;
+    }
+    rhs_slab_lds<T, LOP>(Qs + (int64_t)p * PS, lds, sl, act, o, C, prm, snk, hs);
 }
 
 // Sommerfeld ghosts: one thread per (boundary face, slot, ghost cell)
@@ -1233,7 +1244,7 @@ hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t
 hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn, double *acc, double *Qx,
                         const PatchGeom *geom, int32_t npatch, const RhsParams &p, int32_t precision,
                         int32_t variant, const BoundaryFace *bf, const double *bg, int32_t nbf, const int32_t *nbr,
-                        hipStream_t st)
+                        int32_t paxes, const int32_t *gnbr, hipStream_t st)
 {
     const int64_t nb_slab = ((int64_t)npatch * 3 + 7) / 8 * 8;
     const int64_t nb = nb_slab + (nbf > 0 ? nbf : 0);
@@ -1244,34 +1255,34 @@ hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn
         if (p.advection) {
             if (precision == 1)
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<float, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, bf, bg, nbr, lin);
+                                   ns, p, s, dt, bf, bg, nbr, paxes, gnbr, lin);
             else
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<double, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, bf, bg, nbr, lin);
+                                   ns, p, s, dt, bf, bg, nbr, paxes, gnbr, lin);
         } else {
             if (precision == 1)
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<float, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, bf, bg, nbr, lin);
+                                   ns, p, s, dt, bf, bg, nbr, paxes, gnbr, lin);
             else
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<double, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, bf, bg, nbr, lin);
+                                   ns, p, s, dt, bf, bg, nbr, paxes, gnbr, lin);
         }
     } else {
         const dim3 g((unsigned)nb), b(256);
         if (p.advection) {
             if (precision == 1)
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage<float, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
-                                   p, s, dt, bf, bg, nbr, lin);
+                                   p, s, dt, bf, bg, nbr, paxes, lin);
             else
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage<double, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
-                                   p, s, dt, bf, bg, nbr, lin);
+                                   p, s, dt, bf, bg, nbr, paxes, lin);
         } else {
             if (precision == 1)
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage<float, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
-                                   p, s, dt, bf, bg, nbr, lin);
+                                   p, s, dt, bf, bg, nbr, paxes, lin);
             else
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage<double, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
-                                   p, s, dt, bf, bg, nbr, lin);
+                                   p, s, dt, bf, bg, nbr, paxes, lin);
         }
     }
     return hipGetLastError();

@@ -31,6 +31,20 @@ __host__ __device__ constexpr bool aux_slot(int v) { return v >= SA && v < SK0; 
 // box offset of cell (x, y, z) inside one slot of a patch
 __host__ __device__ constexpr int boff(int x, int y, int z) { return z * ZS + y * YS + x; }
 
+// Accumulator of the fused RK4 stage: state-sized, but private to that stage and laid out for
+// whole-line access.  Within one slot of a patch, interior cell i (0..242) of z-slab sl (cell
+// (x, y, z) with i = ((z - 3 - 3 sl) * 9 + y - 3) * 9 + x - 3) sits at 256 sl + i, so the lanes of
+// a wave cover consecutive 128-byte lines; ghost cell idx of the Sommerfeld face (axis, side)
+// sits at 768 + (2 axis + (side > 0)) * 243 + idx.
+constexpr int ACC_SLAB = 256;
+constexpr int ACC_GHOST = 3 * ACC_SLAB;
+static_assert(ACC_SLAB >= NFACE && ACC_GHOST + 6 * NFACE <= CS, "accumulator layout must fit a slot");
+__host__ __device__ constexpr int acc_cell(int sl, int i) { return ACC_SLAB * sl + i; }
+__host__ __device__ constexpr int acc_ghost(int axis, int side, int idx)
+{
+    return ACC_GHOST + (2 * axis + (side > 0 ? 1 : 0)) * NFACE + idx;
+}
+
 // face-task kinds of the halo fill
 enum FaceKind : int32_t { FK_COPY = 0, FK_NEUMANN = 1, FK_RESTRICT = 2, FK_PROLONG = 3 };
 

@@ -5,7 +5,9 @@
 // direct global->LDS loads (16 bytes per lane, no registers involved), at most 15 slots per
 // round.  A slot occupies, in LDS, the slab's three planes in box layout (3 x 15 x 16 doubles,
 // carrying the x and y halos) followed by the interior rows of the three planes below and the
-// three planes above the slab (6 x 9 rows x 10 doubles, columns x = 2..11).  Every FD4
+// three planes above the slab (6 x 9 rows x 10 doubles, columns x = 2..11).  Each y or z face
+// halo is read either from the patch's own halo or straight from the interior of the same-level
+// neighbour across that face (HaloSrc).  Every FD4
 // derivative and Kreiss-Oliger sum is then read from LDS; a per-lane table maps the seven
 // z-neighbours of a cell into the own planes or the halo rows.
 //
@@ -34,27 +36,44 @@ constexpr int LDS_DOUBLES = LDS_NBUF * LDS_SLOT;  // 151200 bytes
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
+// Where the y and z face halos of a patch are read from: d[2 (a - 1) + (side > 0)] (a = 1, 2) is
+// added to the element index of a halo cell of the face of axis a on that side.  0 reads the
+// patch's own halo (filled beforehand); for a same-level neighbour n it is (n - p) PS -+ 9 stride_a,
+// which reads the neighbour's interior cell at the same position directly, so that those halos
+// need no copy.  The x halos always come from the patch's own halo: x-face sources would split a
+// 16-byte pair (x = 2 from the neighbour, x = 3 from the patch) and need 4-byte copies, which cost
+// more than the x-face copies themselves (the x neighbours are mostly resident in the same L2).
+struct HaloSrc {
+    int64_t d[4];
+};
+
 // Issue the direct global->LDS copies of slot v of slab sl into buffer b (does not wait).
-// Own planes: 360 pairs in six 64-lane chunks; halo rows: 270 pairs in five chunks, pair e
-// being plane e / 45 (0..2 below, 3..5 above), row (e / 5) % 9, columns 2 + 2 (e % 5).
+// Own planes: 360 pairs in six 64-lane chunks, the rows y <= 2 and y >= 12 from the y faces'
+// sources; halo rows: 270 pairs in five chunks, pair e being plane e / 45 (0..2 below, 3..5
+// above), row (e / 5) % 9, columns 2 + 2 (e % 5), planes outside the patch from the z faces'
+// sources.
 __device__ __forceinline__ void lds_stage_slot(const double *__restrict__ qp, double *lds, int sl, int v, int b,
-                                               int w, int lane)
+                                               int w, int lane, const HaloSrc &hs)
 {
     const double *box = qp + v * CS;
     double *dst = lds + b * LDS_SLOT;
     const double *own = box + (3 + 3 * sl) * ZS;
     const int w0 = (w + b) & 3;
     for (int ch = w0; ch < 6; ch += 4)
-        if (ch * 64 + lane < 360)
-            __builtin_amdgcn_global_load_lds((const void *)(own + ch * 128 + 2 * lane), (lds_void_t *)(dst + ch * 128),
-                                             16, 0, 0);
+        if (ch * 64 + lane < 360) {
+            const int e = 2 * (ch * 64 + lane), r = e >> 4, y = r % 15;
+            // selects, not an index into hs.d: a lane-dependent index would put the array in memory
+            const int64_t d = y <= 2 ? hs.d[0] : (y >= 12 ? hs.d[1] : 0);
+            __builtin_amdgcn_global_load_lds((const void *)(own + e + d), (lds_void_t *)(dst + ch * 128), 16, 0, 0);
+        }
     const int w1 = (w + b + 2) & 3;
     for (int ch = w1; ch < 5; ch += 4) {
         const int e = ch * 64 + lane;
         if (e < 270) {
             const int hp = e / 45, row = (e / 5) % 9, pr = e % 5;
             const int z = hp < 3 ? 3 * sl + hp : 3 * sl + 3 + hp;
-            __builtin_amdgcn_global_load_lds((const void *)(box + z * ZS + (row + 3) * YS + 2 + 2 * pr),
+            const int64_t zd = z <= 2 ? hs.d[2] : (z >= 12 ? hs.d[3] : 0);
+            __builtin_amdgcn_global_load_lds((const void *)(box + (z * ZS + (row + 3) * YS + 2 + 2 * pr) + zd),
                                              (lds_void_t *)(dst + LDS_OWN + ch * 128), 16, 0, 0);
         }
     }
@@ -64,11 +83,11 @@ __device__ __forceinline__ void lds_stage_slot(const double *__restrict__ qp, do
 // previous round's buffers; returns without waiting for them.
 template <int N>
 __device__ __forceinline__ void lds_issue(const double *__restrict__ qp, double *lds, int sl, const int (&slots)[N],
-                                          int w, int lane)
+                                          int w, int lane, const HaloSrc &hs)
 {
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < N; ++j) lds_stage_slot(qp, lds, sl, slots[j], j, w, lane);
+    for (int j = 0; j < N; ++j) lds_stage_slot(qp, lds, sl, slots[j], j, w, lane, hs);
 }
 
 // Wait for every outstanding memory operation of the lane and make the staged slots visible to
@@ -82,9 +101,9 @@ __device__ __forceinline__ void lds_wait()
 // Stage the N slots of a round and wait for them.
 template <int N>
 __device__ __forceinline__ void lds_round(const double *__restrict__ qp, double *lds, int sl, const int (&slots)[N],
-                                          int w, int lane)
+                                          int w, int lane, const HaloSrc &hs)
 {
-    lds_issue(qp, lds, sl, slots, w, lane);
+    lds_issue(qp, lds, sl, slots, w, lane, hs);
     lds_wait();
 }
 
@@ -287,7 +306,7 @@ __device__ constexpr int R4_OUT[24] = {SB, SB + 1, SB + 2, SB + 3, SB + 4, SB + 
 // work-group must call this (staging and barriers); only lanes with act = true compute.
 template <typename T, int LOP, typename Sink>
 __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, double *lds, int sl, bool act, int o0,
-                                             const LdsCell &C0, const RhsParams &p, Sink &snk)
+                                             const LdsCell &C0, const RhsParams &p, Sink &snk, const HaloSrc &hs)
 {
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const bool gdrv = p.shift != 0;
@@ -309,7 +328,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
     {
         const int r1[15] = {SAT, SAT + 1, SAT + 2, SAT + 3, SAT + 4, SAT + 5, SB, SB + 1, SB + 2,
                             SB + 3, SB + 4, SB + 5, SB + 6, SB + 7, SB + 8};
-        lds_round(qp, lds, sl, r1, w, lane);
+        lds_round(qp, lds, sl, r1, w, lane, hs);
     }
     if (act) {
         {  // B: advection + KO, GB^i = gt^kl d_(k B_l)^i, sdBtr_k = d_(k B_l)^l, and the shift
@@ -441,7 +460,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
     {
         const int r2[15] = {SD, SD + 1, SD + 2, SD + 3, SD + 4, SD + 5, SD + 6, SD + 7,
                             SD + 8, SD + 9, SD + 10, SD + 11, SD + 12, SD + 13, SD + 14};
-        lds_round(qp, lds, sl, r2, w, lane);
+        lds_round(qp, lds, sl, r2, w, lane, hs);
     }
     if (act) {
         const LdsCell C = fresh(C0);
@@ -471,7 +490,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
                             SGHAT, SGHAT + 1, SGHAT + 2, SK, STHETA};
         double qa[15], qb[15];
         if (act) snk.load(R2_OUT, qa, qb);
-        lds_issue(qp, lds, sl, r3, w, lane);
+        lds_issue(qp, lds, sl, r3, w, lane, hs);
         __builtin_amdgcn_s_waitcnt(0);  // the sink's loads and this wave's copies have landed
         if (act) snk.store(R2_OUT, ro2, qa, qb);
     }
@@ -841,7 +860,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
                             SALPHA, SBETA, SBETA + 1, SBETA + 2, SPHI};
         double qa[20], qb[20];
         if (act) snk.load(R3_OUT, qa, qb);
-        lds_issue(qp, lds, sl, r4, w, lane);
+        lds_issue(qp, lds, sl, r4, w, lane, hs);
         __builtin_amdgcn_s_waitcnt(0);  // the sink's loads and this wave's copies have landed
         if (act) snk.store(R3_OUT, ro3, qa, qb);
     }

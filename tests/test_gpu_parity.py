@@ -47,6 +47,24 @@ def random_state(m, seed, frozen=False):
     return Q
 
 
+def acc_slot_error(a, b):
+    """Per-slot relative difference of two fused-stage accumulators (device tensors, compared in
+    their own private layout, every element of every patch)."""
+    x = a.detach().cpu().numpy().reshape(a.shape[0], 59, -1)
+    y = b.detach().cpu().numpy().reshape(b.shape[0], 59, -1)
+    diff = np.abs(x - y).max(axis=(0, 2))
+    scale = np.abs(y).max(axis=(0, 2))
+    return diff / np.maximum(np.maximum(scale, 1e-3 * scale.max()), 1e-300)
+
+
+def valid_accumulator(ctx, Q, dt=0.01):
+    """An accumulator as stage 0 leaves it (Q + dt/6 RHS(Q) in the accumulator's own layout), so
+    that a later stage, and the projection at s = 3, start from well-conditioned values."""
+    acc, scratch = ctx.new_state(0.0), ctx.new_state(0.0)
+    ctx.rhs_rk4_stage(0, dt, Q, Q, acc, scratch, ccz4.PREC_FP64, 0)
+    return acc
+
+
 # ------------------------------------------------------------------ initial data
 
 @pytest.mark.parametrize("cfg", [1, 2, 5])
@@ -487,10 +505,11 @@ def test_kernels_agree_on_a_static_amr_mesh():
         ctx.set_kernel(ccz4.PREC_FP64, kern)
         acc, Qx = ctx.new_state(0.0), ctx.new_state(0.0)
         ctx.rhs_rk4_stage(1, 0.01, Qd, Qd.clone(), acc, Qx)
-        outs.append((to_host(acc), to_host(Qx)))
-    for a, b in zip(outs[0], outs[1]):
-        e = parity_error(b, a, INTERIOR)
-        assert e.max() <= 1e-13, (e.argmax(), e.max())
+        outs.append((acc, to_host(Qx)))
+    e = parity_error(outs[1][1], outs[0][1], INTERIOR)
+    assert e.max() <= 1e-13, (e.argmax(), e.max())
+    e = acc_slot_error(outs[1][0], outs[0][0])
+    assert e.max() <= 1e-13, (e.argmax(), e.max())
 
 
 def test_kernel_selection_rejects_bad_arguments():
@@ -523,8 +542,9 @@ def test_stage_push_writes_exactly_the_same_level_halos(kernel, periodic):
         assert counts["restrict"] > 0 and counts["prolong"] > 0 and counts["sommerfeld"] > 0
     ctx.set_kernel(ccz4.PREC_FP64, kernel)
     ctx.fill_halos(Q)
+    acc0 = valid_accumulator(ctx, Q)
     for s in (1, 3):
-        acc = Q.clone()  # a valid state, so that the projection at s = 3 is well conditioned
+        acc = acc0.clone()
         a_push, a_ref = ctx.new_state(0.0), ctx.new_state(0.0)
         acc2 = acc.clone()
         ctx.rhs_rk4_stage(s, 0.01, Q, Q, acc, a_push, ccz4.PREC_FP64, ccz4.STAGE_FILL_SAME_LEVEL)
@@ -535,9 +555,105 @@ def test_stage_push_writes_exactly_the_same_level_halos(kernel, periodic):
         assert bad.shape[0] == 0, (s, bad.shape[0], bad[:5].tolist())
         assert torch.equal(acc, acc2), s
     with pytest.raises(ccz4.CCZ4Error):
-        ctx.rhs_rk4_stage(1, 0.01, Q, Q, acc, a_push, ccz4.PREC_FP64, 2)
+        ctx.rhs_rk4_stage(1, 0.01, Q, Q, acc, a_push, ccz4.PREC_FP64, 8)
     with pytest.raises(ccz4.CCZ4Error):
         ctx.fill_halos_kinds(Q, 8)
+
+
+def same_level_halo_mask(ctx, Q, axes=(0, 1, 2)):
+    """Device boolean mask of the halo cells of the faces normal to `axes` that a same-level leaf
+    covers: the cells that a full fill restores but a Neumann + coarse-fine fill leaves alone."""
+    def refilled(kinds):
+        H = torch.full_like(Q, float("nan"))
+        H[:, :, 3:12, 3:12, 3:12] = Q[:, :, 3:12, 3:12, 3:12]
+        ctx.fill_halos_kinds(H, kinds)
+        return ~torch.isnan(H)
+    m = refilled(ccz4.FILL_ALL) & ~refilled(ccz4.FILL_NEUMANN | ccz4.FILL_LEVELS)
+    face = torch.zeros_like(m)
+    for a in axes:  # device layout [patch][slot][z][y][x]
+        idx = [slice(None), slice(None), slice(3, 12), slice(3, 12), slice(3, 12)]
+        for h in (slice(0, 3), slice(12, 15)):
+            idx[4 - a] = h
+            face[tuple(idx)] = True
+    return m & face
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+@pytest.mark.parametrize("push", [False, True])
+def test_stage_gather_reads_same_level_halos_from_the_neighbours(periodic, push):
+    """With CCZ4_STAGE_GATHER_SAME_LEVEL the fused stage reads every same-level y and z face halo
+    of Qs from the neighbour's interior: with those halos of Qs overwritten by NaN it gives Qnext
+    and the accumulator bit-identical to the stage on the filled state (s = 0, 1 and the projected
+    s = 3), on a mesh of periodic self-neighbours and on one with coarse-fine and Sommerfeld
+    faces (whose own halos it still reads), with and without the halo push."""
+    if periodic:
+        w = scenarios.config(1)
+        ctx = ccz4.Context((1, 2, 3), (-0.5, -0.5, -0.5), (1.0 / 3, 2.0 / 3, 1.0), ccz4.BC_PERIODIC, w.params())
+    else:
+        w = scenarios.config(2)
+        ctx = ccz4.Context((3, 3, 2), (-9.0, -9.0, -6.0), (18.0, 18.0, 12.0), w.bc, w.params(), [(0, 1, 1, 0)])
+    Q = ctx.new_state(0.0)
+    ctx.init_patches(Q, w.scenario, w.scen)
+    ctx.fill_halos(Q)
+    ctx.set_kernel(ccz4.PREC_FP64, ccz4.KERNEL_LDS)
+    mask = same_level_halo_mask(ctx, Q, axes=(1, 2))
+    assert int(mask.sum()) > 0
+    G = Q.clone()
+    G[mask] = float("nan")
+    acc0 = valid_accumulator(ctx, Q)
+    fl = ccz4.STAGE_FILL_SAME_LEVEL if push else 0
+    for s in (0, 1, 3):
+        acc_r, acc_g = acc0.clone(), acc0.clone()
+        out_r, out_g = ctx.new_state(0.0), ctx.new_state(0.0)
+        ctx.rhs_rk4_stage(s, 0.01, Q, Q, acc_r, out_r, ccz4.PREC_FP64, fl)
+        ctx.rhs_rk4_stage(s, 0.01, G, Q, acc_g, out_g, ccz4.PREC_FP64, fl | ccz4.STAGE_GATHER_SAME_LEVEL)
+        assert bool(torch.isfinite(out_g).all()), s
+        assert torch.equal(out_g, out_r), (s, int((out_g != out_r).sum()))
+        assert torch.equal(acc_g, acc_r), s
+    # the phased kernel reads its own halos: gathering is refused
+    ctx.set_kernel(ccz4.PREC_FP64, ccz4.KERNEL_PHASED)
+    with pytest.raises(ccz4.CCZ4Error):
+        ctx.rhs_rk4_stage(1, 0.01, Q, Q, acc0, out_r, ccz4.PREC_FP64, ccz4.STAGE_GATHER_SAME_LEVEL)
+    with pytest.raises(ccz4.CCZ4Error):
+        ctx.rhs_rk4_stage(1, 0.01, Q, Q, acc0, out_r, ccz4.PREC_FP64, 8)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_stage_push_x_writes_exactly_the_x_face_halos(kernel):
+    """CCZ4_STAGE_FILL_SAME_LEVEL_X writes the same-level x-face halos of Qnext exactly as the full
+    push does, and no y or z face halo."""
+    w = scenarios.config(2)
+    ctx = ccz4.Context((3, 3, 2), (-9.0, -9.0, -6.0), (18.0, 18.0, 12.0), w.bc, w.params(), [(0, 1, 1, 0)])
+    Q = ctx.new_state(0.0)
+    ctx.init_patches(Q, w.scenario, w.scen)
+    ctx.fill_halos(Q)
+    ctx.set_kernel(ccz4.PREC_FP64, kernel)
+    acc0 = valid_accumulator(ctx, Q)
+    full, xonly, none = ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0)
+    for out, fl in ((full, ccz4.STAGE_FILL_SAME_LEVEL), (xonly, ccz4.STAGE_FILL_SAME_LEVEL_X), (none, 0)):
+        ctx.rhs_rk4_stage(1, 0.01, Q, Q, acc0.clone(), out, ccz4.PREC_FP64, fl)
+    mx = same_level_halo_mask(ctx, Q, axes=(0,))
+    assert int(mx.sum()) > 0
+    assert torch.equal(xonly[mx], full[mx])
+    assert torch.equal(xonly[~mx], none[~mx])
+
+
+def test_step_stage_flags():
+    """The flags of a step's stages: the LDS kernel in the first-order formulation gathers the y
+    and z halos at every stage and copies the x-face halos at s = 0..2 and all of them at s = 3;
+    the phased kernel, or the second-order formulation, copies every face after every stage."""
+    G, F, X = ccz4.STAGE_GATHER_SAME_LEVEL, ccz4.STAGE_FILL_SAME_LEVEL, ccz4.STAGE_FILL_SAME_LEVEL_X
+    for form, want in ((ccz4.FORMULATION_FO, [G | X, G | X, G | X, G | F]), (ccz4.FORMULATION_SO, [F] * 4)):
+        ctx = ccz4.Context((2, 1, 1), (0.0, 0.0, 0.0), (2.0, 1.0, 1.0), ccz4.BC_PERIODIC,
+                           ccz4.params(formulation=form))
+        for prec in (ccz4.PREC_FP64, ccz4.PREC_MIXED):
+            ctx.set_kernel(prec, ccz4.KERNEL_LDS)
+            assert [ctx.step_stage_flags(s, prec) for s in range(4)] == want
+            ctx.set_kernel(prec, ccz4.KERNEL_PHASED)
+            assert [ctx.step_stage_flags(s, prec) for s in range(4)] == [F] * 4
+        for bad in ((-1, 0), (4, 0), (0, 2)):
+            with pytest.raises(ccz4.CCZ4Error):
+                ctx.step_stage_flags(*bad)
 
 
 def test_autotune_and_block_order():
