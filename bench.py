@@ -515,7 +515,8 @@ def main():
         "data": "synthetic (analytic puncture initial data)",
         "config": {"workload": w.name, "patches": r64["patches"], "cells": r64["cells"],
                    "stages_per_step": 4, "dt": w.dt(), "precision": "fp64",
-                   "step": "HIP graph of 4 fused stages with same-level halo push",
+                   "step": "HIP graph of 4 fused stages (y/z halos read from the neighbours, x-face halos "
+                           "copied; every halo copied at the last stage)",
                    "launch_config": r64["kernel"], "autotune_ms": r64["tune_ms"]},
         "eager_ms_per_step": r64["wall_eager"] * 1e3 / args.steps,
         "roofline": {"bound": "hbm", "achieved": r64["stage_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
