@@ -197,7 +197,7 @@ def run_gpu(args, w, precision, formulation=0, advection=0):
                     r0 = torch.cuda.Event(enable_timing=True)
                     r1 = torch.cuda.Event(enable_timing=True)
                     r0.record(stream)
-                ctx.reconstruct(dst, True, stream)
+                ctx.reconstruct(dst, stream=stream, flags=fl)
                 if timed:
                     r1.record(stream)
                     recon_events.append((r0, r1))

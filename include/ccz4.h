@@ -195,24 +195,27 @@ enum { CCZ4_STAGE_FILL_SAME_LEVEL = 1, CCZ4_STAGE_GATHER_SAME_LEVEL = 2, CCZ4_ST
 ccz4_status ccz4_rhs_rk4_stage(ccz4_ctx *ctx, int32_t s, double dt, const double *Qs, const double *Qn,
                                double *acc, double *Qnext, int32_t precision, int32_t flags, void *stream);
 
-/* The flags the step graph passes to stage s (0..3) with the context's current kernel for this
-   precision, into *flags (host).  First-order formulation with the LDS kernel: GATHER at every
-   stage, FILL_SAME_LEVEL_X at s = 0..2 and FILL_SAME_LEVEL at s = 3 (between stages only the
-   x-face halos are copied; the y and z ones are read from the neighbours, and the step leaves
-   complete halos).  Otherwise FILL_SAME_LEVEL at every stage.  Between stages only
-   ccz4_fill_halos_kinds(NEUMANN | LEVELS) is needed either way, and Qn must enter the step with
-   filled halos.  EINVAL on a NULL pointer, bad precision or stage. */
+/* The flags the step graph passes to stage s (0..3), and in the second-order formulation to the
+   reconstruction after it, with the context's current kernel for this precision, into *flags
+   (host).  LDS kernel: GATHER at every stage, FILL_SAME_LEVEL_X at s = 0..2 and FILL_SAME_LEVEL
+   at s = 3 (between stages only the x-face halos are copied; the y and z ones are read from the
+   neighbours, and the step leaves complete halos).  Phased kernel: FILL_SAME_LEVEL at every
+   stage.  Between stages only ccz4_fill_halos_kinds(NEUMANN | LEVELS) is needed either way, and
+   Qn must enter the step with filled halos.  EINVAL on a NULL pointer, bad precision or stage. */
 ccz4_status ccz4_step_stage_flags(ccz4_ctx *ctx, int32_t precision, int32_t s, int32_t *flags);
 
 /* Second-order formulation, explicit gradient reconstruction (Sec. 3.2 and Algorithm 2): on every
    interior cell of every leaf, A_k = d_k alpha, B_k^i = d_k beta^i, D_kij = d_k gt_ij / 2 and
    P_k = d_k phi (eq. auxiliary-variables) from the central FD4 difference of the primaries.
    Q (device, a state of this context) is updated in place; the primaries' halos must be filled
-   (gt, alpha, beta, phi), and no primary is modified.  flags: 0, or CCZ4_STAGE_FILL_SAME_LEVEL:
-   the new values within three layers of a face shared with a same-level leaf are also written
-   into that leaf's face halo (then only ccz4_fill_halos_kinds(NEUMANN | LEVELS) remains for the
-   auxiliaries' halos).  Independent of the context's formulation setting.  EINVAL on a NULL
-   pointer or unknown flags. */
+   (gt, alpha, beta, phi), and no primary is modified.  flags, any combination of
+   CCZ4_STAGE_FILL_SAME_LEVEL (the new values within three layers of a face shared with a
+   same-level leaf are also written into that leaf's face halo; then only
+   ccz4_fill_halos_kinds(NEUMANN | LEVELS) remains for the auxiliaries' halos),
+   CCZ4_STAGE_FILL_SAME_LEVEL_X (the same for the faces normal to x only) and
+   CCZ4_STAGE_GATHER_SAME_LEVEL (the primaries' y and z face halos that a same-level leaf covers
+   are read from that leaf's interior and need not be filled).  Independent of the context's
+   formulation setting and kernel.  EINVAL on a NULL pointer or unknown flags. */
 ccz4_status ccz4_reconstruct_aux(ccz4_ctx *ctx, double *Q, int32_t flags, void *stream);
 
 /* Tracers (Sec. 3.8, data probes).  For each of n points pos[n][3] (device, float64), the leaf
@@ -264,7 +267,7 @@ ccz4_status ccz4_autotune(ccz4_ctx *ctx, const double *Q, double *acc, double *Q
 /* A fused RK4 step captured as a HIP graph: the four stages of ccz4_rhs_rk4_stage with the
    flags of ccz4_step_stage_flags, (Qn -> Q1), (Q1 -> Q2), (Q2 -> Q1), (Q1 -> Qn), each followed
    by ccz4_fill_halos_kinds(NEUMANN | LEVELS) of its output (in the second-order formulation then
-   ccz4_reconstruct_aux with CCZ4_STAGE_FILL_SAME_LEVEL and the same fill again), with the launch
+   ccz4_reconstruct_aux with the same flags and the same fill again), with the launch
    configuration current at creation.  Buffers and dt are fixed at creation; Qn must enter each launch with all halos filled
    and leaves with them filled.  The graph uses the context's tables: destroy it before the
    context.  Launch is asynchronous on `stream`. */

@@ -405,11 +405,14 @@ class Context:
     def rhs_rk4_stage(self, s, dt, Qs, Qn, acc, Qnext, precision=PREC_FP64, flags=0, stream=None):
         ccz4_rhs_rk4_stage(self.h, s, dt, Qs, Qn, acc, Qnext, precision, flags, stream)
 
-    def reconstruct(self, Q, push=True, stream=None):
+    def reconstruct(self, Q, push=True, stream=None, flags=None):
         """Second-order formulation: the auxiliaries A, B, D, P of every interior cell from FD4
         differences of the primaries (whose halos must be filled); with push, also into the
-        same-level neighbours' face halos."""
-        ccz4_reconstruct_aux(self.h, Q, STAGE_FILL_SAME_LEVEL if push else 0, stream)
+        same-level neighbours' face halos.  flags, if given, replaces push (the STAGE_* flags, as
+        ccz4_step_stage_flags gives them for a step)."""
+        if flags is None:
+            flags = STAGE_FILL_SAME_LEVEL if push else 0
+        ccz4_reconstruct_aux(self.h, Q, flags, stream)
 
     def tracers_sample(self, Q, pos, slots, stream=None):
         """(n, len(slots)) float64 device tensor: trilinear samples at the points pos (n, 3) float64
@@ -504,10 +507,11 @@ class Context:
             if push:
                 if s > 0:
                     self.fill_halos_kinds(src, rest, stream)
-                self.rhs_rk4_stage(s, dt, src, Qn, acc, dst, precision, self.step_stage_flags(s, precision), stream)
+                fl = self.step_stage_flags(s, precision)
+                self.rhs_rk4_stage(s, dt, src, Qn, acc, dst, precision, fl, stream)
                 if self.second_order:  # Algorithm 2: the auxiliaries of the new state
                     self.fill_halos_kinds(dst, rest, stream)
-                    self.reconstruct(dst, True, stream)
+                    self.reconstruct(dst, stream=stream, flags=fl)
             else:
                 self.fill_halos(src, stream)
                 self.rhs_rk4_stage(s, dt, src, Qn, acc, dst, precision, 0, stream)

@@ -532,15 +532,23 @@ ccz4_status ccz4_rk4_stage(ccz4_ctx *c, int32_t s, double dt, const double *Qn, 
     return CCZ4_OK;
 }
 
-// Halo handling of stage s of a fused step with kernel variant v.  The LDS kernel reads the
-// same-level y and z face halos of its input straight from the neighbours, so stages 0..2 copy
+// Halo handling of stage s of a fused step with kernel variant v (and of the reconstruction that
+// follows it in the second-order formulation).  The LDS kernel and the reconstruction read the
+// same-level y and z face halos of their input straight from the neighbours, so stages 0..2 copy
 // only the x-face halos, and stage 3 copies all of them, leaving Q^{n+1} with complete halos.
-// The second-order formulation copies every face after every stage (the reconstruction reads the
-// primaries' halos), and so does the phased kernel (it reads its own halos).
-static int32_t step_stage_flags(const ccz4_ctx *c, int32_t v, int32_t s)
+// The phased kernel reads its own halos: with it every face is copied after every stage.
+static int32_t step_stage_flags(const ccz4_ctx *, int32_t v, int32_t s)
 {
-    if (!(v & KV_LDS) || c->prm.formulation == CCZ4_FORMULATION_SECOND_ORDER) return CCZ4_STAGE_FILL_SAME_LEVEL;
+    if (!(v & KV_LDS)) return CCZ4_STAGE_FILL_SAME_LEVEL;
     return CCZ4_STAGE_GATHER_SAME_LEVEL | (s == 3 ? CCZ4_STAGE_FILL_SAME_LEVEL : CCZ4_STAGE_FILL_SAME_LEVEL_X);
+}
+
+static hipError_t launch_reconstruct_flags(const ccz4_ctx *c, double *Q, int32_t flags, hipStream_t st)
+{
+    const bool push = flags & (CCZ4_STAGE_FILL_SAME_LEVEL | CCZ4_STAGE_FILL_SAME_LEVEL_X);
+    return launch_reconstruct(Q, c->d_geom.p, (int32_t)c->leaf.size(), push ? c->d_nbr.p : nullptr,
+                              (flags & CCZ4_STAGE_FILL_SAME_LEVEL) ? 7 : 1,
+                              (flags & CCZ4_STAGE_GATHER_SAME_LEVEL) ? c->d_nbr.p : nullptr, st);
 }
 
 // One fused stage launch with the halo handling of `flags` (validated by the caller).
@@ -594,9 +602,9 @@ ccz4_status ccz4_reconstruct_aux(ccz4_ctx *c, double *Q, int32_t flags, void *st
     if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
     ccz4_status st = check_ptr(Q, "Q");
     if (st) return st;
-    if (flags & ~CCZ4_STAGE_FILL_SAME_LEVEL) return fail(CCZ4_EINVAL, "unknown reconstruction flags");
-    HIP_TRY(launch_reconstruct(Q, c->d_geom.p, (int32_t)c->leaf.size(),
-                               (flags & CCZ4_STAGE_FILL_SAME_LEVEL) ? c->d_nbr.p : nullptr, S(stream)));
+    if (flags & ~(CCZ4_STAGE_FILL_SAME_LEVEL | CCZ4_STAGE_GATHER_SAME_LEVEL | CCZ4_STAGE_FILL_SAME_LEVEL_X))
+        return fail(CCZ4_EINVAL, "unknown reconstruction flags");
+    HIP_TRY(launch_reconstruct_flags(c, Q, flags, S(stream)));
     return CCZ4_OK;
 }
 
@@ -749,7 +757,6 @@ ccz4_status ccz4_step_graph_create(ccz4_ctx *c, double *Qn, double *Q1, double *
         return fail(CCZ4_ENOMEM, "graph");
     }
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    const int32_t np = (int32_t)c->leaf.size();
     double *src[4] = {Qn, Q1, Q2, Q1}, *dst[4] = {Q1, Q2, Q1, Qn};
     for (int s = 0; s < 4 && e == hipSuccess; ++s) {
         const int32_t fl = step_stage_flags(c, c->kernel[precision], s);
@@ -759,7 +766,7 @@ ccz4_status ccz4_step_graph_create(ccz4_ctx *c, double *Qn, double *Q1, double *
         if (e == hipSuccess) e = launch_fill(dst[s], c->d_php.p, (int32_t)c->ph_pro.size(), c->prm.transfer, cs);
         if (c->prm.formulation == CCZ4_FORMULATION_SECOND_ORDER) {
             // Algorithm 2: the auxiliaries of the new state from its primaries, then their halos
-            if (e == hipSuccess) e = launch_reconstruct(dst[s], c->d_geom.p, np, c->d_nbr.p, cs);
+            if (e == hipSuccess) e = launch_reconstruct_flags(c, dst[s], fl, cs);
             if (e == hipSuccess) e = launch_fill(dst[s], c->d_phn.p, (int32_t)c->ph_neu.size(), c->prm.transfer, cs);
             if (e == hipSuccess) e = launch_fill(dst[s], c->d_phr.p, (int32_t)c->ph_res.size(), c->prm.transfer, cs);
             if (e == hipSuccess) e = launch_fill(dst[s], c->d_php.p, (int32_t)c->ph_pro.size(), c->prm.transfer, cs);

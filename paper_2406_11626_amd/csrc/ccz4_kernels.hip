@@ -1013,56 +1013,77 @@ __global__ __launch_bounds__(256) void k_regrid(const double *__restrict__ Qo, d
 // auxiliaries from central FD4 differences of the primaries by their definitions,
 // A_k = d_k alpha, B_k^i = d_k beta^i, D_kij = d_k gt_ij / 2, P_k = d_k phi, on the interior
 // cells of every leaf.  One thread per cell, three work-groups per patch; the primaries'
-// halos must be filled.  With nbr, every value within three layers of a face shared with a
-// same-level leaf is also written into that leaf's face halo (as the stage push does).
-__global__ __launch_bounds__(256) void k_reconstruct(double *__restrict__ Q, const PatchGeom *__restrict__ geom,
-                                                     int32_t npatch, const int32_t *__restrict__ nbr)
+// halos must be filled, except, with gnbr, the y and z face halos shared with a same-level leaf,
+// which are then read from that leaf's interior (as the LDS stage reads them).  With nbr, every
+// value within three layers of a face shared with a same-level leaf and normal to an axis of
+// paxes is also written into that leaf's face halo (as the stage push does).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_reconstruct(
+    double *__restrict__ Q, const PatchGeom *__restrict__ geom, int32_t npatch, const int32_t *__restrict__ nbr,
+    int32_t paxes, const int32_t *__restrict__ gnbr)
 {
     const int p = (int)(blockIdx.x / 3);
     if (p >= npatch || threadIdx.x >= 243) return;
     const int c = (int)(blockIdx.x % 3) * 243 + (int)threadIdx.x;
     const int x = c % 9 + 3, y = (c / 9) % 9 + 3, z = c / 81 + 3;
-    double *qb = Q + (int64_t)p * PS;
+    // the primaries (slots 0..10) are only read and the auxiliaries (25..57) only written, so the
+    // two views of the state never touch the same element
+    const double *__restrict__ qr = Q + (int64_t)p * PS;
+    double *__restrict__ qw = Q + (int64_t)p * PS;
     const int o = boff(x, y, z);
     const PatchGeom g = geom[p];
     int64_t pd[3];
-    push_offsets(nbr, p, x, y, z, o, pd);
-    const int stride[3] = {1, YS, ZS};
-    // every difference first, then every store: the stores go through the same pointer as the
-    // loads, so the compiler would not move a later load above an earlier store
-    double val[3][SPHI + 1];
+    push_offsets(nbr, p, x, y, z, o, pd, paxes);
+    // offsets of the stencil points at -2, -1, +1, +2 along each axis, with the y and z points
+    // outside the interior moved into the same-level neighbour when gathering
+    int64_t so[3][4];
+    double i12[3];
+    {
+        const int cc[3] = {x, y, z};
+        const int stride[3] = {1, YS, ZS};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const double i12 = 1.0 / (12.0 * g.dx[a]);
-        const int h = stride[a];
+        for (int a = 0; a < 3; ++a) {
+            i12[a] = 1.0 / (12.0 * g.dx[a]);
+            int64_t lo = 0, hi = 0;
+            if (a > 0 && gnbr) {
+                const int nl = gnbr[p * 6 + 2 * a], nh = gnbr[p * 6 + 2 * a + 1];
+                lo = nl >= 0 ? (int64_t)(nl - p) * PS + 9 * stride[a] : 0;
+                hi = nh >= 0 ? (int64_t)(nh - p) * PS - 9 * stride[a] : 0;
+            }
 #pragma unroll
-        for (int v = 0; v <= SPHI; ++v) {
-            const double *f = qb + v * CS + o;
-            val[a][v] = (8.0 * (f[h] - f[-h]) - (f[2 * h] - f[-2 * h])) * i12;
+            for (int j = 0; j < 4; ++j) {
+                const int k = j < 2 ? j - 2 : j - 1;
+                const int ck = cc[a] + k;
+                so[a][j] = (int64_t)k * stride[a] + (ck < 3 ? lo : (ck > 11 ? hi : 0));
+            }
         }
     }
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int v = 0; v <= SPHI; ++v) {
+        const double *f = qr + v * CS + o;
 #pragma unroll
-        for (int v = 0; v <= SPHI; ++v) {
+        for (int a = 0; a < 3; ++a) {
+            const double d = (8.0 * (f[so[a][2]] - f[so[a][1]]) - (f[so[a][3]] - f[so[a][0]])) * i12[a];
             // D_a(ij) = d_a gt_ij / 2, A_a = d_a alpha, B_a^i = d_a beta^i, P_a = d_a phi
             const int dst = v < SALPHA ? SD + 6 * a + v
                           : v == SALPHA ? SA + a
                           : v < SPHI ? SB + 3 * a + (v - SBETA)
                                      : SP + a;
-            const double u = v < SALPHA ? 0.5 * val[a][v] : val[a][v];
+            const double u = v < SALPHA ? 0.5 * d : d;
             const int64_t e = (int64_t)dst * CS + o;
-            qb[e] = u;
+            qw[e] = u;
 #pragma unroll
             for (int k = 0; k < 3; ++k)
-                if (pd[k] != 0) qb[e + pd[k]] = u;
+                if (pd[k] != 0) qw[e + pd[k]] = u;
         }
+    }
 }
 
-hipError_t launch_reconstruct(double *Q, const PatchGeom *geom, int32_t npatch, const int32_t *nbr, hipStream_t st)
+hipError_t launch_reconstruct(double *Q, const PatchGeom *geom, int32_t npatch, const int32_t *nbr, int32_t paxes,
+                              const int32_t *gnbr, hipStream_t st)
 {
     if (npatch <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reconstruct, dim3((unsigned)npatch * 3u), dim3(256), 0, st, Q, geom, npatch, nbr);
+    hipLaunchKernelGGL(k_reconstruct, dim3((unsigned)npatch * 3u), dim3(256), 0, st, Q, geom, npatch, nbr, paxes,
+                       gnbr);
     return hipGetLastError();
 }
 

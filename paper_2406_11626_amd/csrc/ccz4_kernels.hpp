@@ -30,7 +30,8 @@ hipError_t launch_capture_bg(const double *Q, const BoundaryFace *bf, double *bg
 hipError_t launch_rk4(int32_t s, double dt, const double *Qn, const double *K, double *acc, double *Qx,
                       int32_t npatch, const BoundaryFace *bf, int32_t nbf, hipStream_t st);
 hipError_t launch_regrid(const double *Qo, double *Qn, const RegridTask *tasks, int32_t n, hipStream_t st);
-hipError_t launch_reconstruct(double *Q, const PatchGeom *geom, int32_t npatch, const int32_t *nbr, hipStream_t st);
+hipError_t launch_reconstruct(double *Q, const PatchGeom *geom, int32_t npatch, const int32_t *nbr, int32_t paxes,
+                              const int32_t *gnbr, hipStream_t st);
 hipError_t launch_tracers(const double *Q, const PatchGeom *geom, int32_t npatch, int64_t n, double *pos,
                           const TracerSlots &sl, double *out, double dt, int32_t advance, hipStream_t st);
 hipError_t launch_tag_tracers(const TrackBox *box, int32_t npatch, int64_t n, const double *pos, const TrackRadii &R,

@@ -48,3 +48,26 @@ def parity_error(gpu, ref, mask=INTERIOR, nslots=59):
     scale = np.abs(r).reshape(-1, nslots).max(0)
     top = scale.max()
     return diff / np.maximum(np.maximum(scale, FLOOR * top), 1e-300)
+
+
+def same_level_halo_mask(ctx, Q, axes=(0, 1, 2)):
+    """Device boolean mask of the halo cells of the faces normal to `axes` that a same-level leaf
+    covers: the cells that a full fill restores but a Neumann + coarse-fine fill leaves alone."""
+    import torch
+
+    from paper_2406_11626_amd import ccz4
+
+    def refilled(kinds):
+        H = torch.full_like(Q, float("nan"))
+        H[:, :, 3:12, 3:12, 3:12] = Q[:, :, 3:12, 3:12, 3:12]
+        ctx.fill_halos_kinds(H, kinds)
+        return ~torch.isnan(H)
+
+    m = refilled(ccz4.FILL_ALL) & ~refilled(ccz4.FILL_NEUMANN | ccz4.FILL_LEVELS)
+    face = torch.zeros_like(m)
+    for a in axes:  # device layout [patch][slot][z][y][x]
+        idx = [slice(None), slice(None), slice(3, 12), slice(3, 12), slice(3, 12)]
+        for h in (slice(0, 3), slice(12, 15)):
+            idx[4 - a] = h
+            face[tuple(idx)] = True
+    return m & face

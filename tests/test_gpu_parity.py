@@ -9,7 +9,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle as orc  # noqa: E402
-from gpu_helpers import INTERIOR, SLABS, parity_error, to_gpu, to_host  # noqa: E402
+from gpu_helpers import INTERIOR, SLABS, parity_error, same_level_halo_mask, to_gpu, to_host  # noqa: E402
 from paper_2406_11626_amd import ccz4, scenarios  # noqa: E402
 from seeded_inputs import box_centers, smooth_state  # noqa: E402
 
@@ -560,24 +560,6 @@ def test_stage_push_writes_exactly_the_same_level_halos(kernel, periodic):
         ctx.fill_halos_kinds(Q, 8)
 
 
-def same_level_halo_mask(ctx, Q, axes=(0, 1, 2)):
-    """Device boolean mask of the halo cells of the faces normal to `axes` that a same-level leaf
-    covers: the cells that a full fill restores but a Neumann + coarse-fine fill leaves alone."""
-    def refilled(kinds):
-        H = torch.full_like(Q, float("nan"))
-        H[:, :, 3:12, 3:12, 3:12] = Q[:, :, 3:12, 3:12, 3:12]
-        ctx.fill_halos_kinds(H, kinds)
-        return ~torch.isnan(H)
-    m = refilled(ccz4.FILL_ALL) & ~refilled(ccz4.FILL_NEUMANN | ccz4.FILL_LEVELS)
-    face = torch.zeros_like(m)
-    for a in axes:  # device layout [patch][slot][z][y][x]
-        idx = [slice(None), slice(None), slice(3, 12), slice(3, 12), slice(3, 12)]
-        for h in (slice(0, 3), slice(12, 15)):
-            idx[4 - a] = h
-            face[tuple(idx)] = True
-    return m & face
-
-
 @pytest.mark.parametrize("periodic", [True, False])
 @pytest.mark.parametrize("push", [False, True])
 def test_stage_gather_reads_same_level_halos_from_the_neighbours(periodic, push):
@@ -639,11 +621,12 @@ def test_stage_push_x_writes_exactly_the_x_face_halos(kernel):
 
 
 def test_step_stage_flags():
-    """The flags of a step's stages: the LDS kernel in the first-order formulation gathers the y
-    and z halos at every stage and copies the x-face halos at s = 0..2 and all of them at s = 3;
-    the phased kernel, or the second-order formulation, copies every face after every stage."""
+    """The flags of a step's stages (and second-order reconstructions): the LDS kernel gathers the
+    y and z halos at every stage and copies the x-face halos at s = 0..2 and all of them at s = 3;
+    the phased kernel copies every face after every stage."""
     G, F, X = ccz4.STAGE_GATHER_SAME_LEVEL, ccz4.STAGE_FILL_SAME_LEVEL, ccz4.STAGE_FILL_SAME_LEVEL_X
-    for form, want in ((ccz4.FORMULATION_FO, [G | X, G | X, G | X, G | F]), (ccz4.FORMULATION_SO, [F] * 4)):
+    for form, want in ((ccz4.FORMULATION_FO, [G | X, G | X, G | X, G | F]),
+                       (ccz4.FORMULATION_SO, [G | X, G | X, G | X, G | F])):
         ctx = ccz4.Context((2, 1, 1), (0.0, 0.0, 0.0), (2.0, 1.0, 1.0), ccz4.BC_PERIODIC,
                            ccz4.params(formulation=form))
         for prec in (ccz4.PREC_FP64, ccz4.PREC_MIXED):

@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle as orc  # noqa: E402
-from gpu_helpers import INTERIOR, SLABS, parity_error, to_gpu, to_host  # noqa: E402
+from gpu_helpers import INTERIOR, SLABS, parity_error, same_level_halo_mask, to_gpu, to_host  # noqa: E402
 from paper_2406_11626_amd import ccz4, scenarios  # noqa: E402
 from seeded_inputs import box_centers, smooth_state  # noqa: E402
 
@@ -112,6 +112,39 @@ def test_reconstruct_parity_and_push(push):
         np.testing.assert_array_equal(np.where(SLABS[..., None], g, 0.0), np.where(SLABS[..., None], Qo, 0.0))
 
 
+@pytest.mark.parametrize("periodic", [True, False])
+def test_reconstruct_gather_reads_same_level_halos_from_the_neighbours(periodic):
+    """With CCZ4_STAGE_GATHER_SAME_LEVEL the reconstruction reads the primaries' same-level y and z
+    face halos from the neighbours' interiors: with those halos overwritten by NaN it writes the
+    same auxiliaries (interior and pushed halos, with no push, the x-face push and the full push)
+    as on the filled state, on a periodic mesh and on one with coarse-fine and Sommerfeld faces."""
+    if periodic:
+        ctx, m = make_pair((3, 2, 2), (-0.4, 0.1, 0.2), (2.4, 1.6, 1.6), ccz4.BC_PERIODIC, so_params())
+        Qo = random_state(m, 53)
+        m.fill_halos(Qo)
+        Q = to_gpu(Qo)
+    else:
+        w = scenarios.config(2)
+        ctx = ccz4.Context((3, 3, 2), (-9.0, -9.0, -6.0), (18.0, 18.0, 12.0), w.bc, so_params(w), [(0, 1, 1, 0)])
+        Q = ctx.new_state(0.0)
+        ctx.init_patches(Q, w.scenario, w.scen)
+        ctx.fill_halos(Q)
+    prim = torch.zeros_like(Q, dtype=torch.bool)
+    prim[:, :11] = True
+    mask = same_level_halo_mask(ctx, Q, axes=(1, 2)) & prim
+    assert int(mask.sum()) > 0
+    G = Q.clone()
+    G[mask] = float("nan")
+    for fl in (0, ccz4.STAGE_FILL_SAME_LEVEL_X, ccz4.STAGE_FILL_SAME_LEVEL):
+        R, H = Q.clone(), G.clone()
+        ctx.reconstruct(R, flags=fl)
+        ctx.reconstruct(H, flags=fl | ccz4.STAGE_GATHER_SAME_LEVEL)
+        assert bool(torch.isfinite(H[~mask]).all()), fl
+        assert torch.equal(H[~mask], R[~mask]), (fl, int((H[~mask] != R[~mask]).sum()))
+    with pytest.raises(ccz4.CCZ4Error):
+        ccz4.ccz4_reconstruct_aux(ctx.h, Q, 8)
+
+
 def _so_steps(w, n0, prm, refined=(), steps=2, perturb=False, kernel=ccz4.KERNEL_LDS, push=True, graph=False):
     ctx, m = make_pair(n0, w.origin, w.extent, w.bc, prm, refined, kernel=kernel)
     Qo = m.zeros()
@@ -179,6 +212,6 @@ def test_reconstruct_rejects_bad_arguments():
     ctx = ccz4.Context((1, 1, 1), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), ccz4.BC_PERIODIC, so_params())
     Q = ctx.new_state(0.0)
     with pytest.raises(ccz4.CCZ4Error):
-        ccz4.ccz4_reconstruct_aux(ctx.h, Q, 2)
+        ccz4.ccz4_reconstruct_aux(ctx.h, Q, 8)
     with pytest.raises(ccz4.CCZ4Error):
         ccz4.ccz4_reconstruct_aux(ctx.h, None, 0)
