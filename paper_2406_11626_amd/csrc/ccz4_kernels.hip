@@ -479,23 +479,38 @@ __device__ __forceinline__ void stage_ghost_face(int fi, int idx, int32_t s, dou
     const double cadv = rr / (fabs(xn) * g.dx[f.axis]), cdmp = 1.0 / rr;
     const int64_t base = (int64_t)f.patch * PS;
     const double *B = bg + (int64_t)f.bg * NV * NFACE + idx;
-    for (int v = 0; v < NV; ++v) {
-        double r = 0.0;
-        if (v != SK0 && !(frozen && frozen_slot(v))) {
-            const double qL = Qs[base + v * CS + og];
-            r = -cadv * (qL - Qs[base + v * CS + oi]) - cdmp * (qL - B[v * NFACE]);
+    const int oa = acc_ghost(f.axis, f.side, idx);
+    // the slots in batches of eight, every load of a batch issued before its arithmetic and stores
+    // (this work-group holds a whole CU's LDS while it runs, so it must not wait slot by slot)
+    for (int v0 = 0; v0 < NV; v0 += SB8) {
+        double qL[SB8], qI[SB8], qB[SB8], q0[SB8], a0[SB8];
+#pragma unroll
+        for (int j = 0; j < SB8; ++j) {
+            const int v = v0 + j;
+            if (v >= NV) break;
+            qL[j] = Qs[base + v * CS + og];
+            qI[j] = Qs[base + v * CS + oi];
+            qB[j] = B[v * NFACE];
+            q0[j] = s < 3 ? Qn[base + v * CS + og] : 0.0;
+            a0[j] = s > 0 ? acc[base + v * CS + oa] : 0.0;
         }
-        const int64_t e = base + v * CS + og;
-        const int64_t ea = base + v * CS + acc_ghost(f.axis, f.side, idx);
-        if (s == 0) {
-            const double q0 = Qn[e];
-            acc[ea] = q0 + (1.0 / 6.0) * dt * r;
-            Qx[e] = q0 + 0.5 * dt * r;
-        } else if (s < 3) {
-            acc[ea] = acc[ea] + (1.0 / 3.0) * dt * r;
-            Qx[e] = Qn[e] + (s == 1 ? 0.5 : 1.0) * dt * r;
-        } else {
-            Qx[e] = acc[ea] + (1.0 / 6.0) * dt * r;
+#pragma unroll
+        for (int j = 0; j < SB8; ++j) {
+            const int v = v0 + j;
+            if (v >= NV) break;
+            const double r = (v != SK0 && !(frozen && frozen_slot(v)))
+                                 ? -cadv * (qL[j] - qI[j]) - cdmp * (qL[j] - qB[j]) : 0.0;
+            const int64_t e = base + v * CS + og;
+            const int64_t ea = base + v * CS + oa;
+            if (s == 0) {
+                acc[ea] = q0[j] + (1.0 / 6.0) * dt * r;
+                Qx[e] = q0[j] + 0.5 * dt * r;
+            } else if (s < 3) {
+                acc[ea] = a0[j] + (1.0 / 3.0) * dt * r;
+                Qx[e] = q0[j] + (s == 1 ? 0.5 : 1.0) * dt * r;
+            } else {
+                Qx[e] = a0[j] + (1.0 / 6.0) * dt * r;
+            }
         }
     }
 }
@@ -638,14 +653,9 @@ template <typename T, int LOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_stage_lds(
     const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
     const PatchGeom *__restrict__ geom, int32_t npatch, int32_t nb_slab, RhsParams prm, int32_t s, double dt,
-    const BoundaryFace *__restrict__ bf, const double *__restrict__ bg, const int32_t *__restrict__ nbr,
-    int32_t paxes, const int32_t *__restrict__ gnbr, int32_t linear)
+    const int32_t *__restrict__ nbr, int32_t paxes, const int32_t *__restrict__ gnbr, int32_t linear)
 {
     __shared__ double lds[LDS_DOUBLES];
-    if ((int32_t)blockIdx.x >= nb_slab) {
-        stage_ghost_face((int)blockIdx.x - nb_slab, threadIdx.x, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, prm.shift == 0);
-        return;
-    }
     const int64_t lb = linear ? (int64_t)blockIdx.x : xcd_logical_block(blockIdx.x, nb_slab);
     const int p = (int)(lb / 3);
     if (p >= npatch) return;  // uniform over the work-group
@@ -675,6 +685,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         hs.d[f] = n >= 0 ? (int64_t)(n - p) * PS + ((f & 1) ? -9 : 9) * (f < 2 ? YS : ZS) : 0;
     }
     rhs_slab_lds<T, LOP>(Qs + (int64_t)p * PS, lds, sl, act, o, C, prm, snk, hs);
+}
+
+// Fused stage on the Sommerfeld ghosts beside the LDS stage kernel: one work-group per boundary
+// face.  A separate launch without LDS, so that these work-groups share the CUs instead of each
+// holding one (inside the LDS kernel every work-group reserves its 151 KB).
+__global__ __launch_bounds__(256) void k_stage_ghost(const double *__restrict__ Qs, const double *__restrict__ Qn,
+                                                     double *__restrict__ acc, double *__restrict__ Qx,
+                                                     const PatchGeom *__restrict__ geom, int32_t s, double dt,
+                                                     const BoundaryFace *__restrict__ bf,
+                                                     const double *__restrict__ bg, int32_t frozen)
+{
+    stage_ghost_face((int)blockIdx.x, threadIdx.x, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, frozen);
 }
 
 // Sommerfeld ghosts: one thread per (boundary face, slot, ghost cell)
@@ -1260,8 +1282,9 @@ hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t
     return hipGetLastError();
 }
 
-// One launch: 3 work-groups per patch (grid padded to a multiple of 8 for the XCD mapping),
-// then one work-group per Sommerfeld boundary face.
+// 3 work-groups per patch (grid padded to a multiple of 8 for the XCD mapping) and one
+// work-group per Sommerfeld boundary face: in the same launch for the phased kernel, in a second
+// launch (k_stage_ghost) for the LDS kernel.
 hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn, double *acc, double *Qx,
                         const PatchGeom *geom, int32_t npatch, const RhsParams &p, int32_t precision,
                         int32_t variant, const BoundaryFace *bf, const double *bg, int32_t nbf, const int32_t *nbr,
@@ -1272,21 +1295,27 @@ hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn
     const int32_t ns = (int32_t)nb_slab;
     const int32_t lin = (variant & KV_LINEAR) ? 1 : 0;
     if (variant & KV_LDS) {
-        const dim3 g((unsigned)nb), b(256);
+        const dim3 g((unsigned)nb_slab), b(256);
         if (p.advection) {
             if (precision == 1)
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<float, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, bf, bg, nbr, paxes, gnbr, lin);
+                                   ns, p, s, dt, nbr, paxes, gnbr, lin);
             else
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<double, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, bf, bg, nbr, paxes, gnbr, lin);
+                                   ns, p, s, dt, nbr, paxes, gnbr, lin);
         } else {
             if (precision == 1)
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<float, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, bf, bg, nbr, paxes, gnbr, lin);
+                                   ns, p, s, dt, nbr, paxes, gnbr, lin);
             else
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<double, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, bf, bg, nbr, paxes, gnbr, lin);
+                                   ns, p, s, dt, nbr, paxes, gnbr, lin);
+        }
+        if (nbf > 0) {
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_stage_ghost, dim3((unsigned)nbf), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, s, dt, bf,
+                               bg, p.shift == 0 ? 1 : 0);
         }
     } else {
         const dim3 g((unsigned)nb), b(256);
