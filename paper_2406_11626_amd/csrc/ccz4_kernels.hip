@@ -189,9 +189,8 @@ __device__ __forceinline__ void ppar(int F, int &l, double &w0, double &w1)
     w0 = 1.0 - w1;
 }
 
-// One block per face task, one thread per slab cell; the 59 slots are handled in batches of
-// eight (all loads of a batch issued before its stores, since source and destination share
-// the state array).
+// One block per (face task, batch of eight slots), one thread per slab cell; a copy issues all
+// loads of its batch before its stores, since source and destination share the state array.
 constexpr int SB8 = 8;
 
 __global__ __launch_bounds__(256) void k_fill(double *__restrict__ Q, const FaceTask *__restrict__ tasks,
@@ -200,6 +199,8 @@ __global__ __launch_bounds__(256) void k_fill(double *__restrict__ Q, const Face
     const int ti = blockIdx.x;
     const int idx = threadIdx.x;
     if (ti >= ntask || idx >= NFACE) return;
+    // blockIdx.y picks a batch of eight slots, so that a task's slots are filled in parallel
+    const int v_lo = (int)blockIdx.y * SB8, v_hi = v_lo + SB8 < NV ? v_lo + SB8 : NV;
     const FaceTask tk = tasks[ti];
     int L, t1, t2;
     slab_coords(tk.axis, idx, L, t1, t2);
@@ -215,13 +216,13 @@ __global__ __launch_bounds__(256) void k_fill(double *__restrict__ Q, const Face
             : inject ? Q + (int64_t)tk.src[(F2 / 9) * 3 + F1 / 9] * PS +
                            slab_off(tk.axis, depth_c(-tk.side, 3 * L - 1), F1 % 9, F2 % 9)
                      : Q + (int64_t)tk.patch * PS + slab_off(tk.axis, depth_c(tk.side, 1), t1, t2);
-        for (int v0 = 0; v0 < NV; v0 += SB8) {
+        {
             double r[SB8];
 #pragma unroll
-            for (int j = 0; j < SB8; ++j) r[j] = (v0 + j < NV) ? src[(v0 + j) * CS] : 0.0;
+            for (int j = 0; j < SB8; ++j) r[j] = (v_lo + j < v_hi) ? src[(v_lo + j) * CS] : 0.0;
 #pragma unroll
             for (int j = 0; j < SB8; ++j)
-                if (v0 + j < NV) dst[(v0 + j) * CS] = r[j];
+                if (v_lo + j < v_hi) dst[(v_lo + j) * CS] = r[j];
         }
     } else if (tk.kind == FK_RESTRICT) {
         // coarse ghost c_{2+L}; fine interior layers f3..f5 = depth 1..3 from the kid's face -side;
@@ -238,7 +239,7 @@ __global__ __launch_bounds__(256) void k_fill(double *__restrict__ Q, const Face
             for (int b2 = 0; b2 < 3; ++b2)
                 for (int b1 = 0; b1 < 3; ++b1)
                     off[m][b2 * 3 + b1] = slab_off(tk.axis, depth_c(-tk.side, m + 1), f1 + b1, f2 + b2);
-        for (int v = 0; v < NV; ++v) {
+        for (int v = v_lo; v < v_hi; ++v) {
             double acc = 0.0;
             for (int m = 0; m < 3; ++m) {
                 if (wf[m] == 0.0) continue;
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(256) void k_fill(double *__restrict__ Q, const Face
             w[d][1] = 1.0 - s * s;
             w[d][2] = s * (s + 1.0) / 2.0;
         }
-        for (int v = 0; v < NV; ++v) {
+        for (int v = v_lo; v < v_hi; ++v) {
             const double *c = cp + v * CS;
             double acc = 0.0;
 #pragma unroll
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(256) void k_fill(double *__restrict__ Q, const Face
             off[m][2] = slab_off(tk.axis, cA[m], l1, l2 + 1);
             off[m][3] = slab_off(tk.axis, cA[m], l1 + 1, l2 + 1);
         }
-        for (int v = 0; v < NV; ++v) {
+        for (int v = v_lo; v < v_hi; ++v) {
             const double *c = cp + v * CS;
             double acc = 0.0;
             for (int m = 0; m < 2; ++m) {
@@ -1243,7 +1244,7 @@ hipError_t launch_init(double *Q, const PatchGeom *geom, const uint8_t *bmask, i
 hipError_t launch_fill(double *Q, const FaceTask *tasks, int32_t ntask, int32_t transfer, hipStream_t st)
 {
     if (ntask <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill, dim3(ntask), dim3(256), 0, st, Q, tasks, ntask, transfer);
+    hipLaunchKernelGGL(k_fill, dim3(ntask, (NV + SB8 - 1) / SB8), dim3(256), 0, st, Q, tasks, ntask, transfer);
     return hipGetLastError();
 }
 
