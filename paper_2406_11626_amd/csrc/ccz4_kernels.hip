@@ -193,8 +193,8 @@ __device__ __forceinline__ void ppar(int F, int &l, double &w0, double &w1)
 // loads of its batch before its stores, since source and destination share the state array.
 constexpr int SB8 = 8;
 
-__global__ __launch_bounds__(256) void k_fill(double *__restrict__ Q, const FaceTask *__restrict__ tasks,
-                                              int32_t ntask, int32_t transfer)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_fill(
+    double *__restrict__ Q, const FaceTask *__restrict__ tasks, int32_t ntask, int32_t transfer)
 {
     const int ti = blockIdx.x;
     const int idx = threadIdx.x;
