@@ -370,6 +370,72 @@ def run_tracker(args):
                 wall_s=wall, ms_per_step=wall * 1e3 / max(1, i), track=track)
 
 
+def run_learned_bbh(args):
+    """The learned refinement indicator trained on the solver's own binary-puncture runs in the
+    second-order formulation (stable, and the punctures orbit, so the refinement pattern moves).
+    Two training runs with Bowen-York momenta scaled to 0.9 and 1.1 of the standard 0.095 and one
+    held-out run at the standard momenta, each on the static r = 2 refinement around the punctures
+    to t_end.  Snapshots of the leaf features and the plain tags every sample_dt; the network learns
+    the plain tag of the next snapshot from the features of the current one, and is scored on the
+    held-out run by the REFINE miss rate against the next snapshot's plain tags."""
+    import numpy as np
+    import torch
+    from paper_2406_11626_amd import ccz4, learned, scenarios
+    w = scenarios.binary_tracking()
+    prm = ccz4.params(**{**w.prm, "formulation": ccz4.FORMULATION_SO})
+    dt = w.dt()
+    steps = int(round(args.t_end / dt))
+    every = max(1, int(round(args.sample_dt / dt)))
+    theta = None
+    runs = {}
+    t0 = time.perf_counter()
+    for name, scale in (("train_0.9", 0.9), ("train_1.1", 1.1), ("heldout_1.0", 1.0)):
+        scen = list(w.scen)
+        scen[5] *= scale   # y momentum of the puncture at +x
+        scen[12] *= scale  # and of the one at -x
+        ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, prm, w.refined)
+        Q = ctx.new_state(0.0)
+        ctx.init_patches(Q, w.scenario, scen)
+        ctx.fill_halos(Q)
+        ctx.reconstruct(Q)
+        ctx.fill_halos(Q)
+        if theta is None:  # thresholds from the first run's indicator at t = 0, kept for all runs
+            ind = torch.empty((ctx.n_patches, 3), dtype=torch.float64, device="cuda")
+            tags = torch.empty(ctx.n_patches, dtype=torch.int8, device="cuda")
+            ctx.tag_refine(Q, 1e300, -1.0, 2, tags, ind)
+            e = ind.max(dim=1).values.cpu().numpy()
+            theta = (float(np.percentile(e, 99.0)), float(np.percentile(e, 30.0)))
+        snaps = learned.snapshots(ctx, Q, dt, steps, every, theta[0], theta[1], 2)
+        norms, _ = ctx.constraints(Q)
+        runs[name] = (ctx, snaps, norms)
+        print(f"# {name}: {len(snaps)} snapshots, REFINE per snapshot "
+              f"{[int((t == 1).sum()) for _, t in snaps]}, non-finite {norms[2]:.0f}", file=sys.stderr, flush=True)
+    sim_s = time.perf_counter() - t0
+    feats, targets = [], []
+    for name in ("train_0.9", "train_1.1"):
+        snaps = runs[name][1]
+        for k in range(len(snaps) - 1):
+            feats.append(snaps[k][0])
+            targets.append(snaps[k + 1][1])
+    feat = torch.cat(feats)
+    target = torch.cat(targets)
+    ind = learned.LearnedIndicator(seed=0)
+    ind.fit_normalisation(feat)
+    t1 = time.perf_counter()
+    loss0 = ind.train(feat, target, 0)
+    loss = ind.train(feat, target, args.train_iters)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    ctx_h, snaps_h, norms_h = runs["heldout_1.0"]
+    score = learned.anticipation(ind, ctx_h, snaps_h, conf=0.6, max_level=2)
+    return dict(workload=w.name + ", second-order formulation", leaves=ctx_h.n_patches, dt=dt, t_end=args.t_end,
+                sample_dt=every * dt, theta_refine_coarsen=theta, training_rows=int(feat.shape[0]),
+                train_iters=args.train_iters, loss_before=loss0, loss_after=loss, train_s=train_s,
+                simulation_s=sim_s, heldout_nonfinite=norms_h[2],
+                heldout_refine_per_snapshot=[int((t == 1).sum()) for _, t in snaps_h],
+                heldout_score={k: {"miss_rate": v[0], "extra_refine": v[1]} for k, v in score.items()})
+
+
 def run_dynamic(args, w):
     """Binary puncture with dynamic AMR: a regrid by the plain criterion every 10 steps.  The
     thresholds are fixed once from the indicator at t = 0 (its 99.5th and 30th percentiles over
@@ -462,6 +528,10 @@ def main():
     ap.add_argument("--stability-transfer", action="store_true",
                     help="with --stability: second order with the App. E against the higher-order coarse-fine "
                          "operators")
+    ap.add_argument("--learned-bbh", action="store_true",
+                    help="train the learned refinement indicator on second-order binary-puncture runs and score "
+                         "it on a held-out run")
+    ap.add_argument("--train-iters", type=int, default=2000)
     ap.add_argument("--t-end", type=float, default=10.0)
     ap.add_argument("--sample-dt", type=float, default=0.5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -480,6 +550,9 @@ def main():
     w = scenarios.config(args.config)
     if args.tracker:
         print(json.dumps(run_tracker(args)), flush=True)
+        return
+    if args.learned_bbh:
+        print(json.dumps(run_learned_bbh(args)), flush=True)
         return
     if args.stability:
         r = run_stability(args, w)
