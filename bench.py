@@ -262,8 +262,7 @@ def run_gpu(args, w, precision, formulation=0, advection=0):
     targs = ("<double, " if precision == ccz4.PREC_FP64 else "<float, ") + ("1>" if advection else "0>")
     order = " (plain block order)" if kc & ccz4.KERNEL_LINEAR_ORDER else ""
     # the kernels one stage call (one right-hand-side call) launches
-    kname = ("k_stage_lds" if kc & ccz4.KERNEL_LDS else "k_stage") + targs + order + \
-        (" + k_stage_ghost" if nbf and kc & ccz4.KERNEL_LDS else "")
+    kname = ("k_stage_lds" if kc & ccz4.KERNEL_LDS else "k_stage") + targs + order
     rname = ("k_rhs_lds" if kc & ccz4.KERNEL_LDS else "k_rhs") + targs + order + (" + k_rhs_sommerfeld" if nbf else "")
     recon_ms = [a.elapsed_time(b) for a, b in recon_events]
     out = dict(wall=wall, wall_eager=wall_eager, tune_ms=tune_ms, cells=cells, patches=ctx.n_patches, rhs_ms=rhs_ms,

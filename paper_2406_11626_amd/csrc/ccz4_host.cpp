@@ -88,12 +88,14 @@ struct ccz4_ctx {
     std::vector<FaceTask> ph_copy, ph_neu, ph_res, ph_pro;  // fill tasks by kind (restrict before prolong)
     std::vector<int32_t> nbr;                 // [leaf][6] same-level face neighbour or -1
     std::vector<BoundaryFace> bface;
+    std::vector<int32_t> pface;               // per leaf and face 2 axis + (side > 0): index into bface or -1
     std::vector<uint8_t> bmask;
     std::vector<int32_t> sib;
     DevBuf<PatchGeom> d_geom;
     DevBuf<FaceTask> d_phc, d_phn, d_phr, d_php;
     DevBuf<int32_t> d_nbr;
     DevBuf<BoundaryFace> d_bf;
+    DevBuf<int32_t> d_pface;
     DevBuf<uint8_t> d_bmask;
     DevBuf<int32_t> d_sib;
     DevBuf<double> d_bg, d_part, d_out3, d_hm;
@@ -367,6 +369,12 @@ ccz4_status ccz4_create(ccz4_ctx **out, const ccz4_grid_desc *g, const ccz4_para
     if (e == hipSuccess) e = c->d_nbr.upload(c->nbr);
     if (e == hipSuccess) e = c->d_pre.alloc(c->leaf.size());
     if (e == hipSuccess) e = c->d_bf.upload(c->bface);
+    c->pface.assign(c->leaf.size() * 6, -1);
+    for (size_t i = 0; i < c->bface.size(); ++i) {
+        const BoundaryFace &b = c->bface[i];
+        c->pface[(size_t)b.patch * 6 + 2 * b.axis + (b.side > 0 ? 1 : 0)] = (int32_t)i;
+    }
+    if (e == hipSuccess && !c->pface.empty()) e = c->d_pface.upload(c->pface);
     if (e == hipSuccess) e = c->d_bmask.upload(c->bmask);
     if (e == hipSuccess) e = c->d_sib.upload(c->sib);
     if (e == hipSuccess) e = c->d_bg.alloc(nbf * NV * NFACE);
@@ -395,6 +403,7 @@ void ccz4_destroy(ccz4_ctx *c)
     c->d_nbr.release();
     c->d_pre.release();
     c->d_bf.release();
+    c->d_pface.release();
     c->d_bmask.release();
     c->d_sib.release();
     c->d_bg.release();
@@ -559,8 +568,8 @@ static hipError_t launch_stage_flags(const ccz4_ctx *c, int32_t s, double dt, co
     const bool push = flags & (CCZ4_STAGE_FILL_SAME_LEVEL | CCZ4_STAGE_FILL_SAME_LEVEL_X);
     const int32_t axes = (flags & CCZ4_STAGE_FILL_SAME_LEVEL) ? 7 : 1;
     return launch_stage(s, dt, Qs, Qn, acc, Qx, c->d_geom.p, (int32_t)c->leaf.size(), c->prm, precision, variant,
-                        c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(), push ? c->d_nbr.p : nullptr, axes,
-                        (flags & CCZ4_STAGE_GATHER_SAME_LEVEL) ? c->d_nbr.p : nullptr, st);
+                        c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(), c->d_pface.p, push ? c->d_nbr.p : nullptr,
+                        axes, (flags & CCZ4_STAGE_GATHER_SAME_LEVEL) ? c->d_nbr.p : nullptr, st);
 }
 
 ccz4_status ccz4_step_stage_flags(ccz4_ctx *c, int32_t precision, int32_t s, int32_t *flags)

@@ -517,6 +517,31 @@ __device__ __forceinline__ void stage_ghost_face(int fi, int idx, int32_t s, dou
 }
 
 
+// The Sommerfeld ghost cells beside z-slab sl of patch p, updated by that slab's work-group after
+// its interior: of each boundary face of the patch, the ghost cells next to the slab's three planes
+// (81 for an x or y face; the whole face slab of 243 for the z face below slab 0 or above slab 2).
+// Those rows were just fetched and written by the same work-group, so the ghost update finds them
+// in the L2 instead of touching a line of HBM for every 3 ghost cells of an x face.
+__device__ __forceinline__ void stage_ghost_slab(int p, int sl, const int32_t *__restrict__ pface, int32_t s,
+                                                 double dt, const double *__restrict__ Qs,
+                                                 const double *__restrict__ Qn, double *__restrict__ acc,
+                                                 double *__restrict__ Qx, const PatchGeom *__restrict__ geom,
+                                                 const BoundaryFace *__restrict__ bf,
+                                                 const double *__restrict__ bg, int32_t frozen)
+{
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const int fi = pface[p * 6 + f];
+        const int axis = f >> 1;
+        const int n = fi < 0 ? 0 : (axis < 2 ? 81 : ((f & 1) ? (sl == 2 ? NFACE : 0) : (sl == 0 ? NFACE : 0)));
+        for (int r = (int)threadIdx.x; r < n; r += (int)blockDim.x) {
+            // slab_coords order: x face idx = (L - 1) + 3 y + 27 z; y face idx = x + 9 z + 81 (L - 1)
+            const int idx = axis == 0 ? 81 * sl + r : (axis == 1 ? 81 * (r / 27) + 27 * sl + r % 27 : r);
+            stage_ghost_face(fi, idx, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, frozen);
+        }
+    }
+}
+
 template <typename T, int LOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WPE))) void k_stage(
     const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
@@ -654,6 +679,7 @@ template <typename T, int LOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_stage_lds(
     const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
     const PatchGeom *__restrict__ geom, int32_t npatch, int32_t nb_slab, RhsParams prm, int32_t s, double dt,
+    const BoundaryFace *__restrict__ bf, const double *__restrict__ bg, const int32_t *__restrict__ pface,
     const int32_t *__restrict__ nbr, int32_t paxes, const int32_t *__restrict__ gnbr, int32_t linear)
 {
     __shared__ double lds[LDS_DOUBLES];
@@ -686,18 +712,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         hs.d[f] = n >= 0 ? (int64_t)(n - p) * PS + ((f & 1) ? -9 : 9) * (f < 2 ? YS : ZS) : 0;
     }
     rhs_slab_lds<T, LOP>(Qs + (int64_t)p * PS, lds, sl, act, o, C, prm, snk, hs);
-}
-
-// Fused stage on the Sommerfeld ghosts beside the LDS stage kernel: one work-group per boundary
-// face.  A separate launch without LDS, so that these work-groups share the CUs instead of each
-// holding one (inside the LDS kernel every work-group reserves its 151 KB).
-__global__ __launch_bounds__(256) void k_stage_ghost(const double *__restrict__ Qs, const double *__restrict__ Qn,
-                                                     double *__restrict__ acc, double *__restrict__ Qx,
-                                                     const PatchGeom *__restrict__ geom, int32_t s, double dt,
-                                                     const BoundaryFace *__restrict__ bf,
-                                                     const double *__restrict__ bg, int32_t frozen)
-{
-    stage_ghost_face((int)blockIdx.x, threadIdx.x, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, frozen);
+    if (pface) stage_ghost_slab(p, sl, pface, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, prm.shift == 0);
 }
 
 // Sommerfeld ghosts: one thread per (boundary face, slot, ghost cell)
@@ -1283,14 +1298,16 @@ hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t
     return hipGetLastError();
 }
 
-// 3 work-groups per patch (grid padded to a multiple of 8 for the XCD mapping) and one
-// work-group per Sommerfeld boundary face: in the same launch for the phased kernel, in a second
-// launch (k_stage_ghost) for the LDS kernel.
+// 3 work-groups per patch (grid padded to a multiple of 8 for the XCD mapping).  The Sommerfeld
+// ghost faces get one more work-group each in the same launch with the phased kernel; with the
+// LDS kernel each slab work-group updates the ghost cells beside its own planes.
 hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn, double *acc, double *Qx,
                         const PatchGeom *geom, int32_t npatch, const RhsParams &p, int32_t precision,
-                        int32_t variant, const BoundaryFace *bf, const double *bg, int32_t nbf, const int32_t *nbr,
-                        int32_t paxes, const int32_t *gnbr, hipStream_t st)
+                        int32_t variant, const BoundaryFace *bf, const double *bg, int32_t nbf, const int32_t *pface,
+                        const int32_t *nbr, int32_t paxes, const int32_t *gnbr, hipStream_t st)
 {
+    // the LDS kernel updates the Sommerfeld ghosts inside the slab work-groups (per-leaf face table)
+    const int32_t *slab_ghosts = nbf > 0 ? pface : nullptr;
     const int64_t nb_slab = ((int64_t)npatch * 3 + 7) / 8 * 8;
     const int64_t nb = nb_slab + (nbf > 0 ? nbf : 0);
     const int32_t ns = (int32_t)nb_slab;
@@ -1300,23 +1317,17 @@ hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn
         if (p.advection) {
             if (precision == 1)
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<float, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, nbr, paxes, gnbr, lin);
+                                   ns, p, s, dt, bf, bg, slab_ghosts, nbr, paxes, gnbr, lin);
             else
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<double, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, nbr, paxes, gnbr, lin);
+                                   ns, p, s, dt, bf, bg, slab_ghosts, nbr, paxes, gnbr, lin);
         } else {
             if (precision == 1)
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<float, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, nbr, paxes, gnbr, lin);
+                                   ns, p, s, dt, bf, bg, slab_ghosts, nbr, paxes, gnbr, lin);
             else
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<double, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, nbr, paxes, gnbr, lin);
-        }
-        if (nbf > 0) {
-            const hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_stage_ghost, dim3((unsigned)nbf), dim3(256), 0, st, Qs, Qn, acc, Qx, geom, s, dt, bf,
-                               bg, p.shift == 0 ? 1 : 0);
+                                   ns, p, s, dt, bf, bg, slab_ghosts, nbr, paxes, gnbr, lin);
         }
     } else {
         const dim3 g((unsigned)nb), b(256);

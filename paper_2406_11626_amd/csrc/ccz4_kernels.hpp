@@ -22,8 +22,8 @@ hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t
                       int32_t precision, int32_t variant, hipStream_t st);
 hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn, double *acc, double *Qx,
                         const PatchGeom *geom, int32_t npatch, const RhsParams &p, int32_t precision,
-                        int32_t variant, const BoundaryFace *bf, const double *bg, int32_t nbf, const int32_t *nbr,
-                        int32_t paxes, const int32_t *gnbr, hipStream_t st);
+                        int32_t variant, const BoundaryFace *bf, const double *bg, int32_t nbf, const int32_t *pface,
+                        const int32_t *nbr, int32_t paxes, const int32_t *gnbr, hipStream_t st);
 hipError_t launch_rhs_sommerfeld(const double *Q, double *K, const PatchGeom *geom, const BoundaryFace *bf,
                                  const double *bg, int32_t nbf, int32_t frozen, hipStream_t st);
 hipError_t launch_capture_bg(const double *Q, const BoundaryFace *bf, double *bg, int32_t nbf, hipStream_t st);
