@@ -263,7 +263,8 @@ def run_gpu(args, w, precision, formulation=0, advection=0):
     order = " (plain block order)" if kc & ccz4.KERNEL_LINEAR_ORDER else ""
     # the kernels one stage call (one right-hand-side call) launches
     kname = ("k_stage_lds" if kc & ccz4.KERNEL_LDS else "k_stage") + targs + order
-    rname = ("k_rhs_lds" if kc & ccz4.KERNEL_LDS else "k_rhs") + targs + order + (" + k_rhs_sommerfeld" if nbf else "")
+    rname = ("k_rhs_lds" if kc & ccz4.KERNEL_LDS else "k_rhs") + targs + order + \
+        (" + k_rhs_sommerfeld" if nbf and not kc & ccz4.KERNEL_LDS else "")
     recon_ms = [a.elapsed_time(b) for a, b in recon_events]
     out = dict(wall=wall, wall_eager=wall_eager, tune_ms=tune_ms, cells=cells, patches=ctx.n_patches, rhs_ms=rhs_ms,
                reconstruct_ms=sum(recon_ms) / len(recon_ms) if recon_ms else None,

@@ -518,9 +518,7 @@ ccz4_status ccz4_rhs(ccz4_ctx *c, const double *Q, double *k, int32_t precision,
     if (!c->bface.empty() && !c->bg_valid)
         return fail(CCZ4_ESTATE, "Sommerfeld background not set (call ccz4_init_patches or ccz4_set_background)");
     HIP_TRY(launch_rhs(Q, k, c->d_geom.p, (int32_t)c->leaf.size(), c->prm, precision, c->kernel[precision],
-                       S(stream)));
-    HIP_TRY(launch_rhs_sommerfeld(Q, k, c->d_geom.p, c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(),
-                                  c->prm.shift == 0, S(stream)));
+                       c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(), c->d_pface.p, S(stream)));
     return CCZ4_OK;
 }
 

@@ -517,17 +517,14 @@ __device__ __forceinline__ void stage_ghost_face(int fi, int idx, int32_t s, dou
 }
 
 
-// The Sommerfeld ghost cells beside z-slab sl of patch p, updated by that slab's work-group after
+// The Sommerfeld ghost cells beside z-slab sl of patch p, handled by that slab's work-group after
 // its interior: of each boundary face of the patch, the ghost cells next to the slab's three planes
 // (81 for an x or y face; the whole face slab of 243 for the z face below slab 0 or above slab 2).
 // Those rows were just fetched and written by the same work-group, so the ghost update finds them
-// in the L2 instead of touching a line of HBM for every 3 ghost cells of an x face.
-__device__ __forceinline__ void stage_ghost_slab(int p, int sl, const int32_t *__restrict__ pface, int32_t s,
-                                                 double dt, const double *__restrict__ Qs,
-                                                 const double *__restrict__ Qn, double *__restrict__ acc,
-                                                 double *__restrict__ Qx, const PatchGeom *__restrict__ geom,
-                                                 const BoundaryFace *__restrict__ bf,
-                                                 const double *__restrict__ bg, int32_t frozen)
+// in the L2 instead of touching a line of HBM for every 3 ghost cells of an x face.  cell(fi, idx)
+// is called once for every such ghost cell (face fi of the boundary-face list, index idx in its slab).
+template <typename Cell>
+__device__ __forceinline__ void ghost_slab_cells(int p, int sl, const int32_t *__restrict__ pface, Cell &&cell)
 {
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
@@ -537,7 +534,56 @@ __device__ __forceinline__ void stage_ghost_slab(int p, int sl, const int32_t *_
         for (int r = (int)threadIdx.x; r < n; r += (int)blockDim.x) {
             // slab_coords order: x face idx = (L - 1) + 3 y + 27 z; y face idx = x + 9 z + 81 (L - 1)
             const int idx = axis == 0 ? 81 * sl + r : (axis == 1 ? 81 * (r / 27) + 27 * sl + r % 27 : r);
-            stage_ghost_face(fi, idx, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, frozen);
+            cell(fi, idx);
+        }
+    }
+}
+
+// Right-hand side G_L of all slots at ghost cell idx of boundary face fi (what k_rhs_sommerfeld
+// computes one thread per slot), the slots in batches of eight with every load of a batch first.
+__device__ __forceinline__ void rhs_ghost_cell(int fi, int idx, const double *__restrict__ Q, double *__restrict__ K,
+                                               const PatchGeom *__restrict__ geom,
+                                               const BoundaryFace *__restrict__ bf, const double *__restrict__ bg,
+                                               int32_t frozen)
+{
+    if (idx >= NFACE) return;
+    const BoundaryFace f = bf[fi];
+    int L, t1, t2;
+    slab_coords(f.axis, idx, L, t1, t2);
+    const int cg = ghost_c(f.side, L);
+    const int og = slab_off(f.axis, cg, t1, t2);
+    const int ci = L == 1 ? depth_c(f.side, 1) : ghost_c(f.side, L - 1);
+    const int oi = slab_off(f.axis, ci, t1, t2);
+    const PatchGeom g = geom[f.patch];
+    int cx, cy, cz;
+    if (f.axis == 0) { cx = cg; cy = t1 + 3; cz = t2 + 3; }
+    else if (f.axis == 1) { cx = t1 + 3; cy = cg; cz = t2 + 3; }
+    else { cx = t1 + 3; cy = t2 + 3; cz = cg; }
+    const double X = g.org[0] + (cx - 2.5) * g.dx[0];
+    const double Y = g.org[1] + (cy - 2.5) * g.dx[1];
+    const double Z = g.org[2] + (cz - 2.5) * g.dx[2];
+    const double rr = sqrt(X * X + Y * Y + Z * Z);
+    const double xn = f.axis == 0 ? X : (f.axis == 1 ? Y : Z);
+    const double *Qp = Q + (int64_t)f.patch * PS;
+    double *Kp = K + (int64_t)f.patch * PS;
+    const double *B = bg + (int64_t)f.bg * NV * NFACE + idx;
+    for (int v0 = 0; v0 < NV; v0 += SB8) {
+        double qL[SB8], qI[SB8], qB[SB8];
+#pragma unroll
+        for (int j = 0; j < SB8; ++j) {
+            const int v = v0 + j;
+            if (v >= NV) break;
+            qL[j] = Qp[v * CS + og];
+            qI[j] = Qp[v * CS + oi];
+            qB[j] = B[v * NFACE];
+        }
+#pragma unroll
+        for (int j = 0; j < SB8; ++j) {
+            const int v = v0 + j;
+            if (v >= NV) break;
+            Kp[v * CS + og] = (v == SK0 || (frozen && frozen_slot(v)))
+                                  ? 0.0
+                                  : -(rr / (fabs(xn) * g.dx[f.axis])) * (qL[j] - qI[j]) - (1.0 / rr) * (qL[j] - qB[j]);
         }
     }
 }
@@ -608,7 +654,8 @@ __device__ __forceinline__ void lds_cell_setup(double *lds, int sl, const PatchG
 template <typename T, int LOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rhs_lds(
     const double *__restrict__ Q, double *__restrict__ K, const PatchGeom *__restrict__ geom, int32_t npatch,
-    RhsParams prm, int32_t linear)
+    RhsParams prm, const BoundaryFace *__restrict__ bf, const double *__restrict__ bg,
+    const int32_t *__restrict__ pface, int32_t linear)
 {
     __shared__ double lds[LDS_DOUBLES];
     const int64_t lb = linear ? (int64_t)blockIdx.x : xcd_logical_block(blockIdx.x, gridDim.x);
@@ -626,6 +673,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     snk.so = prm.formulation;
     const HaloSrc hs{{0, 0, 0, 0}};
     rhs_slab_lds<T, LOP>(Q + (int64_t)p * PS, lds, sl, act, o, C, prm, snk, hs);
+    if (pface) {
+        const int32_t frozen = prm.shift == 0;
+        ghost_slab_cells(p, sl, pface, [&](int fi, int idx) { rhs_ghost_cell(fi, idx, Q, K, geom, bf, bg, frozen); });
+    }
 }
 
 struct LdsStageSink {
@@ -712,7 +763,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         hs.d[f] = n >= 0 ? (int64_t)(n - p) * PS + ((f & 1) ? -9 : 9) * (f < 2 ? YS : ZS) : 0;
     }
     rhs_slab_lds<T, LOP>(Qs + (int64_t)p * PS, lds, sl, act, o, C, prm, snk, hs);
-    if (pface) stage_ghost_slab(p, sl, pface, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, prm.shift == 0);
+    if (pface) {
+        const int32_t frozen = prm.shift == 0;
+        ghost_slab_cells(p, sl, pface, [&](int fi, int idx) {
+            stage_ghost_face(fi, idx, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, frozen);
+        });
+    }
 }
 
 // Sommerfeld ghosts: one thread per (boundary face, slot, ghost cell)
@@ -1264,22 +1320,30 @@ hipError_t launch_fill(double *Q, const FaceTask *tasks, int32_t ntask, int32_t 
 }
 
 hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t npatch, const RhsParams &p,
-                      int32_t precision, int32_t variant, hipStream_t st)
+                      int32_t precision, int32_t variant, const BoundaryFace *bf, const double *bg, int32_t nbf,
+                      const int32_t *pface, hipStream_t st)
 {
+    // the LDS kernel computes the Sommerfeld ghosts' right-hand side inside the slab work-groups;
+    // the phased kernel leaves it to k_rhs_sommerfeld
+    const int32_t *slab_ghosts = nbf > 0 ? pface : nullptr;
     const int64_t nb = ((int64_t)npatch * 3 + 7) / 8 * 8;
     const int32_t lin = (variant & KV_LINEAR) ? 1 : 0;
     if (variant & KV_LDS) {
         const dim3 g((unsigned)nb), b(256);
         if (p.advection) {
             if (precision == 1)
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<float, 1>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<float, 1>), g, b, 0, st, Q, K, geom, npatch, p, bf, bg,
+                                   slab_ghosts, lin);
             else
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<double, 1>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<double, 1>), g, b, 0, st, Q, K, geom, npatch, p, bf, bg,
+                                   slab_ghosts, lin);
         } else {
             if (precision == 1)
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<float, 0>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<float, 0>), g, b, 0, st, Q, K, geom, npatch, p, bf, bg,
+                                   slab_ghosts, lin);
             else
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<double, 0>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<double, 0>), g, b, 0, st, Q, K, geom, npatch, p, bf, bg,
+                                   slab_ghosts, lin);
         }
     } else {
         const dim3 g((unsigned)nb), b(256);
@@ -1293,6 +1357,11 @@ hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs<float, 0>), g, b, 0, st, Q, K, geom, npatch, p, lin);
             else
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs<double, 0>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+        }
+        if (nbf > 0) {
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            return launch_rhs_sommerfeld(Q, K, geom, bf, bg, nbf, p.shift == 0 ? 1 : 0, st);
         }
     }
     return hipGetLastError();

@@ -19,7 +19,8 @@ hipError_t launch_fill(double *Q, const FaceTask *tasks, int32_t ntask, int32_t 
 enum KernelVariant : int32_t { KV_PHASED = 0, KV_LDS = 1, KV_LINEAR = 2, KV_COUNT = 4 };
 
 hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t npatch, const RhsParams &p,
-                      int32_t precision, int32_t variant, hipStream_t st);
+                      int32_t precision, int32_t variant, const BoundaryFace *bf, const double *bg, int32_t nbf,
+                      const int32_t *pface, hipStream_t st);
 hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn, double *acc, double *Qx,
                         const PatchGeom *geom, int32_t npatch, const RhsParams &p, int32_t precision,
                         int32_t variant, const BoundaryFace *bf, const double *bg, int32_t nbf, const int32_t *pface,
