@@ -1103,60 +1103,16 @@ __global__ __launch_bounds__(256) void k_regrid(const double *__restrict__ Qo, d
     }
 }
 
-// Second-order formulation (Sec. 3.2, explicit gradient reconstruction; Algorithm 2): the
-// auxiliaries from central FD4 differences of the primaries by their definitions,
-// A_k = d_k alpha, B_k^i = d_k beta^i, D_kij = d_k gt_ij / 2, P_k = d_k phi, on the interior
-// cells of every leaf.  One thread per cell, three work-groups per patch; the primaries'
-// halos must be filled, except, with gnbr, the y and z face halos shared with a same-level leaf,
-// which are then read from that leaf's interior (as the LDS stage reads them).  With nbr, every
-// value within three layers of a face shared with a same-level leaf and normal to an axis of
-// paxes is also written into that leaf's face halo (as the stage push does).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_reconstruct(
-    double *__restrict__ Q, const PatchGeom *__restrict__ geom, int32_t npatch, const int32_t *__restrict__ nbr,
-    int32_t paxes, const int32_t *__restrict__ gnbr)
+// Differences of primaries V0..V1-1, staged in LDS buffers 0.., into the auxiliaries of the cell.
+template <int V0, int V1>
+__device__ __forceinline__ void reconstruct_from_lds(const LdsCell &C, double *__restrict__ qb, int o,
+                                                     const int64_t (&pd)[3])
 {
-    const int p = (int)(blockIdx.x / 3);
-    if (p >= npatch || threadIdx.x >= 243) return;
-    const int c = (int)(blockIdx.x % 3) * 243 + (int)threadIdx.x;
-    const int x = c % 9 + 3, y = (c / 9) % 9 + 3, z = c / 81 + 3;
-    // the primaries (slots 0..10) are only read and the auxiliaries (25..57) only written, so the
-    // two views of the state never touch the same element
-    const double *__restrict__ qr = Q + (int64_t)p * PS;
-    double *__restrict__ qw = Q + (int64_t)p * PS;
-    const int o = boff(x, y, z);
-    const PatchGeom g = geom[p];
-    int64_t pd[3];
-    push_offsets(nbr, p, x, y, z, o, pd, paxes);
-    // offsets of the stencil points at -2, -1, +1, +2 along each axis, with the y and z points
-    // outside the interior moved into the same-level neighbour when gathering
-    int64_t so[3][4];
-    double i12[3];
-    {
-        const int cc[3] = {x, y, z};
-        const int stride[3] = {1, YS, ZS};
+#pragma unroll
+    for (int v = V0; v < V1; ++v)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            i12[a] = 1.0 / (12.0 * g.dx[a]);
-            int64_t lo = 0, hi = 0;
-            if (a > 0 && gnbr) {
-                const int nl = gnbr[p * 6 + 2 * a], nh = gnbr[p * 6 + 2 * a + 1];
-                lo = nl >= 0 ? (int64_t)(nl - p) * PS + 9 * stride[a] : 0;
-                hi = nh >= 0 ? (int64_t)(nh - p) * PS - 9 * stride[a] : 0;
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = j < 2 ? j - 2 : j - 1;
-                const int ck = cc[a] + k;
-                so[a][j] = (int64_t)k * stride[a] + (ck < 3 ? lo : (ck > 11 ? hi : 0));
-            }
-        }
-    }
-#pragma unroll
-    for (int v = 0; v <= SPHI; ++v) {
-        const double *f = qr + v * CS + o;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const double d = (8.0 * (f[so[a][2]] - f[so[a][1]]) - (f[so[a][3]] - f[so[a][0]])) * i12[a];
+            const double d = fd(C, v - V0, a);
             // D_a(ij) = d_a gt_ij / 2, A_a = d_a alpha, B_a^i = d_a beta^i, P_a = d_a phi
             const int dst = v < SALPHA ? SD + 6 * a + v
                           : v == SALPHA ? SA + a
@@ -1164,20 +1120,76 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                      : SP + a;
             const double u = v < SALPHA ? 0.5 * d : d;
             const int64_t e = (int64_t)dst * CS + o;
-            qw[e] = u;
+            qb[e] = u;
 #pragma unroll
             for (int k = 0; k < 3; ++k)
-                if (pd[k] != 0) qw[e + pd[k]] = u;
+                if (pd[k] != 0) qb[e + pd[k]] = u;
         }
-    }
 }
+
+// Second-order formulation (Sec. 3.2, explicit gradient reconstruction; Algorithm 2): the
+// auxiliaries from central FD4 differences of the primaries by their definitions,
+// A_k = d_k alpha, B_k^i = d_k beta^i, D_kij = d_k gt_ij / 2, P_k = d_k phi, on the interior
+// cells of every leaf.  One work-group per z-slab copies the slab's 11 primaries into LDS exactly as
+// the stage kernel stages a slot (the slab's planes with their x and y halos, the interior rows of
+// the three planes below and above), then every lane forms its cell's 33 differences from LDS
+// (110 KB: one work-group per CU; two rounds of six primaries in 60 KB, two work-groups per CU, ran
+// 5% slower; one thread per cell reading its stencils through the caches ran 30% slower).  The
+// primaries' halos must be filled, except, with gnbr, the y and z face halos shared with a
+// same-level leaf, which are then read from that leaf's interior.  With nbr, every value within
+// three layers of a face shared with a same-level leaf and normal to an axis of paxes is also
+// written into that leaf's face halo (as the stage push does).
+__global__ __launch_bounds__(256) void k_reconstruct_lds(double *__restrict__ Q, const PatchGeom *__restrict__ geom,
+                                                         int32_t npatch, const int32_t *__restrict__ nbr,
+                                                         int32_t paxes, const int32_t *__restrict__ gnbr)
+{
+    __shared__ double lds[(SPHI + 1) * LDS_SLOT];
+    const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int p = (int)(lb / 3);
+    if (p >= npatch) return;  // uniform over the work-group
+    const int sl = (int)(lb % 3);
+    const PatchGeom g = geom[p];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const bool act = tid < 243;
+    const int cc = act ? tid : 242;
+    const int x = cc % 9 + 3, y = (cc / 9) % 9 + 3, zl = cc / 81;
+    LdsCell C;
+    C.s = lds;
+    C.c = zl * ZS + y * YS + x;
+#pragma unroll
+    for (int k = -3; k <= 3; ++k) {
+        const int z2 = zl + k;
+        C.zo[k + 3] = (z2 >= 0 && z2 <= 2) ? z2 * ZS + y * YS + x
+                                            : LDS_OWN + (z2 < 0 ? z2 + 3 : z2) * 90 + (y - 3) * LDS_HROW + (x - 2);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        C.i12[a] = 1.0 / (12.0 * g.dx[a]);
+        C.koc[a] = 0.0;
+    }
+    HaloSrc hs;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {  // faces y-, y+, z-, z+
+        const int n = gnbr ? gnbr[p * 6 + 2 + f] : -1;
+        hs.d[f] = n >= 0 ? (int64_t)(n - p) * PS + ((f & 1) ? -9 : 9) * (f < 2 ? YS : ZS) : 0;
+    }
+    double *qb = Q + (int64_t)p * PS;
+    const int z = zl + 3 + 3 * sl;
+    const int o = boff(x, y, z);
+    int64_t pd[3];
+    push_offsets(nbr, p, x, y, z, o, pd, paxes);
+    const int slots[SPHI + 1] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10};
+    lds_round(qb, lds, sl, slots, w, lane, hs);
+    if (act) reconstruct_from_lds<0, SPHI + 1>(C, qb, o, pd);
+}
+
 
 hipError_t launch_reconstruct(double *Q, const PatchGeom *geom, int32_t npatch, const int32_t *nbr, int32_t paxes,
                               const int32_t *gnbr, hipStream_t st)
 {
     if (npatch <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reconstruct, dim3((unsigned)npatch * 3u), dim3(256), 0, st, Q, geom, npatch, nbr, paxes,
-                       gnbr);
+    const int64_t nb = ((int64_t)npatch * 3 + 7) / 8 * 8;  // a multiple of 8 for the XCD block order
+    hipLaunchKernelGGL(k_reconstruct_lds, dim3((unsigned)nb), dim3(256), 0, st, Q, geom, npatch, nbr, paxes, gnbr);
     return hipGetLastError();
 }
 
