@@ -363,6 +363,45 @@ def test_full_size_sampled(cfg):
     assert e.max() <= 1e-13, ("init", e.argmax(), e.max())
 
 
+def test_full_size_step_graph_sampled():
+    """The single puncture on its full 16^3-leaf mesh, one RK4 step in the launch configuration
+    of the benchmark (autotuned fused stage kernel and block order, the step's halo flags, the
+    captured step graph), against the oracle's RK4 step on the whole mesh, compared on sampled
+    leaves: the interior, and the Sommerfeld ghost slabs of boundary leaves."""
+    w = scenarios.config(2)
+    ctx, m = make_pair(w.n0, w.origin, w.extent, w.bc, w.params(), w.refined)
+    Qo = m.zeros()
+    m.init(Qo, w.scenario, w.scen)
+    m.fill_halos(Qo)
+    m.set_background(Qo)
+    sel = _sample_patches(m.ids)
+    Q0 = Qo[sel].copy()
+    Qd = to_gpu(Qo)
+    ctx.set_background(Qd)
+    ctx.autotune(Qd, reps=1)
+    ctx.fill_halos(Qd)
+    dt = w.dt()
+    Qo = m.rk4_step(oparams(w.params()), Qo, dt)
+    ref = Qo[sel].copy()
+    del Qo
+    bufs = (ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0))
+    g = ctx.step_graph(Qd, bufs, dt)
+    g.launch()
+    torch.cuda.synchronize()
+    g.close()
+    del bufs
+    got = to_host(Qd, sel)
+    del Qd
+    e = parity_error(got, ref, INTERIOR)
+    assert e.max() <= 1e-11, ("interior", e.argmax(), e.max())
+    bm = boundary_ghost_mask(m, w.n0)[sel]
+    eg = parity_error(np.where(bm[..., None], got, 0.0), np.where(bm[..., None], ref, 0.0), SLABS)
+    assert eg.max() <= 1e-11, ("ghosts", eg.argmax(), eg.max())
+    assert bm.any()
+    # the step moved the state: the comparison is not one of unchanged data
+    assert np.abs(ref[:, 3:12, 3:12, 3:12] - Q0[:, 3:12, 3:12, 3:12]).max() > 1e-10
+
+
 # ------------------------------------------------------------------ fused stage
 
 def _fused_vs_oracle(w, n0, refined=(), steps=2, perturb=False, kernel=ccz4.KERNEL_LDS, push=True):
