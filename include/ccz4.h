@@ -59,7 +59,7 @@ enum { CCZ4_SCEN_GAUGE_WAVE = 0, CCZ4_SCEN_PUNCTURE = 1, CCZ4_SCEN_BL_BY = 2 };
 /* Parameters of App. B (kappa1..3, tau, e, c, mu, f, eta), the KO strength epsilon of
    App. D, the slicing function g(alpha) (harmonic: 1; 1+log: 2/alpha), the shift
    condition (frozen: beta, b, B do not evolve; Gamma-driver: s = 1) and the formulation
-   (Sec. 2.4): first order (all 58 variables evolve, with the red constraint-addition terms of
+   (Sec. 2.2): first order (all 58 variables evolve, with the red constraint-addition terms of
    App. B) or second order (the 24 primaries evolve without the red terms; the auxiliaries
    A, B, D, P are recomputed from the primaries after every update, ccz4_reconstruct_aux), and
    the derivative taken in the advection terms beta^k d_k Q (App. D): the central FD4 difference,
@@ -163,7 +163,9 @@ ccz4_status ccz4_plan_counts(const ccz4_ctx *ctx, int64_t *counts);
    (the Sommerfeld ghost slots keep G_L for every slot). */
 ccz4_status ccz4_rhs(ccz4_ctx *ctx, const double *Q, double *k, int32_t precision, void *stream);
 
-/* RK4 stage.  Stage s (0..3) of classical RK4 in two-register form, on interior cells and
+/* RK4 stage (Sec. 3.2: Runge-Kutta time stepping of the FD4 solver up to fourth order, with a
+   global time step over all levels; the algebraic post-processing of Sec. 4.2.1 after each step).
+   Stage s (0..3) of classical RK4 in two-register form, on interior cells and
    Sommerfeld ghosts:  s=0: acc = Qn + dt/6 k, Qnext = Qn + dt/2 k;  s=1: acc += dt/3 k,
    Qnext = Qn + dt/2 k;  s=2: acc += dt/3 k, Qnext = Qn + dt k;  s=3: Qnext = acc + dt/6 k,
    then gt <- gt/det(gt)^(1/3) and At <- At - gt tr(At)/3 on interior cells.  dt > 0.
@@ -227,12 +229,12 @@ ccz4_status ccz4_reconstruct_aux(ccz4_ctx *ctx, double *Q, int32_t flags, void *
 ccz4_status ccz4_tracers_sample(ccz4_ctx *ctx, const double *Q, int64_t n, const double *pos, int32_t nslots,
                                 const int32_t *slots, double *out, void *stream);
 
-/* Puncture trackers (Sec. 4: tracers moved by the reversed shift).  One explicit Euler step of the
+/* Puncture trackers (Sec. 4.2.3: tracers moved by the reversed shift).  One explicit Euler step of the
    Sec. 3.8 rule x <- x + dt v with v = -beta(x), beta interpolated as in ccz4_tracers_sample; pos
    (device) is updated in place; a point outside every leaf stays.  Q's halos must be filled. */
 ccz4_status ccz4_tracers_advance(ccz4_ctx *ctx, const double *Q, int64_t n, double *pos, double dt, void *stream);
 
-/* Refinement tags by coordinates (Sec. 3, dynamic refinement based on coordinates): with the
+/* Refinement tags by coordinates (Sec. 4.2.1, dynamic refinement based on coordinates): with the
    per-level radii r[0..nradii-1] (host), a leaf of level l < min(max_level, nradii) whose closed
    cube lies within r[l] of one of the n tracers pos[n][3] (device) is tagged REFINE (1); a leaf of
    level l >= 1 whose parent cube lies farther than r[l-1] from every tracer COARSEN (-1); every
@@ -286,7 +288,8 @@ void ccz4_step_graph_destroy(ccz4_graph *graph);
 ccz4_status ccz4_constraints(ccz4_ctx *ctx, const double *Q, double *HM, double r_excise,
                              double *norms_host, void *stream);
 
-/* Refinement tags.  Plain refinement criterion per leaf (requires filled halos): indicator[p] =
+/* Refinement tags (Sec. 3.6: feature-based refinement by the largest difference between two
+   adjacent volumes of a patch).  Plain refinement criterion per leaf (requires filled halos): indicator[p] =
    (max |chi_a - chi_b|, max |alpha_a - alpha_b| over face-adjacent interior cells a, b with
    chi = phi^2, dx^2 max |H|) and e = the largest of the three.  tags[p] = +1 (refine) if
    e >= theta_r and level < max_level; -1 (coarsen) if level > 0, e < theta_c and all 27
@@ -317,7 +320,7 @@ ccz4_status ccz4_regrid_transfer(const ccz4_ctx *old_ctx, const double *Qold, co
 
 /* ---------------------------------------------------------------------------------------
    Learned refinement indicator (a project addition on the refinement-criterion hook of the
-   paper's Sec. 3): a small perceptron, trained on tags of the plain criterion, that can add
+   paper's Sec. 3.6): a small perceptron, trained on tags of the plain criterion, that can add
    refinement ahead of the plain criterion and veto its coarsening; the plain criterion stays
    the fallback.  Parameter vector of CCZ4_MLP_NPARAM floats, row-major (out x in):
      W1[64][81] b1[64] W2[64][64] b2[64] W3[3][64] b3[3].

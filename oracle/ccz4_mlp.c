@@ -1,6 +1,6 @@
 /*
  * ccz4_mlp.c -- oracle of the learned refinement indicator (a project addition built on the
- * paper's refinement-criterion hook, Sec. 3): per-patch features and a small multilayer
+ * paper's refinement-criterion hook, Sec. 3.6): per-patch features and a small multilayer
  * perceptron with its loss gradient and an Adam step.
  *
  * TEST INFRASTRUCTURE ONLY (see ccz4_oracle.h).  Plain loops in FP64.  With bf16 = 1 every

@@ -802,7 +802,7 @@ void orc_rhs(const orc_mesh *m, const orc_params *pr, const double *Q, double *k
 
 /* ----------------------------------------------------------------------------------------
  * Tracers (Sec. 3.8): a point's value is the trilinear interpolation of the 2^3 cell centres
- * around it in the leaf that holds it; puncture trackers (Sec. 4) move with velocity -beta by
+ * around it in the leaf that holds it; puncture trackers (Sec. 4.2.3) move with velocity -beta by
  * the explicit Euler rule x <- x + dt v.
  * ---------------------------------------------------------------------------------------- */
 int64_t orc_find_leaf(const orc_mesh *m, const double x[3])
@@ -923,7 +923,7 @@ void orc_tag_tracers(const orc_mesh *m, int64_t n, const double *pos, int nrad, 
 }
 
 /* ----------------------------------------------------------------------------------------
- * Second-order formulation (Sec. 2.4; Sec. 3.2, explicit gradient reconstruction; Algorithm 2):
+ * Second-order formulation (Sec. 2.2; Sec. 3.2, explicit gradient reconstruction; Algorithm 2):
  * after each update the auxiliaries are recomputed from the primaries with the central FD4
  * difference, by their definitions A_i = d_i alpha, B_k^i = d_k beta^i,
  * D_kij = d_k gt_ij / 2, P_i = d_i phi (eq. auxiliary-variables).  Interior cells of every
@@ -1203,7 +1203,7 @@ void orc_tag_learned(const orc_mesh *m, const float *logits, const int8_t *plain
 }
 
 /* ----------------------------------------------------------------------------------------
- * Regrid (dynamic AMR on the refinement-criterion hook, Sec. 3): the refined cubes of the mesh
+ * Regrid (dynamic AMR on the refinement-criterion hook, Sec. 3.6): the refined cubes of the mesh
  * after per-leaf tags, and the transfer of a state onto the new leaves.
  * ---------------------------------------------------------------------------------------- */
 typedef struct {

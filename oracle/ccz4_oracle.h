@@ -109,7 +109,7 @@ int64_t orc_constraints(const orc_mesh *m, const double *Q, double *HM /* [n][72
                         double r_excise, double norms[3]);
 void orc_tag_indicator(const orc_mesh *m, const double *Q, double *ind /* [n][3] */);
 
-/* ---- tracers (Sec. 3.8) and puncture trackers (Sec. 4, puncture tracking) ---- */
+/* ---- tracers (Sec. 3.8) and puncture trackers (Sec. 4.2.3, puncture tracking) ---- */
 /* the leaf whose interior box [o, o + 9 dx) holds x, or -1 */
 int64_t orc_find_leaf(const orc_mesh *m, const double x[3]);
 /* trilinear interpolation of nslot slots at n points pos[n][3] from the 2^3 cell centres around
@@ -120,7 +120,7 @@ int64_t orc_tracer_sample(const orc_mesh *m, const double *Q, int64_t n, const d
 /* one explicit Euler step of puncture trackers: x <- x + dt v with v = -beta(x) interpolated as
    above; points outside every leaf stay; returns their number */
 int64_t orc_tracer_advance(const orc_mesh *m, const double *Q, int64_t n, double *pos, double dt);
-/* Tracker-based refinement tags (Sec. 3, refinement by coordinates): with R_l = radii[l],
+/* Tracker-based refinement tags (Sec. 4.2.1, refinement by coordinates): with R_l = radii[l],
    a leaf of level l < min(max_level, nrad) whose cube lies within R_l of a tracer gets REFINE (1);
    a leaf of level l >= 1 whose parent cube lies farther than R_(l-1) from every tracer gets
    COARSEN (-1); every other leaf KEEP (0).  Distances are from the tracer to the nearest point

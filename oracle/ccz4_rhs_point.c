@@ -12,7 +12,7 @@
  *     d_(k B_l)^i = (d_k B_l^i + d_l B_k^i)/2, d_(i A_j) = (d_i A_j + d_j A_i)/2;
  *   - the Ricci tensor R_ij is evaluated for all nine index pairs from the relations of
  *     App. B and its symmetric part enters the At equation (its trace uses all nine);
- *   - second-order formulation (pr->formulation = 1, Sec. 2.4 and Algorithm 2): the same
+ *   - second-order formulation (pr->formulation = 1, Sec. 2.2 and Algorithm 2): the same
  *     equations for the primaries with the red terms removed (App. B: they are used in the
  *     first-order formulation only), and zero right-hand sides for A, B, D, P.
  * dq[k][v] is the derivative along axis k of slot v; only slots 11..57 are ever read.

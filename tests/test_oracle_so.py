@@ -1,4 +1,4 @@
-"""Pins of the oracle's second-order formulation (Sec. 2.4; Sec. 3.2 "explicit gradient reconstruction";
+"""Pins of the oracle's second-order formulation (Sec. 2.2; Sec. 3.2 "explicit gradient reconstruction";
 Algorithm 2, and the remark of App. B that the red terms belong to the first-order system only):
 the reconstruction of A, B, D, P is exact on quartic primaries, the right-hand side of the
 primaries still converges to the exact time derivative at fourth order, and a trace shift of
