@@ -1,17 +1,24 @@
 """Benchmark of the CCZ4 FD4 hot path on one MI355X.
 
-A step is one classical RK4 step of the whole hot path over the single-puncture workload of
-16^3 patches of 9^3 cells (144^3 = 2,985,984 cells on [-9,9]^3, Sommerfeld boundaries, 1+log
-slicing, Gamma-driver): four fused stages (FD4 derivatives + CCZ4 algebra + Kreiss-Oliger + RK4
-stage combine, the last stage with the algebraic projection), each of which also writes the
-same-level face halos of its output; the Neumann and coarse-fine halo fill between stages has
-no faces on this uniform mesh.  The metric is cell-updates per second per RK4 stage: cells x 4
-stages x steps / wall time, with the state resident in HBM.
+A step is one classical RK4 step of the whole hot path over the largest single-GPU workload by
+default: the single puncture on 24^3 patches of 9^3 cells (216^3 = 10,077,696 cells on [-9,9]^3,
+Sommerfeld boundaries, 1+log slicing, Gamma-driver; six state-sized buffers of 23.5 GB).  The
+step is four fused stages (FD4 derivatives + CCZ4 algebra + Kreiss-Oliger + RK4 stage combine,
+the last stage with the algebraic projection) captured in one HIP graph; each stage also writes
+the same-level face halos its successor needs, so on a uniform mesh no fill kernel runs between
+stages.  The metric is cell-updates per second per RK4 stage: cells x 4 stages x steps / wall
+time, with the state resident in HBM.
 
-The roofline object is the fused stage kernel's: algorithmic bytes per launch (per cell: every
-evolved slot with its three-cell face halos read once, the step state and accumulator streamed
-as the stage requires; plus the same-level halo cells written) over its average launch time,
-taken with events on the launch stream.
+Beside the FP64 graph step (the headline `value`) the line carries: the mixed-precision step and
+its state error against the FP64 step after the same number of steps (the FP64 GPU step is held
+to the oracle by the parity tests), the constraint norms of both over 50 steps, the plain
+unfused path (halo fill, right-hand side, RK4 stage as three calls per stage) timed on the same
+workload, the standalone right-hand-side kernel, and the oracle on the host cores.
+
+The roofline object is the fused stage kernel's: 3304 algorithmic bytes per cell-stage (every
+evolved slot with its three-cell face halos read once, Q^n and the accumulator read, the
+accumulator and Q_next written) over its average launch time, taken with events on the launch
+stream; the halo copies and Sommerfeld ghost updates the launch also does are reported apart.
 
 Prints one JSON line.  --gpus N > 1 is not supported (the path runs on one GPU).
 """
@@ -27,6 +34,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 NV = 59
+# Algorithmic bytes per interior cell: fused stage (the evolved slots over interior and face halos,
+# 3 x 472, plus Q^n and the accumulator read, 2 x 472, plus the accumulator and Q_next written,
+# 2 x 472) and standalone right-hand side (3 x 472 read, 472 written).
+FUSED_BYTES_PER_CELL = 3304
+RHS_BYTES_PER_CELL_MODEL = 1888
+METRIC = "CCZ4 cell-updates/s per RK4 stage (FP64 vs mixed), % of FP64/HBM roofline"
 # Fused stage, bytes per interior cell.  Q_s: the 58 evolved slots with interior + face halos
 # (2187 cell-vectors per 729 cells) and K_0 pointwise.  Streamed, per stage s:
 #   s = 0: read Q_n, write acc, write Q_next;  s = 1, 2: read/write acc, read Q_n, write Q_next;
@@ -85,8 +98,16 @@ def same_level_faces_per_axis(ctx):
     return count
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_stage_lds_puncture16_hbm_traffic.md")
-FLOPS_FILE = os.path.join(ROOT, "profiles", "k_stage_lds_puncture16_fp64_ops.md")
+# workload tags of the committed counter summaries (profiles/<kernel>_<tag>_<what>.md)
+WORKLOAD_TAG = {2: "puncture16", 3: "puncture_static3", 4: "puncture24", 5: "bbh_amr4"}
+
+
+def traffic_file(config):
+    return os.path.join(ROOT, "profiles", f"k_stage_lds_{WORKLOAD_TAG.get(config, config)}_hbm_traffic.md")
+
+
+def flops_file(config):
+    return os.path.join(ROOT, "profiles", f"k_stage_lds_{WORKLOAD_TAG.get(config, config)}_fp64_ops.md")
 
 
 def kernel_source_digest():
@@ -124,15 +145,16 @@ def _record_float(rec, key):
         return None
 
 
-def measured_traffic(config):
-    """HBM bytes per launch of the fused stage kernel from the committed counter summary."""
-    return _record_float(_profile_record(TRAFFIC_FILE, config), "hbm_bytes_per_launch")
+def measured_traffic(config, key="hbm_bytes_per_launch"):
+    """HBM bytes per launch of the fused stage kernel (or, with key hbm_bytes_per_rhs_launch, of the
+    standalone right-hand side) from the committed counter summary."""
+    return _record_float(_profile_record(traffic_file(config), config), key)
 
 
 def measured_fp64_ops(config):
     """FP64 operations per launch of the fused stage kernel and of the standalone right-hand side
     (64 lanes x (ADD + MUL + 2 FMA + TRANS) wave instructions) from the committed counter summary."""
-    rec = _profile_record(FLOPS_FILE, config)
+    rec = _profile_record(flops_file(config), config)
     return _record_float(rec, "fp64_ops_per_stage_launch"), _record_float(rec, "fp64_ops_per_rhs_launch")
 
 
@@ -165,7 +187,15 @@ def copy_bandwidth(nbytes=2**30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def run_gpu(args, w, precision, formulation=0, advection=0):
+def _say(msg):
+    print("# " + msg, file=sys.stderr, flush=True)
+
+
+def run_gpu(args, w, precision, formulation=0, advection=0, total_steps=0, keep=False, rhs=True):
+    """One leg of the benchmark: the fused step on workload w, eager (events per stage launch)
+    and as the captured graph (the timed value), then untimed graph steps up to total_steps steps
+    since the initial data; constraint norms at t = 0 and at the end.  keep: also return the final
+    state (the caller frees it)."""
     import torch
     from paper_2406_11626_amd import ccz4
     prm = ccz4.params(**{**w.prm, "formulation": formulation, "advection": advection})
@@ -183,6 +213,7 @@ def run_gpu(args, w, precision, formulation=0, advection=0):
     if so:  # the auxiliaries of the initial data from its primaries
         ctx.reconstruct(Q, True, stream)
         ctx.fill_halos(Q, stream)
+    norms0, _ = ctx.constraints(Q, r_excise=1.0)
     tune_ms = ctx.autotune(Q, precision, reps=2) if args.autotune else None
     ctx.fill_halos(Q, stream)
 
@@ -211,28 +242,40 @@ def run_gpu(args, w, precision, formulation=0, advection=0):
                     recon_events.append((r0, r1))
         ctx.fill_halos_kinds(Q, rest, stream)
 
+    done = 0
     for _ in range(args.warmup):
         step(False)
+        done += 1
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step(True)
+        done += 1
         if args.progress:
-            print(f"# step {i + 1}/{args.steps}", file=sys.stderr, flush=True)
+            _say(f"step {i + 1}/{args.steps}")
     torch.cuda.synchronize()
     wall_eager = time.perf_counter() - t0
     # the same step captured once as a HIP graph and replayed (the production path)
     graph = ctx.step_graph(Q, (Q1, Q2, acc), dt, precision)
     for _ in range(args.warmup):
         graph.launch(stream)
+        done += 1
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         graph.launch(stream)
+        done += 1
         if args.progress:
-            print(f"# graph step {i + 1}/{args.steps}", file=sys.stderr, flush=True)
+            _say(f"graph step {i + 1}/{args.steps}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    while done < total_steps:  # untimed, up to the drift horizon
+        graph.launch(stream)
+        done += 1
+        if done % 10 == 0:
+            torch.cuda.synchronize()
+            _say(f"step {done}/{total_steps}")
+    torch.cuda.synchronize()
     graph.close()
     cells = ctx.n_patches * 729
     faces = same_level_faces_per_axis(ctx)
@@ -243,7 +286,8 @@ def run_gpu(args, w, precision, formulation=0, advection=0):
             faces[0] if fl & ccz4.STAGE_FILL_SAME_LEVEL_X else 0)
     # the standalone right-hand side on the final state (its own kernel, same launch configuration)
     rhs_ms = None
-    if precision == ccz4.PREC_FP64 and not so:
+    if rhs and precision == ccz4.PREC_FP64 and not so:
+        del Q1
         kbuf = ctx.new_state(0.0)
         ctx.rhs(Q, kbuf, precision, stream)
         r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -254,28 +298,121 @@ def run_gpu(args, w, precision, formulation=0, advection=0):
         torch.cuda.synchronize()
         rhs_ms = r0.elapsed_time(r1) / 5
         del kbuf
+        Q1 = None
     stage_ms = [a.elapsed_time(b) for _, a, b, _ in events]
     nbf = ctx.plan_counts()["sommerfeld"]
     launch_bytes = [stage_bytes(s, cells, pushed(fl), nbf) for s, _, _, fl in events]
+    halo_bytes = [HALO_BYTES_PER_FACE * pushed(fl) for s, _, _, fl in events]
+    ghost_bytes = [GHOST_VECTORS[s] * 8 * NV * 243 * nbf for s, _, _, fl in events]
     norms, st = ctx.constraints(Q, r_excise=1.0)
     kc = ctx.get_kernel(precision)
     targs = ("<double, " if precision == ccz4.PREC_FP64 else "<float, ") + ("1>" if advection else "0>")
-    order = " (plain block order)" if kc & ccz4.KERNEL_LINEAR_ORDER else ""
+    border = " (plain block order)" if kc & ccz4.KERNEL_LINEAR_ORDER else ""
     # the kernels one stage call (one right-hand-side call) launches
-    kname = ("k_stage_lds" if kc & ccz4.KERNEL_LDS else "k_stage") + targs + order
-    rname = ("k_rhs_lds" if kc & ccz4.KERNEL_LDS else "k_rhs") + targs + order + \
+    kname = ("k_stage_lds" if kc & ccz4.KERNEL_LDS else "k_stage") + targs + border
+    rname = ("k_rhs_lds" if kc & ccz4.KERNEL_LDS else "k_rhs") + targs + border + \
         (" + k_rhs_sommerfeld" if nbf and not kc & ccz4.KERNEL_LDS else "")
     recon_ms = [a.elapsed_time(b) for a, b in recon_events]
+    avg = lambda v: sum(v) / len(v)  # noqa: E731
     out = dict(wall=wall, wall_eager=wall_eager, tune_ms=tune_ms, cells=cells, patches=ctx.n_patches, rhs_ms=rhs_ms,
-               reconstruct_ms=sum(recon_ms) / len(recon_ms) if recon_ms else None,
-               stage_ms=sum(stage_ms) / len(stage_ms),
-               stage_bytes=sum(launch_bytes) / len(launch_bytes),
-               stage_gbs=sum(launch_bytes) / (sum(stage_ms) * 1e-3) / 1e9, norms=norms, status=st,
-               kernel=kname, rhs_kernel=rname, ghost_faces=nbf)
-    del Q, Q1, Q2, acc
+               reconstruct_ms=avg(recon_ms) if recon_ms else None, stage_ms=avg(stage_ms),
+               stage_ms_by_s=[avg([t for (s, _, _, _), t in zip(events, stage_ms) if s == q]) for q in range(4)],
+               stage_bytes=avg(launch_bytes), halo_bytes=avg(halo_bytes), ghost_bytes=avg(ghost_bytes),
+               stage_gbs=sum(launch_bytes) / (sum(stage_ms) * 1e-3) / 1e9, norms=norms, norms0=norms0, status=st,
+               kernel=kname, rhs_kernel=rname, ghost_faces=nbf, steps_total=done, dt=dt)
+    if keep:
+        out["Q"] = Q
+    del Q, Q2, acc
     ctx.close()
     torch.cuda.empty_cache()
     return out
+
+
+def run_plain(args, w, total_steps=0, keep=False):
+    """The plain, unfused FP64 path on workload w: per stage a full halo fill, the right-hand side
+    into a state-sized k, and the RK4 stage combine (three calls, each its own launch), with
+    events per call; total_steps as in run_gpu."""
+    import torch
+    from paper_2406_11626_amd import ccz4
+    ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, w.params(), w.refined)
+    Q = ctx.new_state(0.0)
+    ctx.init_patches(Q, w.scenario, w.scen)
+    Qs, k, acc = ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0)
+    dt = w.dt()
+    stream = torch.cuda.current_stream()
+    ev = {"fill": [], "rhs": [], "rk4_stage": []}
+
+    def timed(name, fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        ev[name].append((e0, e1))
+
+    def step(with_events):
+        cur = Q
+        for s in range(4):
+            nxt = Q if s == 3 else Qs
+            if with_events:
+                timed("fill", lambda: ctx.fill_halos(cur, stream))
+                timed("rhs", lambda: ctx.rhs(cur, k, ccz4.PREC_FP64, stream))
+                timed("rk4_stage", lambda: ctx.rk4_stage(s, dt, Q, k, acc, nxt, stream))
+            else:
+                ctx.fill_halos(cur, stream)
+                ctx.rhs(cur, k, ccz4.PREC_FP64, stream)
+                ctx.rk4_stage(s, dt, Q, k, acc, nxt, stream)
+            cur = nxt
+
+    done = 0
+    for _ in range(args.warmup):
+        step(False)
+        done += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(False)
+        done += 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step(True)  # one more step with events per call
+    done += 1
+    while done < total_steps:
+        step(False)
+        done += 1
+        if done % 10 == 0:
+            torch.cuda.synchronize()
+            _say(f"plain step {done}/{total_steps}")
+    torch.cuda.synchronize()
+    ctx.fill_halos(Q, stream)
+    norms, _ = ctx.constraints(Q, r_excise=1.0)
+    ms = {n: sum(a.elapsed_time(b) for a, b in v) / len(v) for n, v in ev.items()}
+    out = dict(wall=wall, cells=ctx.n_patches * 729, norms=norms, steps_total=done, call_ms=ms)
+    if keep:
+        out["Q"] = Q
+    del Q, Qs, k, acc
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def state_error(Qa, Qb, chunk=256):
+    """Per-slot error of state Qa against Qb over the interior cells: max|a - b| / max|b| for slots
+    above 1e-10 of the largest slot, max|a - b| / (largest slot) for the others (the parity
+    measure of the tests).  Returns (per-slot list, largest value, its slot)."""
+    import torch
+    n = Qa.shape[0]
+    diff = torch.zeros(NV, dtype=torch.float64, device=Qa.device)
+    scale = torch.zeros(NV, dtype=torch.float64, device=Qa.device)
+    for p0 in range(0, n, chunk):
+        a = Qa[p0:p0 + chunk, :, 3:12, 3:12, 3:12]
+        b = Qb[p0:p0 + chunk, :, 3:12, 3:12, 3:12]
+        diff = torch.maximum(diff, (a - b).abs().amax(dim=(0, 2, 3, 4)))
+        scale = torch.maximum(scale, b.abs().amax(dim=(0, 2, 3, 4)))
+    diff, scale = diff.cpu().tolist(), scale.cpu().tolist()
+    top = max(max(scale), 1e-300)
+    e = [d / (sc if sc > 1e-10 * top else top) for d, sc in zip(diff, scale)]
+    k = max(range(NV), key=lambda i: e[i])
+    return e, e[k], k
 
 
 def run_stability(args, w):
@@ -473,41 +610,75 @@ def run_dynamic(args, w):
                 learned_inference_ms=t_learned * 1e3, norms=norms, logits_shape=list(logits.shape))
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, target_s):
-    """The oracle (single-threaded C, as it stands) on a bounded sample of the same workload:
-    the full mesh is initialised and filled once, then one RK4 stage's RHS is timed on a sample
-    of patches; the fill of the whole mesh and the stage combine are pro-rated to the sample."""
+    """The oracle (plain C, as it stands; OpenMP over patches changes no arithmetic) on a bounded
+    piece of the workload: the 8^3-patch sub-box around the puncture at the workload's spacing
+    (512 patches, 373,248 cells).  All host threads: whole RK4 steps (per stage a fill of the
+    sub-box, the right-hand side of every patch and the stage combine) until target_s / 2 has
+    passed.  One thread: one stage on a sample of patches sized to target_s / 2, the fill and
+    combine pro-rated."""
     import numpy as np
     import oracle as orc
-    from paper_2406_11626_amd import ccz4
-    m = orc.Mesh(w.n0, w.origin, w.extent, w.bc, w.refined)
+    from paper_2406_11626_amd import ccz4, scenarios
+    sw = scenarios.subbox(w) if not w.refined else w
+    m = orc.Mesh(sw.n0, sw.origin, sw.extent, sw.bc, sw.refined)
     Q = m.zeros()
-    m.init(Q, w.scenario, w.scen)
-    pr = orc.Params(**{f: getattr(w.params(), f) for f, _ in ccz4.Params._fields_})
+    m.init(Q, sw.scenario, sw.scen)
+    m.set_background(Q)
+    pr = orc.Params(**{f: getattr(sw.params(), f) for f, _ in ccz4.Params._fields_})
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    orc.set_threads(threads)
+    used = orc.max_threads()
+    cells = m.np * 729
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        Q = m.rk4_step(pr, Q, sw.dt())
+        steps += 1
+        if time.perf_counter() - t0 >= 0.5 * target_s:
+            break
+    t_all = time.perf_counter() - t0
+    all_rate = cells * 4 * steps / t_all
+    # one thread
+    orc.set_threads(1)
     t = time.perf_counter()
     m.fill_halos(Q)
     t_fill = time.perf_counter() - t
     rng = np.random.default_rng(0)
-    probe = sorted(rng.choice(m.np, 8, replace=False).tolist())
+    probe = sorted(rng.choice(m.np, 4, replace=False).tolist())
     k = np.zeros_like(Q)
     t = time.perf_counter()
     m.rhs(pr, Q, k, subset=probe)
     per_patch = (time.perf_counter() - t) / len(probe)
-    n = int(min(m.np, max(8, target_s / max(per_patch, 1e-9))))
+    n = int(min(m.np, max(4, 0.5 * target_s / max(per_patch, 1e-9))))
     sel = sorted(rng.choice(m.np, n, replace=False).tolist())
     t = time.perf_counter()
     m.rhs(pr, Q, k, subset=sel)
     t_rhs = time.perf_counter() - t
     acc, Qnext = np.zeros_like(Q), np.zeros_like(Q)
     t = time.perf_counter()
-    m.rk4_stage(0, w.dt(), Q, k, acc, Qnext)
+    m.rk4_stage(0, sw.dt(), Q, k, acc, Qnext)
     t_stage = time.perf_counter() - t
-    frac = n / m.np
-    t_total = t_rhs + (t_fill + t_stage) * frac
-    cells = n * 729
-    return dict(value=cells / t_total, unit="cell-updates/s", cores=1, kind="oracle",
-                sample=f"one RK4 stage (fill + RHS + stage combine) on {n} of {m.np} patches ({cells} cells) "
-                       f"of the same workload; fill and combine pro-rated; {t_total:.1f} s of CPU work")
+    t_one = t_rhs + (t_fill + t_stage) * n / m.np
+    orc.set_threads(threads)
+    return dict(value=all_rate, unit="cell-updates/s", cores=used, kind="oracle",
+                sample=f"{steps} RK4 steps (4 stages of fill + RHS + stage combine) of the {m.np}-patch sub-box "
+                       f"({cells} cells) {sw.name}, on {used} host threads: {t_all:.1f} s",
+                nproc=os.cpu_count(), cpu_model=_cpu_model(),
+                single_thread={"value": n * 729 / t_one, "unit": "cell-updates/s", "cores": 1,
+                               "sample": f"one stage on {n} of the {m.np} patches, fill and combine pro-rated: "
+                                         f"{t_one:.1f} s"})
 
 
 def main():
@@ -515,10 +686,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=4)
+    ap.add_argument("--drift-steps", type=int, default=50,
+                    help="steps since the initial data after which the constraint norms are compared")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision run")
     ap.add_argument("--no-so", action="store_true", help="skip the second-order-formulation run")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain unfused FP64 path")
     ap.add_argument("--no-lopsided", action="store_true", help="skip the lopsided-advection run")
     ap.add_argument("--stability", action="store_true",
                     help="instead of timing: evolve the workload in both formulations up to --t-end and "
@@ -534,7 +708,7 @@ def main():
     ap.add_argument("--train-iters", type=int, default=2000)
     ap.add_argument("--t-end", type=float, default=10.0)
     ap.add_argument("--sample-dt", type=float, default=0.5)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference kernel for the HBM byte counters)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
@@ -561,7 +735,7 @@ def main():
     if args.config == 5:
         r = run_dynamic(args, w)
         print(json.dumps({
-            "metric": "CCZ4 cell-updates/s per RK4 stage (FP64 vs mixed), % of FP64/HBM roofline",
+            "metric": METRIC,
             "value": r["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": 0,
             "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64", "data": "synthetic (analytic binary-puncture initial data)",
@@ -579,14 +753,20 @@ def main():
         torch.cuda.synchronize()
         del a, b
         torch.cuda.empty_cache()
-    r64 = run_gpu(args, w, 0)
+    horizon = max(args.drift_steps, 0)
+    _say(f"FP64 fused step on {w.name}")
+    r64 = run_gpu(args, w, 0, total_steps=horizon, keep=not args.no_mixed or not args.no_plain)
     stages = 4 * args.steps
     value = r64["cells"] * stages / r64["wall"]
     traffic = measured_traffic(args.config)
+    traffic_rhs = measured_traffic(args.config, "hbm_bytes_per_rhs_launch")
     ops_stage, ops_rhs = measured_fp64_ops(args.config)
     copy_gbs = copy_bandwidth()
+    alg = FUSED_BYTES_PER_CELL * r64["cells"]
+    ach = alg / (r64["stage_ms"] * 1e-3) / 1e9
+    l2h = r64["norms"][0]
     line = {
-        "metric": "CCZ4 cell-updates/s per RK4 stage (FP64 vs mixed), % of FP64/HBM roofline",
+        "metric": METRIC,
         "value": value,
         "unit": "cell-updates/s",
         "n_gpus": 1,
@@ -604,42 +784,85 @@ def main():
                            "copied; every halo copied at the last stage)",
                    "launch_config": r64["kernel"], "autotune_ms": r64["tune_ms"]},
         "eager_ms_per_step": r64["wall_eager"] * 1e3 / args.steps,
-        "roofline": {"bound": "hbm", "achieved": r64["stage_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r64["stage_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": r64["kernel"], "avg_ms": r64["stage_ms"],
-                     "copy_gbs": copy_gbs, "frac_of_copy": r64["stage_gbs"] / copy_gbs,
-                     "algorithmic_bytes_per_launch": r64["stage_bytes"],
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": r64["kernel"], "avg_ms": r64["stage_ms"], "avg_ms_by_stage": r64["stage_ms_by_s"],
+                     "bytes_per_cell_stage": FUSED_BYTES_PER_CELL, "algorithmic_bytes_per_launch": alg,
+                     "extra_bytes_per_launch": {"same_level_halo_copies": r64["halo_bytes"],
+                                                "sommerfeld_ghost_update": r64["ghost_bytes"],
+                                                "stage_dependent_stream": r64["stage_bytes"] - alg - r64["halo_bytes"] -
+                                                r64["ghost_bytes"]},
+                     "achieved_with_extra": r64["stage_gbs"],
+                     "copy_gbs": copy_gbs, "frac_of_copy": ach / copy_gbs,
                      "fp64": fp64_rate(ops_stage, r64["stage_ms"])},
-        "constraints_after": {"L2_H": r64["norms"][0], "L2_M": r64["norms"][1], "nonfinite": r64["norms"][2]},
+        "constraints": {"steps": r64["steps_total"], "t": r64["steps_total"] * r64["dt"], "r_excise": 1.0,
+                        "L2_H_t0": r64["norms0"][0], "L2_M_t0": r64["norms0"][1],
+                        "L2_H": l2h, "L2_M": r64["norms"][1], "nonfinite": r64["norms"][2]},
     }
     if r64["rhs_ms"]:
-        rb = RHS_BYTES_PER_CELL * r64["cells"] + RHS_GHOST_VECTORS * 8 * NV * 243 * r64["ghost_faces"]
+        rb = RHS_BYTES_PER_CELL_MODEL * r64["cells"]
         gbs = rb / (r64["rhs_ms"] * 1e-3) / 1e9
-        line["rhs_kernel"] = {"kernel": r64["rhs_kernel"], "avg_ms": r64["rhs_ms"],
+        line["rhs_kernel"] = {"kernel": r64["rhs_kernel"], "avg_ms": r64["rhs_ms"], "bytes_per_cell": RHS_BYTES_PER_CELL_MODEL,
                               "algorithmic_bytes_per_launch": rb, "achieved": gbs, "unit": "GB/s",
-                              "frac": gbs / HBM_PEAK_GBS, "frac_of_copy": gbs / copy_gbs,
+                              "frac": gbs / HBM_PEAK_GBS, "frac_of_copy": gbs / copy_gbs, "traffic": traffic_rhs,
                               "frac_ideal_bytes": RHS_IDEAL_BYTES_PER_CELL * r64["cells"] /
                               (r64["rhs_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                               "fp64": fp64_rate(ops_rhs, r64["rhs_ms"])}
+    Q64 = r64.pop("Q", None)
     if not args.no_mixed:
-        rm = run_gpu(args, w, 1)
+        _say("mixed-precision fused step")
+        rm = run_gpu(args, w, 1, total_steps=horizon, keep=True)
         vm = rm["cells"] * stages / rm["wall"]
-        line["mixed"] = {"value": vm, "stage_avg_ms": rm["stage_ms"], "speedup_vs_fp64": vm / value,
-                         "L2_H": rm["norms"][0], "L2_M": rm["norms"][1]}
+        Qm = rm.pop("Q")
+        per_slot, emax, kmax = state_error(Qm, Q64)
+        del Qm
+        torch.cuda.empty_cache()
+        line["mixed"] = {"value": vm, "ms_per_step": rm["wall"] * 1e3 / args.steps, "stage_avg_ms": rm["stage_ms"],
+                         "kernel": rm["kernel"], "speedup_vs_fp64": vm / value,
+                         "L2_H": rm["norms"][0], "L2_M": rm["norms"][1], "steps": rm["steps_total"],
+                         "dL2_H_rel": abs(rm["norms"][0] - l2h) / l2h if l2h else None,
+                         "equal_constraint_violation": abs(rm["norms"][0] - l2h) <= 0.01 * l2h,
+                         "state_error_vs_fp64": {"max": emax, "slot": kmax, "per_slot": per_slot,
+                                                 "measure": "max|Q_mixed - Q_fp64| / max|Q_fp64| per slot over "
+                                                            "interior cells (slots below 1e-10 of the largest: "
+                                                            "relative to the largest)"}}
+    if not args.no_plain:
+        _say("plain unfused FP64 path")
+        rp = run_plain(args, w, total_steps=horizon, keep=True)
+        vp = rp["cells"] * stages / rp["wall"]
+        Qp = rp.pop("Q")
+        per_slot, emax, kmax = state_error(Qp, Q64)
+        del Qp
+        torch.cuda.empty_cache()
+        lp = rp["norms"][0]
+        line["plain_fp64"] = {"value": vp, "ms_per_step": rp["wall"] * 1e3 / args.steps,
+                              "call_ms": rp["call_ms"], "L2_H": lp, "L2_M": rp["norms"][1], "steps": rp["steps_total"],
+                              "path": "per stage: ccz4_fill_halos, ccz4_rhs, ccz4_rk4_stage (eager launches)",
+                              "state_error_vs_fused": {"max": emax, "slot": kmax},
+                              "speedup_fused_fp64_over_plain": value / vp,
+                              "speedup_mixed_over_plain": line["mixed"]["value"] / vp if "mixed" in line else None,
+                              "dL2_H_rel_fused_fp64": abs(l2h - lp) / lp if lp else None,
+                              "dL2_H_rel_mixed": abs(line["mixed"]["L2_H"] - lp) / lp if lp and "mixed" in line
+                              else None}
+    del Q64
+    torch.cuda.empty_cache()
     if not args.no_so:
-        rs = run_gpu(args, w, 0, formulation=1)
+        _say("second-order formulation")
+        rs = run_gpu(args, w, 0, formulation=1, rhs=False)
         vs = rs["cells"] * stages / rs["wall"]
         line["second_order"] = {"value": vs, "ms_per_step": rs["wall"] * 1e3 / args.steps,
                                 "stage_avg_ms": rs["stage_ms"], "reconstruct_avg_ms": rs["reconstruct_ms"],
                                 "speedup_vs_first_order": vs / value,
                                 "L2_H": rs["norms"][0], "L2_M": rs["norms"][1]}
     if not args.no_lopsided:
-        rl = run_gpu(args, w, 0, advection=1)
+        _say("lopsided advection")
+        rl = run_gpu(args, w, 0, advection=1, rhs=False)
         vl = rl["cells"] * stages / rl["wall"]
         line["lopsided_advection"] = {"value": vl, "ms_per_step": rl["wall"] * 1e3 / args.steps,
                                       "stage_avg_ms": rl["stage_ms"], "speedup_vs_central": vl / value,
                                       "L2_H": rl["norms"][0], "L2_M": rl["norms"][1]}
     if not args.no_cpu:
+        _say("oracle on the host")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 

@@ -347,7 +347,13 @@ ccz4_status ccz4_mlp_workspace(int64_t n, int64_t *floats);
 
 /* Mean softmax cross-entropy of the logits of n rows against tags in {-1, 0, 1} (COARSEN,
    KEEP, REFINE) and its gradient with respect to every parameter (grad: CCZ4_MLP_NPARAM floats;
-   loss: one float, may be NULL).  work: at least ccz4_mlp_workspace(n) floats. */
+   loss: one float, may be NULL).  work: at least ccz4_mlp_workspace(n) floats.  With
+   work_floats >= ccz4_mlp_workspace(n) + CCZ4_MLP_TRACE * n the call also leaves, for row r at
+   work + ccz4_mlp_workspace(n) + CCZ4_MLP_TRACE * r, the operands of its matrix products as FP32
+   values (for checking the gradient layer by layer): the BF16 standardised input x[81], the
+   BF16 activations a1[64] and a2[64], and the FP32 pre-activation gradients d3[3] (softmax minus
+   one-hot, divided by n), d2[64] and d1[64] before their BF16 rounding. */
+enum { CCZ4_MLP_TRACE = 340 };
 ccz4_status ccz4_mlp_grad(const float *params, const float *norm, const float *feat, const int8_t *tags,
                           int64_t n, float *work, int64_t work_floats, float *grad, float *loss, void *stream);
 

@@ -104,6 +104,19 @@ def _c(a, dt=np.float64):
 
 
 _feat = _sig("orc_features", None, [ctypes.c_void_p, _dp, _dp])
+_set_threads = _sig("orc_set_threads", None, [ctypes.c_int])
+_max_threads = _sig("orc_max_threads", ctypes.c_int, [])
+
+
+def set_threads(n):
+    """Host threads of the oracle's patch loops (RHS and RK4 stage); the arithmetic of each
+    patch is the same for any number."""
+    _set_threads(int(n))
+
+
+def max_threads():
+    return int(_max_threads())
+
 _rg_plan = _sig("orc_regrid_plan", ctypes.c_int64, [ctypes.c_void_p, _i8p, ctypes.c_int, _ip, ctypes.c_int64])
 _rg_transfer = _sig("orc_regrid_transfer", None, [ctypes.c_void_p, _dp, ctypes.c_void_p, _dp])
 _bf16 = _sig("orc_bf16_round", ctypes.c_double, [ctypes.c_double])
@@ -147,6 +160,50 @@ def mlp_loss_grad(x, labels, prm, bf16=True):
     g = np.zeros(MLP_NPARAM)
     loss = _mlp_grad(x.shape[0], x, np.ascontiguousarray(labels, dtype=np.int32), _c(prm), int(bf16), g)
     return loss, g
+
+
+def _mlp_split(prm):
+    """(W1, b1, W2, b2, W3, b3) views of a parameter vector (row-major, out x in)."""
+    prm = np.asarray(prm, dtype=np.float64)
+    o = np.cumsum([0, MLP_NH * MLP_NIN, MLP_NH, MLP_NH * MLP_NH, MLP_NH, MLP_NOUT * MLP_NH, MLP_NOUT])
+    shp = [(MLP_NH, MLP_NIN), (MLP_NH,), (MLP_NH, MLP_NH), (MLP_NH,), (MLP_NOUT, MLP_NH), (MLP_NOUT,)]
+    return [prm[o[i]:o[i + 1]].reshape(shp[i]) for i in range(6)]
+
+
+def bf16_array(x):
+    """bf16_round of every element."""
+    return np.vectorize(bf16_round, otypes=[np.float64])(np.asarray(x, dtype=np.float64))
+
+
+def mlp_layers(prm, x, a1, a2, labels, d3, d2, d1, bf16=True):
+    """The perceptron layer by layer in FP64, each layer from the given operands of the layer
+    before it rather than from this function's own previous layer: x, a1, a2 (rows of layer
+    inputs, BF16 values) and d3, d2, d1 (pre-activation gradients, rounded here to BF16 where
+    they enter a matrix product, as the forward activations are).  Returns a dict with
+      z1, z2, z3: pre-activations x W1b^T + b1, a1 W2b^T + b2, a2 W3b^T + b3 (Wb = BF16 weights);
+      d3: (softmax(z3) - onehot(labels)) / n;
+      d2, d1: (bf16(d3) W3b) * [a2 > 0], (bf16(d2) W2b) * [a1 > 0];
+      gW3, gb3, gW2, gb2, gW1, gb1: bf16(d3)^T a2, sum d3, bf16(d2)^T a1, sum d2, bf16(d1)^T x,
+      sum d1 (the loss gradient of the mean cross-entropy).
+    bf16=False skips every BF16 rounding; chained on its own outputs this is then the gradient
+    of mlp_loss_grad."""
+    W1, b1, W2, b2, W3, b3 = _mlp_split(prm)
+    rnd = bf16_array if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    W1b, W2b, W3b = rnd(W1), rnd(W2), rnd(W3)
+    n = x.shape[0]
+    out = {"z1": x @ W1b.T + b1, "z2": a1 @ W2b.T + b2, "z3": a2 @ W3b.T + b3}
+    z3 = out["z3"]
+    e = np.exp(z3 - z3.max(axis=1, keepdims=True))
+    onehot = np.zeros_like(z3)
+    onehot[np.arange(n), np.asarray(labels)] = 1.0
+    out["d3"] = (e / e.sum(axis=1, keepdims=True) - onehot) / n
+    d3b, d2b, d1b = rnd(d3), rnd(d2), rnd(d1)
+    out["d2"] = (d3b @ W3b) * (a2 > 0)
+    out["d1"] = (d2b @ W2b) * (a1 > 0)
+    out["gW3"], out["gb3"] = d3b.T @ a2, d3.sum(axis=0)
+    out["gW2"], out["gb2"] = d2b.T @ a1, d2.sum(axis=0)
+    out["gW1"], out["gb1"] = d1b.T @ x, d1.sum(axis=0)
+    return out
 
 
 def adam_step(p, m, v, g, t, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -7,6 +7,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include "ccz4_oracle.h"
 
 #define NV ORC_NV
@@ -597,16 +600,17 @@ static void fill_face_restrict(const orc_mesh *m, double *Q, int64_t p, int a, i
             }
 }
 
+/* P-parallel, built once before any fill runs (orc_fill_halos) */
+static double Ppar[3 * PP][PP];
+static int Ppar_built = 0;
+
 /* fine leaf p face (a, side) whose neighbour region is covered by the coarse leaf cp */
 static void fill_face_prolong(const orc_mesh *m, double *Q, int64_t p, int a, int side,
                               int64_t cp, const int ni[3])
 {
-    static double Ppar[3 * PP][PP];
-    static int built = 0;
     const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;
     int L, t1, t2, l1, l2, m6, v, c[3];
     int o1, o2;
-    if (!built) { build_P_par(Ppar); built = 1; }
     /* position of this fine patch inside the coarse face: fine index minus 3 * coarse index */
     o1 = ni[b1] - 3 * m->id[4 * cp + 1 + b1];
     o2 = ni[b2] - 3 * m->id[4 * cp + 1 + b2];
@@ -714,11 +718,19 @@ static face_t classify(const orc_mesh *m, int64_t p, int a, int side)
     return f;
 }
 
+/* Every face task writes only its own leaf's halo and reads interiors (the prolongation also
+   reads coarse halos, which the first sweep completes), so each sweep may run over the leaves on
+   several host threads (OpenMP) with the same result. */
 void orc_fill_halos(const orc_mesh *m, double *Q)
 {
     int64_t p;
-    int a, side;
-    for (p = 0; p < m->np; p++)
+    if (!Ppar_built) {
+        build_P_par(Ppar);
+        Ppar_built = 1;
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (p = 0; p < m->np; p++) {
+        int a, side;
         for (a = 0; a < 3; a++)
             for (side = -1; side <= 1; side += 2) {
                 face_t f = classify(m, p, a, side);
@@ -726,12 +738,16 @@ void orc_fill_halos(const orc_mesh *m, double *Q)
                 else if (f.kind == 1) { if (m->bc == ORC_BC_NEUMANN) fill_face_neumann(Q, p, a, side); }
                 else if (f.kind == 2) fill_face_restrict(m, Q, p, a, side, f.ni);
             }
-    for (p = 0; p < m->np; p++)
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (p = 0; p < m->np; p++) {
+        int a, side;
         for (a = 0; a < 3; a++)
             for (side = -1; side <= 1; side += 2) {
                 face_t f = classify(m, p, a, side);
                 if (f.kind == 3) fill_face_prolong(m, Q, p, a, side, f.nb, f.ni);
             }
+    }
 }
 
 /* ----------------------------------------------------------------------------------------
@@ -779,10 +795,13 @@ static void sommerfeld_box(const orc_mesh *m, const orc_params *pr, int64_t p, c
         }
 }
 
+/* Patches are independent here, so the loop may run on several host threads (OpenMP, see
+   orc_set_threads): each patch's arithmetic is the same whichever thread takes it. */
 void orc_rhs_subset(const orc_mesh *m, const orc_params *pr, const double *Q, double *kout,
                     int64_t n_sel, const int64_t *sel)
 {
     int64_t s;
+#pragma omp parallel for schedule(dynamic, 1)
     for (s = 0; s < n_sel; s++) {
         int64_t p = sel[s];
         double org[3], dx[3];
@@ -796,8 +815,29 @@ void orc_rhs_subset(const orc_mesh *m, const orc_params *pr, const double *Q, do
 
 void orc_rhs(const orc_mesh *m, const orc_params *pr, const double *Q, double *kout)
 {
-    int64_t p;
-    for (p = 0; p < m->np; p++) orc_rhs_subset(m, pr, Q, kout, 1, &p);
+    int64_t p, *all = (int64_t *)malloc(sizeof(int64_t) * (m->np ? m->np : 1));
+    for (p = 0; p < m->np; p++) all[p] = p;
+    orc_rhs_subset(m, pr, Q, kout, m->np, all);
+    free(all);
+}
+
+/* Host threads of the patch loops (OpenMP; 1 without it). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* ----------------------------------------------------------------------------------------
@@ -1014,9 +1054,10 @@ int orc_rk4_stage(const orc_mesh *m, int s, double dt, const double *Qn, const d
     static const double bw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
     static const double aw[3] = {0.5, 0.5, 1.0};
     int64_t p;
-    int x, y, z, v;
     if (s < 0 || s > 3 || !(dt > 0)) return -1;
-    for (p = 0; p < m->np; p++)
+#pragma omp parallel for schedule(static)
+    for (p = 0; p < m->np; p++) {
+        int x, y, z, v;
         for (z = 0; z < NB; z++)
             for (y = 0; y < NB; y++)
                 for (x = 0; x < NB; x++) {
@@ -1038,6 +1079,7 @@ int orc_rk4_stage(const orc_mesh *m, int s, double dt, const double *Qn, const d
                     }
                     if (s == 3 && nin == 3) orc_project_point(Qnext + o);
                 }
+    }
     return 0;
 }
 

@@ -96,6 +96,9 @@ int orc_init(const orc_mesh *m, double *Q, int scenario, const double *sp);
 void orc_set_background(orc_mesh *m, const double *Q);
 void orc_fill_halos(const orc_mesh *m, double *Q);
 void orc_rhs(const orc_mesh *m, const orc_params *pr, const double *Q, double *kout);
+/* host threads of the patch loops of orc_rhs, orc_rhs_subset and orc_rk4_stage (OpenMP) */
+void orc_set_threads(int n);
+int orc_max_threads(void);
 /* Second-order formulation: the auxiliaries A_k = d_k alpha, B_k^i = d_k beta^i,
    D_kij = d_k gt_ij / 2, P_k = d_k phi on every leaf interior cell, from central FD4
    differences of the primaries (whose halos must be filled); halos are left as they are. */

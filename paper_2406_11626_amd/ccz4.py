@@ -23,6 +23,7 @@ KERNEL_PHASED, KERNEL_LDS, KERNEL_LINEAR_ORDER = 0, 1, 2
 FILL_SAME_LEVEL, FILL_NEUMANN, FILL_LEVELS, FILL_ALL = 1, 2, 4, 7
 STAGE_FILL_SAME_LEVEL, STAGE_GATHER_SAME_LEVEL, STAGE_FILL_SAME_LEVEL_X = 1, 2, 4
 MLP_NIN, MLP_NH, MLP_NOUT, MLP_NPARAM = 81, 64, 3, 9603
+MLP_TRACE = 340  # floats per row of the optional gradient trace
 SCEN_GAUGE_WAVE, SCEN_PUNCTURE, SCEN_BL_BY = 0, 1, 2
 
 

@@ -986,8 +986,10 @@ ccz4_status ccz4_mlp_grad(const float *params, const float *norm, const float *f
 {
     if (!params || !norm || !feat || !tags || !work || !grad) return fail(CCZ4_EINVAL, "NULL buffer");
     if (n <= 0) return fail(CCZ4_EINVAL, "n must be > 0");
-    if (work_floats < (int64_t)mlp_tiles(n) * (MLP_NPARAM + 1)) return fail(CCZ4_EINVAL, "workspace too small");
-    HIP_TRY(launch_mlp_grad(params, norm, feat, tags, n, work, grad, loss, S(stream)));
+    const int64_t base = (int64_t)mlp_tiles(n) * (MLP_NPARAM + 1);
+    if (work_floats < base) return fail(CCZ4_EINVAL, "workspace too small");
+    float *trace = work_floats >= base + (int64_t)MLP_TRACE * n ? work + base : nullptr;
+    HIP_TRY(launch_mlp_grad(params, norm, feat, tags, n, work, trace, grad, loss, S(stream)));
     return CCZ4_OK;
 }
 

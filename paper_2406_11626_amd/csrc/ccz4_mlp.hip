@@ -27,6 +27,8 @@ typedef short bf4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
 // FP32 -> BF16, round to nearest, ties to even (NaN -> quiet NaN)
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
 __device__ __forceinline__ uint16_t f2bf(float f)
 {
     uint32_t u = __float_as_uint(f);
@@ -145,9 +147,12 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float *__restrict__ p
 }
 
 // Loss and gradient partials of one tile: part[blk][0 .. NPARAM-1] gradient, [NPARAM] loss sum.
+// With trace != nullptr, each row also leaves the operands of its matrix products there (as FP32
+// values, MLP_TRACE per row): the BF16 standardised input, the BF16 activations a1 and a2, and the
+// FP32 pre-activation gradients d3, d2 and d1 before their BF16 rounding.
 __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ prm, const float *__restrict__ norm,
                                                   const float *__restrict__ feat, const int8_t *__restrict__ tags,
-                                                  int64_t n, float *__restrict__ part)
+                                                  int64_t n, float *__restrict__ part, float *__restrict__ trace)
 {
     __shared__ MlpShared S;
     __shared__ float d3[TILE][NOUTP];
@@ -156,6 +161,14 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ prm,
     const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lk = (l >> 4) * 4;
     float *out = part + (int64_t)blockIdx.x * (MLP_NPARAM + 1);
     mlp_forward_tile(S, prm, norm, feat, n, r0);
+    if (trace) {
+        for (int e = t; e < TILE * (NIN + 2 * NH); e += blockDim.x) {
+            const int r = e / (NIN + 2 * NH), i = e % (NIN + 2 * NH);
+            if (r0 + r >= n) continue;
+            const uint16_t b = i < NIN ? S.x[r][i] : (i < NIN + NH ? S.a1[r][i - NIN] : S.a2[r][i - NIN - NH]);
+            trace[(r0 + r) * MLP_TRACE + i] = bf2f(b);
+        }
+    }
     const float inv_n = 1.0f / (float)n;
     // softmax cross-entropy per row
     if (t < TILE) {
@@ -180,6 +193,9 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ prm,
             d3[t][j] = j < NOUT ? d[j] : 0.f;
             S.db[t][j] = j < NOUT ? f2bf(d[j]) : (uint16_t)0;
         }
+        if (trace && r0 + t < n)
+#pragma unroll
+            for (int j = 0; j < NOUT; ++j) trace[(r0 + t) * MLP_TRACE + NIN + 2 * NH + j] = d[j];
     }
     __syncthreads();
     if (t == 0) {
@@ -227,6 +243,11 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ prm,
         for (int r = 0; r < TILE; ++r) s += S.z2[r][t];
         dsum[t] = s;
     }
+    if (trace)
+        for (int e = t; e < TILE * NH; e += blockDim.x) {
+            const int r = e / NH, h = e % NH;
+            if (r0 + r < n) trace[(r0 + r) * MLP_TRACE + NIN + 2 * NH + NOUT + h] = S.z2[r][h];
+        }
     // gW2[o][i] = sum_rows d2b[row][o] a1[row][i]: 16 tiles, four per wave
     for (int q = 0; q < 4; ++q) {
         const int ob = w, ib = q;
@@ -262,6 +283,11 @@ __global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ prm,
         for (int r = 0; r < TILE; ++r) s += S.z1[r][t];
         out[OB1 + t] = s;
     }
+    if (trace)
+        for (int e = t; e < TILE * NH; e += blockDim.x) {
+            const int r = e / NH, h = e % NH;
+            if (r0 + r < n) trace[(r0 + r) * MLP_TRACE + NIN + 3 * NH + NOUT + h] = S.z1[r][h];
+        }
     // gW1[o][i] = sum_rows d1b[row][o] x[row][i]: 4 x 6 tiles, six per wave
     for (int q = 0; q < 6; ++q) {
         const int ob = w, ib = q;
@@ -412,10 +438,10 @@ hipError_t launch_mlp_forward(const float *prm, const float *norm, const float *
 }
 
 hipError_t launch_mlp_grad(const float *prm, const float *norm, const float *feat, const int8_t *tags, int64_t n,
-                           float *work, float *grad, float *loss, hipStream_t st)
+                           float *work, float *trace, float *grad, float *loss, hipStream_t st)
 {
     const int32_t nt = mlp_tiles(n);
-    hipLaunchKernelGGL(k_mlp_grad, dim3(nt), dim3(256), 0, st, prm, norm, feat, tags, n, work);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(nt), dim3(256), 0, st, prm, norm, feat, tags, n, work, trace);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_mlp_reduce, dim3((MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, st, work, nt, n, grad, loss);

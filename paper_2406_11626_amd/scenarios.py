@@ -111,3 +111,13 @@ def binary_tracking(radii=(2.0,)):
     ref = sphere_refinement(w.n0, w.origin, w.extent, [(3.0, 0.0, 0.0), (-3.0, 0.0, 0.0)], list(radii))
     return Workload(f"binary puncture on [-12,12]^3, static refinement r = {list(radii)} around the punctures",
                     w.n0, w.origin, w.extent, w.bc, BLACK_HOLE, w.scenario, w.scen, 20, refined=ref)
+
+
+def subbox(w, n=8):
+    """An n^3-patch box of workload w's level-0 spacing centred on the origin (same puncture, same
+    parameters and boundary condition): a bounded piece of a uniform workload of the same per-cell
+    arithmetic, for timing the host oracle."""
+    assert not w.refined
+    L = w.extent[0] / w.n0[0]  # edge of one patch
+    return Workload(f"{n}^3-patch sub-box of: {w.name}", (n, n, n), (-0.5 * n * L,) * 3, (n * L,) * 3, w.bc, w.prm,
+                    w.scenario, w.scen, w.steps, cfl=w.cfl)

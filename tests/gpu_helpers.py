@@ -33,21 +33,23 @@ def to_host(Qd, patches=None):
     return from_device_layout(t.cpu().numpy())
 
 
-FLOOR = 1e-3
+FLOOR = 1e-10
 
 
 def parity_error(gpu, ref, mask=INTERIOR, nslots=59):
     """Per-slot error of the parity bar over the masked cells:
-        e_c = max|gpu_c - ref_c| / max(max|ref_c|, FLOOR * max_c' max|ref_c'|).
-    Slots within three orders of magnitude of the largest one are measured relative to their
-    own size; smaller slots (cancellation residuals such as Theta of the gauge wave, whose
-    terms are 1e5 times larger than their sum) relative to FLOOR times the largest slot."""
+        e_c = max|gpu_c - ref_c| / max|ref_c|   where max|ref_c| > FLOOR * top,
+        e_c = max|gpu_c - ref_c| / top          otherwise,
+    with top = max_c' max|ref_c'|.  Slots within ten orders of magnitude of the largest one are
+    measured relative to their own size; the others (slots that vanish, or cancellation
+    residuals far below the rounding of the terms that form them) are held to an absolute bound
+    relative to the largest slot."""
     g = gpu[:, mask][..., :nslots]
     r = ref[:, mask][..., :nslots]
     diff = np.abs(g - r).reshape(-1, nslots).max(0)
     scale = np.abs(r).reshape(-1, nslots).max(0)
-    top = scale.max()
-    return diff / np.maximum(np.maximum(scale, FLOOR * top), 1e-300)
+    top = max(scale.max(), 1e-300)
+    return diff / np.where(scale > FLOOR * top, scale, top)
 
 
 def same_level_halo_mask(ctx, Q, axes=(0, 1, 2)):

@@ -91,8 +91,8 @@ def write_record(path, **rec):
 def test_profile_readers_guard_digest_and_workload(tmp_path, monkeypatch):
     digest = bench.kernel_source_digest()
     t, fl = tmp_path / "traffic.md", tmp_path / "ops.md"
-    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(t))
-    monkeypatch.setattr(bench, "FLOPS_FILE", str(fl))
+    monkeypatch.setattr(bench, "traffic_file", lambda config: str(t))
+    monkeypatch.setattr(bench, "flops_file", lambda config: str(fl))
     assert bench.measured_traffic(2) is None and bench.measured_fp64_ops(2) == (None, None)
     write_record(t, hbm_bytes_per_launch=2.5e10, source_sha256=digest, workload_config=2)
     write_record(fl, fp64_ops_per_stage_launch=2.75e10, fp64_ops_per_rhs_launch=2.6e10, source_sha256=digest,
@@ -109,8 +109,12 @@ def test_profile_readers_guard_digest_and_workload(tmp_path, monkeypatch):
 
 def test_committed_profiles_parse():
     """The committed summaries carry the fields the readers take (whatever their digest)."""
-    for path, keys in ((bench.TRAFFIC_FILE, ("hbm_bytes_per_launch",)),
-                       (bench.FLOPS_FILE, ("fp64_ops_per_stage_launch", "fp64_ops_per_rhs_launch"))):
+    import glob
+    files = [(p, ("hbm_bytes_per_launch",)) for p in glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.md"))]
+    files += [(p, ("fp64_ops_per_stage_launch", "fp64_ops_per_rhs_launch"))
+              for p in glob.glob(os.path.join(ROOT, "profiles", "*_fp64_ops.md"))]
+    assert files
+    for path, keys in files:
         rec = {}
         for ln in open(path):
             if ln.startswith("- ") and ":" in ln:

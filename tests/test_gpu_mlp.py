@@ -6,7 +6,8 @@ ulps.  The perceptron uses the same BF16 operands on both sides (the standardise
 formed in FP32 identically); what differs is the accumulation (FP32 on the matrix cores, FP64
 in the oracle), which occasionally flips the BF16 rounding of a hidden activation or of a
 back-propagated gradient by one BF16 ulp (2^-8 relative); the normwise bounds below allow for
-a few such flips per tensor.  Adam is FP32 against FP64 with the same FP32 hyper-parameters: a
+a few such flips per tensor.  The layer-wise test removes that cascade by handing the oracle the
+GPU's own operands of each layer (the gradient trace), and holds every gradient to 1e-4.  Adam is FP32 against FP64 with the same FP32 hyper-parameters: a
 few FP32 roundings of the terms of each update.  The tags are integers: bit-exact."""
 import numpy as np
 import pytest
@@ -96,6 +97,42 @@ def test_gradient_parity(n):
     # the workspace query and its check
     with pytest.raises(ccz4.CCZ4Error):
         ccz4.ccz4_mlp_grad(ind.params, ind.norm, dev(feat), dev(tags), n, ind._work[:10], ind.grad)
+
+
+@pytest.mark.parametrize("n", [64, 331])
+def test_gradient_layerwise_parity(n):
+    """Each layer of the GPU's forward and backward pass against the oracle's layer evaluated on
+    the GPU's own operands of that layer (the trace of ccz4_mlp_grad), so that a BF16 rounding
+    flip in one layer cannot propagate into the next: weight and bias gradients and the
+    back-propagated pre-activation gradients to 1e-4 normwise (FP32 against FP64 accumulation),
+    the BF16 activations to their own rounding."""
+    prm, feat, norm, tags = mlp_inputs(n, 50 + n)
+    base = ccz4.ccz4_mlp_workspace(n)
+    work = torch.zeros(base + ccz4.MLP_TRACE * n, dtype=torch.float32, device="cuda")
+    grad = torch.zeros(NP, dtype=torch.float32, device="cuda")
+    ccz4.ccz4_mlp_grad(dev(prm), dev(norm), dev(feat), dev(tags), n, work, grad)
+    g = grad.cpu().numpy().astype(np.float64)
+    tr = work[base:].cpu().numpy().astype(np.float64).reshape(n, ccz4.MLP_TRACE)
+    x, a1, a2 = tr[:, :81], tr[:, 81:145], tr[:, 145:209]
+    d3, d2, d1 = tr[:, 209:212], tr[:, 212:276], tr[:, 276:340]
+    # the BF16 input is the standardised feature rounded as the oracle rounds it
+    assert np.array_equal(x, orc.bf16_array(orc.mlp_standardize(feat, norm)))
+    r = orc.mlp_layers(prm.astype(np.float64), x, a1, a2, tags.astype(np.int64) + 1, d3, d2, d1)
+    for name, (a, b) in BLOCKS.items():
+        assert rel(g[a:b], r["g" + name].ravel()) <= 1e-4, (name, rel(g[a:b], r["g" + name].ravel()))
+    for name, got in (("d3", d3), ("d2", d2), ("d1", d1)):
+        assert rel(got, r[name]) <= 1e-4, (name, rel(got, r[name]))
+    # activations: the BF16 rounding (half a unit in the last place, 2^-8 relative at most) of
+    # ReLU of the pre-activation, up to the FP32 accumulation of the matrix cores
+    for got, z in ((a1, r["z1"]), (a2, r["z2"])):
+        ref = np.maximum(z, 0.0)
+        assert np.all(np.abs(got - ref) <= 2.0 ** -8 * ref + 1e-5 * np.abs(z).max())
+        flip = (got > 0) != (ref > 0)  # ReLU masks differ only where z is at rounding level
+        assert np.all(np.abs(z[flip]) <= 1e-5 * np.abs(z).max())
+    # the plain workspace gives the same gradient without the trace
+    g2 = torch.zeros(NP, dtype=torch.float32, device="cuda")
+    ccz4.ccz4_mlp_grad(dev(prm), dev(norm), dev(feat), dev(tags), n, work[:base], g2)
+    assert torch.equal(g2, grad)
 
 
 def test_adam_parity():

@@ -9,7 +9,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle as orc  # noqa: E402
-from gpu_helpers import INTERIOR, SLABS, parity_error, same_level_halo_mask, to_gpu, to_host  # noqa: E402
+from gpu_helpers import FLOOR, INTERIOR, SLABS, parity_error, same_level_halo_mask, to_gpu, to_host  # noqa: E402
 from paper_2406_11626_amd import ccz4, scenarios  # noqa: E402
 from seeded_inputs import box_centers, smooth_state  # noqa: E402
 
@@ -54,7 +54,8 @@ def acc_slot_error(a, b):
     y = b.detach().cpu().numpy().reshape(b.shape[0], 59, -1)
     diff = np.abs(x - y).max(axis=(0, 2))
     scale = np.abs(y).max(axis=(0, 2))
-    return diff / np.maximum(np.maximum(scale, 1e-3 * scale.max()), 1e-300)
+    top = max(scale.max(), 1e-300)
+    return diff / np.where(scale > FLOOR * top, scale, top)
 
 
 def valid_accumulator(ctx, Q, dt=0.01):
@@ -499,24 +500,53 @@ def test_fused_stage_rejects_aliasing():
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-def test_mixed_precision_stage_error_bound(kernel):
-    """FP32 nonlinear algebra with FP64 state: after two fused RK4 steps of the perturbed
-    puncture, the state differs from the FP64 path by a small relative amount per slot."""
+def test_fused_steps_static_amr_first_order_app_e_match_oracle(kernel):
+    """First-order formulation with the App. E coarse-fine operators on a static two-level mesh
+    with Sommerfeld faces: fused RK4 steps against the oracle's steps, interior and ghost slabs.
+    The refined cube [-9, 0]^3 has the puncture at its corner, so no cell centre falls on it."""
     w = scenarios.config(2)
-    ctx = ccz4.Context((2, 2, 2), w.origin, w.extent, w.bc, w.params())
-    for prec in (ccz4.PREC_FP64, ccz4.PREC_MIXED):
-        ctx.set_kernel(prec, kernel)
-    Q = ctx.new_state(0.0)
-    ctx.init_patches(Q, w.scenario, w.scen)
-    ctx.fill_halos(Q)
-    Qm = Q.clone()
-    b1 = (ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0))
-    b2 = (ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0))
+    e, eg, _, _ = _fused_vs_oracle(w, (2, 2, 2), refined=[(0, 0, 0, 0)], steps=2, perturb=True, kernel=kernel)
+    assert e.max() <= 1e-11, (e.argmax(), e.max())
+    assert eg.max() <= 1e-11, (eg.argmax(), eg.max())
+
+
+# Mixed precision (FP32 nonlinear algebra; FP64 state, stencil differences, metric inverse and
+# determinant, 1/phi factors and RK accumulation) against the FP64 oracle: after two RK4 steps
+# of the perturbed puncture, the per-slot error of the parity measure stays below MIXED_BOUND.
+# The bound is FP32 rounding (6e-8) of the algebra's terms, each of which can be larger than the
+# slot it feeds (the Ricci sum against alpha R / 2 of Theta), times the two steps' accumulation.
+MIXED_BOUND = 1e-6
+
+
+@pytest.mark.parametrize("refined", [(), ((0, 0, 0, 0),)], ids=["uniform", "two_levels"])
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_mixed_precision_steps_against_oracle(kernel, refined):
+    w = scenarios.config(2)
+    ctx, m = make_pair((2, 2, 2), w.origin, w.extent, w.bc, w.params(), list(refined))
+    ctx.set_kernel(ccz4.PREC_MIXED, kernel)
+    Qo = m.zeros()
+    m.init(Qo, w.scenario, w.scen)
+    for p in range(m.np):
+        Qo[p, 3:12, 3:12, 3:12] += 1e-3 * smooth_state(box_centers(m.geom[p, :3], m.geom[p, 3:]), 50)[3:12, 3:12, 3:12]
+    Qd = to_gpu(Qo)
+    ctx.set_background(to_gpu(Qo))
+    m.set_background(Qo)
+    ctx.fill_halos(Qd)
+    bufs = (ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0))
+    pr = oparams(w.params())
+    dt = w.dt()
     for _ in range(2):
-        ctx.rk4_step_fused(Q, w.dt(), b1, ccz4.PREC_FP64)
-        ctx.rk4_step_fused(Qm, w.dt(), b2, ccz4.PREC_MIXED)
-    e = parity_error(to_host(Qm), to_host(Q), INTERIOR)
-    assert e.max() <= 1e-6, (e.argmax(), e.max())
+        ctx.rk4_step_fused(Qd, dt, bufs, ccz4.PREC_MIXED)
+        Qo = m.rk4_step(pr, Qo, dt)
+    g = to_host(Qd)
+    e = parity_error(g, Qo, INTERIOR)
+    print(f"mixed vs oracle ({kernel}, {len(refined)} refined): max {e.max():.3e} at slot {e.argmax()}")
+    assert e.max() <= MIXED_BOUND, (e.argmax(), e.max())
+    bm = boundary_ghost_mask(m, (2, 2, 2))
+    eg = parity_error(np.where(bm[..., None], g, 0.0), np.where(bm[..., None], Qo, 0.0), SLABS)
+    assert eg.max() <= MIXED_BOUND, (eg.argmax(), eg.max())
+    # the mixed path differs from the FP64 one: the bound is not met trivially
+    assert e.max() > 1e-12
 
 
 def test_kernels_agree_on_a_static_amr_mesh():

@@ -164,3 +164,31 @@ def test_learned_tag_rule_cases():
     logits = np.tile([1.0, 1.0, 1.0], (n, 1))
     plain = np.zeros(n, np.int8)
     assert np.all(m.tag_learned(logits, plain, 0.3, 2)[l0] == 1)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_layerwise_form_chains_to_the_loss_gradient(bf16):
+    """The layer-by-layer form of the oracle, chained on its own outputs (activations ReLU of the
+    pre-activations, rounded to BF16 where the matrix cores take them), reproduces the whole
+    loss gradient of the oracle, which the finite-difference test above pins."""
+    rng = np.random.default_rng(7)
+    n = 37
+    prm = rand_params(8)
+    x = rng.normal(size=(n, 81))
+    if bf16:
+        x = orc.bf16_array(x)
+    labels = rng.integers(0, 3, n)
+    rnd = orc.bf16_array if bf16 else (lambda a: a)
+    z = np.zeros((n, 64))
+    d = np.zeros((n, 3))
+    a1 = rnd(np.maximum(orc.mlp_layers(prm, x, z, z, labels, d, z, z, bf16)["z1"], 0.0))
+    a2 = rnd(np.maximum(orc.mlp_layers(prm, x, a1, z, labels, d, z, z, bf16)["z2"], 0.0))
+    d3 = orc.mlp_layers(prm, x, a1, a2, labels, d, z, z, bf16)["d3"]
+    d2 = orc.mlp_layers(prm, x, a1, a2, labels, d3, z, z, bf16)["d2"]
+    d1 = orc.mlp_layers(prm, x, a1, a2, labels, d3, d2, z, bf16)["d1"]
+    r = orc.mlp_layers(prm, x, a1, a2, labels, d3, d2, d1, bf16)
+    g = np.concatenate([r["gW1"].ravel(), r["gb1"], r["gW2"].ravel(), r["gb2"], r["gW3"].ravel(), r["gb3"]])
+    _, go = orc.mlp_loss_grad(x, labels, prm, bf16=bf16)
+    np.testing.assert_allclose(g, go, rtol=1e-12, atol=1e-14 * np.abs(go).max())
+    # and the logits of the chained form are the oracle's forward pass
+    np.testing.assert_allclose(r["z3"], orc.mlp_forward(x, prm, bf16=bf16)[2], rtol=1e-12, atol=1e-14)
