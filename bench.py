@@ -214,7 +214,11 @@ def run_gpu(args, w, precision, formulation=0, advection=0, total_steps=0, keep=
         ctx.reconstruct(Q, True, stream)
         ctx.fill_halos(Q, stream)
     norms0, _ = ctx.constraints(Q, r_excise=1.0)
-    tune_ms = ctx.autotune(Q, precision, reps=2) if args.autotune else None
+    tune_ms = None
+    if args.autotune:
+        ms = ctx.autotune(Q, precision, reps=2)
+        tune_ms = {"chosen": ccz4.kernel_config_name(ctx.get_kernel(precision)),
+                   "ms": {ccz4.kernel_config_name(k): t for k, t in enumerate(ms)}}
     ctx.fill_halos(Q, stream)
 
     def step(timed):
@@ -307,7 +311,7 @@ def run_gpu(args, w, precision, formulation=0, advection=0, total_steps=0, keep=
     norms, st = ctx.constraints(Q, r_excise=1.0)
     kc = ctx.get_kernel(precision)
     targs = ("<double, " if precision == ccz4.PREC_FP64 else "<float, ") + ("1>" if advection else "0>")
-    border = " (plain block order)" if kc & ccz4.KERNEL_LINEAR_ORDER else ""
+    border = " (" + ccz4.kernel_config_name(kc).split("/", 1)[1] + ")"
     # the kernels one stage call (one right-hand-side call) launches
     kname = ("k_stage_lds" if kc & ccz4.KERNEL_LDS else "k_stage") + targs + border
     rname = ("k_rhs_lds" if kc & ccz4.KERNEL_LDS else "k_rhs") + targs + border + \
@@ -507,14 +511,10 @@ def run_tracker(args):
                 wall_s=wall, ms_per_step=wall * 1e3 / max(1, i), track=track)
 
 
-def run_learned_bbh(args):
-    """The learned refinement indicator trained on the solver's own binary-puncture runs in the
-    second-order formulation (stable, and the punctures orbit, so the refinement pattern moves).
-    Two training runs with Bowen-York momenta scaled to 0.9 and 1.1 of the standard 0.095 and one
-    held-out run at the standard momenta, each on the static r = 2 refinement around the punctures
-    to t_end.  Snapshots of the leaf features and the plain tags every sample_dt; the network learns
-    the plain tag of the next snapshot from the features of the current one, and is scored on the
-    held-out run by the REFINE miss rate against the next snapshot's plain tags."""
+def _bbh_training_runs(args, names):
+    """Second-order binary-puncture runs on the static r = 2 refinement (the tracker workload) to
+    t_end, with snapshots of the leaf features and the plain tags every sample_dt; the Bowen-York
+    momenta scaled per run.  Returns {name: (ctx, snapshots, norms)} and the thresholds."""
     import numpy as np
     import torch
     from paper_2406_11626_amd import ccz4, learned, scenarios
@@ -525,8 +525,7 @@ def run_learned_bbh(args):
     every = max(1, int(round(args.sample_dt / dt)))
     theta = None
     runs = {}
-    t0 = time.perf_counter()
-    for name, scale in (("train_0.9", 0.9), ("train_1.1", 1.1), ("heldout_1.0", 1.0)):
+    for name, scale in names:
         scen = list(w.scen)
         scen[5] *= scale   # y momentum of the puncture at +x
         scen[12] *= scale  # and of the one at -x
@@ -544,12 +543,18 @@ def run_learned_bbh(args):
             theta = (float(np.percentile(e, 99.0)), float(np.percentile(e, 30.0)))
         snaps = learned.snapshots(ctx, Q, dt, steps, every, theta[0], theta[1], 2)
         norms, _ = ctx.constraints(Q)
+        del Q
         runs[name] = (ctx, snaps, norms)
-        print(f"# {name}: {len(snaps)} snapshots, REFINE per snapshot "
-              f"{[int((t == 1).sum()) for _, t in snaps]}, non-finite {norms[2]:.0f}", file=sys.stderr, flush=True)
-    sim_s = time.perf_counter() - t0
+        _say(f"{name}: {len(snaps)} snapshots, REFINE per snapshot {[int((t == 1).sum()) for _, t in snaps]}, "
+             f"non-finite {norms[2]:.0f}")
+    return runs, theta, w, dt, every
+
+
+def _train_on(runs, names, args):
+    import torch
+    from paper_2406_11626_amd import learned
     feats, targets = [], []
-    for name in ("train_0.9", "train_1.1"):
+    for name in names:
         snaps = runs[name][1]
         for k in range(len(snaps) - 1):
             feats.append(snaps[k][0])
@@ -562,52 +567,107 @@ def run_learned_bbh(args):
     loss0 = ind.train(feat, target, 0)
     loss = ind.train(feat, target, args.train_iters)
     torch.cuda.synchronize()
-    train_s = time.perf_counter() - t1
+    return ind, dict(training_rows=int(feat.shape[0]), train_iters=args.train_iters, loss_before=loss0,
+                     loss_after=loss, train_s=time.perf_counter() - t1)
+
+
+def train_bbh_indicator(args):
+    """The indicator trained on two second-order binary-puncture runs (momenta x0.9 and x1.1),
+    features of snapshot k against the plain tags of snapshot k + 1."""
+    names = (("train_0.9", 0.9), ("train_1.1", 1.1))
+    t0 = time.perf_counter()
+    runs, theta, w, dt, every = _bbh_training_runs(args, names)
+    sim_s = time.perf_counter() - t0
+    ind, info = _train_on(runs, [n for n, _ in names], args)
+    for ctx, _, _ in runs.values():
+        ctx.close()
+    return ind, dict(info, workload=w.name + ", second-order formulation", t_end=args.t_end,
+                     sample_dt=every * dt, simulation_s=sim_s)
+
+
+def run_learned_bbh(args):
+    """The learned refinement indicator trained on the solver's own binary-puncture runs in the
+    second-order formulation (stable, and the punctures orbit, so the refinement pattern moves).
+    Two training runs with Bowen-York momenta scaled to 0.9 and 1.1 of the standard 0.095 and one
+    held-out run at the standard momenta, each on the static r = 2 refinement around the punctures
+    to t_end.  Snapshots of the leaf features and the plain tags every sample_dt; the network learns
+    the plain tag of the next snapshot from the features of the current one, and is scored on the
+    held-out run by the REFINE miss rate against the next snapshot's plain tags."""
+    from paper_2406_11626_amd import learned
+    names = (("train_0.9", 0.9), ("train_1.1", 1.1), ("heldout_1.0", 1.0))
+    t0 = time.perf_counter()
+    runs, theta, w, dt, every = _bbh_training_runs(args, names)
+    sim_s = time.perf_counter() - t0
+    ind, info = _train_on(runs, ("train_0.9", "train_1.1"), args)
     ctx_h, snaps_h, norms_h = runs["heldout_1.0"]
     score = learned.anticipation(ind, ctx_h, snaps_h, conf=0.6, max_level=2)
     return dict(workload=w.name + ", second-order formulation", leaves=ctx_h.n_patches, dt=dt, t_end=args.t_end,
-                sample_dt=every * dt, theta_refine_coarsen=theta, training_rows=int(feat.shape[0]),
-                train_iters=args.train_iters, loss_before=loss0, loss_after=loss, train_s=train_s,
-                simulation_s=sim_s, heldout_nonfinite=norms_h[2],
+                sample_dt=every * dt, theta_refine_coarsen=theta, simulation_s=sim_s, **info,
+                heldout_nonfinite=norms_h[2],
                 heldout_refine_per_snapshot=[int((t == 1).sum()) for _, t in snaps_h],
                 heldout_score={k: {"miss_rate": v[0], "extra_refine": v[1]} for k, v in score.items()})
 
 
 def run_dynamic(args, w):
-    """Binary puncture with dynamic AMR: a regrid by the plain criterion every 10 steps.  The
+    """Binary puncture with dynamic AMR: a regrid every 10 steps, first by the plain criterion
+    alone, then with the learned indicator trained as in run_learned_bbh (the plain criterion's
+    REFINE tags kept, the network adding confident REFINE tags and vetoing COARSEN).  The
     thresholds are fixed once from the indicator at t = 0 (its 99.5th and 30th percentiles over
-    the leaves, which keeps the mesh near its initial 20k leaves).  Returns the stepping throughput (graph-launched fused steps, regrids excluded), the
-    regrid records and the cost of the learned indicator's inference on the final mesh."""
+    the leaves, which keeps the mesh near its initial 20k leaves).  Per regrid: the REFINE tags of
+    the plain criterion and of the combination, and the network's own miss rate against the
+    plain criterion (the share of plain-REFINE leaves its arg-max does not tag REFINE).  Returns
+    the stepping throughput of both runs (graph-launched fused steps, regrids excluded)."""
     import numpy as np
     import torch
-    from paper_2406_11626_amd import ccz4, dynamic
-    from paper_2406_11626_amd.learned import LearnedIndicator
-    ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, w.params(), w.refined)
-    Q = ctx.new_state(0.0)
-    ctx.init_patches(Q, w.scenario, w.scen)
-    ctx.fill_halos(Q)
+    from paper_2406_11626_amd import ccz4, dynamic, learned
+
+    def start():
+        ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, w.params(), w.refined)
+        Q = ctx.new_state(0.0)
+        ctx.init_patches(Q, w.scenario, w.scen)
+        ctx.fill_halos(Q)
+        return ctx, Q
+
+    ctx, Q = start()
     ind = torch.empty((ctx.n_patches, 3), dtype=torch.float64, device="cuda")
     tags = torch.empty(ctx.n_patches, dtype=torch.int8, device="cuda")
     ctx.tag_refine(Q, 1e300, -1.0, 3, tags, ind)
     e = ind.max(dim=1).values.cpu().numpy()
     theta_r, theta_c = float(np.percentile(e, 99.5)), float(np.percentile(e, 30))
     leaves0 = dynamic.levels(ctx)
+    _say("config 5, plain criterion")
     ctx, Q, log = dynamic.evolve(ctx, Q, w, args.steps, 10, theta_r, theta_c, 3)
-    # learned indicator inference on the final mesh (features from the constraint fields)
-    net = LearnedIndicator(seed=0)
-    HM = torch.empty((ctx.n_patches, 4, 729), dtype=torch.float64, device="cuda")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.constraints(Q, HM)
-    feat = ctx.features(Q, HM)
-    logits = net.forward(feat)
-    torch.cuda.synchronize()
-    t_learned = time.perf_counter() - t0
+    plain = dict(value=log["cell_stages"] / log["step_seconds"], ms_per_step=log["step_seconds"] * 1e3 / args.steps,
+                 leaves_final=dynamic.levels(ctx), regrids=log["regrids"])
     norms, _ = ctx.constraints(Q, r_excise=0.5)
-    return dict(value=log["cell_stages"] / log["step_seconds"], steps=args.steps,
-                ms_per_step=log["step_seconds"] * 1e3 / args.steps, leaves_initial=leaves0,
-                leaves_final=dynamic.levels(ctx), regrids=log["regrids"], theta=(theta_r, theta_c),
-                learned_inference_ms=t_learned * 1e3, norms=norms, logits_shape=list(logits.shape))
+    plain["constraints_after"] = {"L2_H": norms[0], "L2_M": norms[1], "nonfinite": norms[2]}
+    del Q
+    ctx.close()
+    torch.cuda.empty_cache()
+    _say("training the learned indicator on second-order binary-puncture runs")
+    net, train = train_bbh_indicator(args)
+    torch.cuda.empty_cache()
+    ctx, Q = start()
+
+    def judge(rec, ctx_, Q_, plain_tags, feat):
+        logits = net.forward(feat)
+        own = (torch.argmax(logits, dim=1) - 1).to(torch.int8)
+        miss, extra = learned.miss_rate(own, plain_tags)
+        rec["network_miss_rate_vs_plain"] = miss
+        rec["network_extra_refine"] = extra
+
+    _say("config 5, plain criterion with the learned indicator")
+    ctx, Q, logl = dynamic.evolve(ctx, Q, w, args.steps, 10, theta_r, theta_c, 3, indicator=net, conf=0.6,
+                                  on_tags=judge)
+    norms, _ = ctx.constraints(Q, r_excise=0.5)
+    lrn = dict(value=logl["cell_stages"] / logl["step_seconds"], ms_per_step=logl["step_seconds"] * 1e3 / args.steps,
+               leaves_final=dynamic.levels(ctx), regrids=logl["regrids"],
+               constraints_after={"L2_H": norms[0], "L2_M": norms[1], "nonfinite": norms[2]})
+    del Q
+    ctx.close()
+    torch.cuda.empty_cache()
+    return dict(value=plain["value"], steps=args.steps, ms_per_step=plain["ms_per_step"], leaves_initial=leaves0,
+                theta=(theta_r, theta_c), plain=plain, learned=lrn, training=train)
 
 
 def _cpu_model():
@@ -739,11 +799,10 @@ def main():
             "value": r["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": 0,
             "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64", "data": "synthetic (analytic binary-puncture initial data)",
-            "config": {"workload": w.name, "leaves_initial_per_level": r["leaves_initial"],
-                       "leaves_final_per_level": r["leaves_final"], "regrid_every": 10,
+            "config": {"workload": w.name, "leaves_initial_per_level": r["leaves_initial"], "regrid_every": 10,
                        "theta_refine_coarsen": r["theta"], "precision": "fp64"},
-            "regrids": r["regrids"], "learned_indicator_inference_ms": r["learned_inference_ms"],
-            "constraints_after": {"L2_H": r["norms"][0], "L2_M": r["norms"][1], "nonfinite": r["norms"][2]},
+            "plain_criterion": r["plain"], "learned_indicator": r["learned"], "training": r["training"],
+            "learned_over_plain_throughput": r["learned"]["value"] / r["plain"]["value"],
         }), flush=True)
         return
     if args.copy_calibration:
@@ -782,7 +841,7 @@ def main():
                    "stages_per_step": 4, "dt": w.dt(), "precision": "fp64",
                    "step": "HIP graph of 4 fused stages (y/z halos read from the neighbours, x-face halos "
                            "copied; every halo copied at the last stage)",
-                   "launch_config": r64["kernel"], "autotune_ms": r64["tune_ms"]},
+                   "launch_config": r64["kernel"], "autotune": r64["tune_ms"]},
         "eager_ms_per_step": r64["wall_eager"] * 1e3 / args.steps,
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": traffic,

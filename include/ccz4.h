@@ -246,23 +246,38 @@ ccz4_status ccz4_tag_tracers(ccz4_ctx *ctx, int64_t n, const double *pos, int32_
 
 /* Launch configuration of ccz4_rhs and ccz4_rhs_rk4_stage, per precision (CCZ4_PREC_FP64 or
    CCZ4_PREC_MIXED): CCZ4_KERNEL_PHASED or CCZ4_KERNEL_LDS, optionally with
-   CCZ4_KERNEL_LINEAR_ORDER added.  Both kernels evaluate the same right-hand side (App. B algebra,
-   App. D FD4 and KO stencils) and agree up to floating-point rounding order; they differ only in
-   how the stencil footprints reach the registers.  CCZ4_KERNEL_PHASED reads every stencil point
-   from the state in six phases; CCZ4_KERNEL_LDS copies each slot's slab footprint once into LDS
-   per evaluation, in four rounds.  The work-groups of a patch run on one XCD unless
-   CCZ4_KERNEL_LINEAR_ORDER is given (plain block order).  Default after ccz4_create:
-   CCZ4_KERNEL_LDS for both precisions.  EINVAL on an unknown precision or value, or a NULL out
-   pointer. */
-typedef enum { CCZ4_KERNEL_PHASED = 0, CCZ4_KERNEL_LDS = 1, CCZ4_KERNEL_LINEAR_ORDER = 2 } ccz4_kernel;
+   CCZ4_KERNEL_LINEAR_ORDER added, plus one CCZ4_KERNEL_ORDER_* value.  Both kernels evaluate the
+   same right-hand side (App. B algebra, App. D FD4 and KO stencils) and agree up to
+   floating-point rounding order; they differ only in how the stencil footprints reach the
+   registers.  CCZ4_KERNEL_PHASED reads every stencil point from the state in six phases;
+   CCZ4_KERNEL_LDS copies each slot's slab footprint once into LDS per evaluation, in four rounds.
+   The work-groups of consecutive logical patches run on one XCD unless CCZ4_KERNEL_LINEAR_ORDER
+   is given (plain block order).  The leaf order sets which leaf each logical patch is, level by
+   level: canonical (i fastest), z-pencils (k fastest, then j, then i), bricks of 4^3 cubes, or
+   Morton (bits of i, j, k interleaved); neighbours across y and z faces, whose halos a stage
+   reads, are then processed closer in time.  No configuration changes the arithmetic of a cell.
+   Default after ccz4_create: CCZ4_KERNEL_LDS (canonical order) for both precisions.  EINVAL on an
+   unknown precision or value (0..15), or a NULL out pointer. */
+typedef enum {
+    CCZ4_KERNEL_PHASED = 0,
+    CCZ4_KERNEL_LDS = 1,
+    CCZ4_KERNEL_LINEAR_ORDER = 2,
+    CCZ4_KERNEL_ORDER_CANONICAL = 0,
+    CCZ4_KERNEL_ORDER_Z_PENCILS = 4,
+    CCZ4_KERNEL_ORDER_BRICKS = 8,
+    CCZ4_KERNEL_ORDER_MORTON = 12,
+    CCZ4_KERNEL_CONFIGS = 16
+} ccz4_kernel;
 ccz4_status ccz4_set_kernel(ccz4_ctx *ctx, int32_t precision, int32_t kernel);
 ccz4_status ccz4_get_kernel(const ccz4_ctx *ctx, int32_t precision, int32_t *kernel);
 
 /* Autotuner: times one fused stage (s = 1, with the flags ccz4_step_stage_flags gives that
-   configuration) of every launch configuration (0..3 above) on this context's mesh, `reps` launches each after one warm-up,
-   with events on `stream`, and selects the fastest for `precision`.  Q: a state with filled
-   halos (read only); acc and Qx: state-sized scratch (overwritten).  ms (host, may be NULL)
-   receives the four average launch times in milliseconds.  Synchronises `stream`. */
+   configuration) of every launch configuration (0..CCZ4_KERNEL_CONFIGS-1 above: kernel, block
+   order and leaf order) on this context's mesh, `reps` launches each after one warm-up, with
+   events on `stream`, and selects the fastest for `precision`.  Q: a state with filled halos
+   (read only); acc and Qx: state-sized scratch (overwritten).  ms (host, may be NULL) receives the
+   CCZ4_KERNEL_CONFIGS average launch times in milliseconds, indexed by configuration.
+   Synchronises `stream`. */
 ccz4_status ccz4_autotune(ccz4_ctx *ctx, const double *Q, double *acc, double *Qx, int32_t precision,
                           int32_t reps, double *ms, void *stream);
 

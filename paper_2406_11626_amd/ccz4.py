@@ -20,6 +20,15 @@ FORMULATION_FO, FORMULATION_SO = 0, 1
 ADVECTION_CENTRAL, ADVECTION_LOPSIDED_UPWIND, ADVECTION_LOPSIDED_PRINTED = 0, 1, 2
 TRANSFER_APP_E, TRANSFER_HIGHER_ORDER = 0, 1
 KERNEL_PHASED, KERNEL_LDS, KERNEL_LINEAR_ORDER = 0, 1, 2
+KERNEL_ORDER_CANONICAL, KERNEL_ORDER_Z_PENCILS, KERNEL_ORDER_BRICKS, KERNEL_ORDER_MORTON = 0, 4, 8, 12
+KERNEL_CONFIGS = 16  # launch configurations: kernel | block order | leaf order
+
+
+def kernel_config_name(k):
+    """Readable name of launch configuration k."""
+    order = ("canonical", "z-pencils", "bricks", "morton")[(k >> 2) & 3]
+    return (("lds" if k & KERNEL_LDS else "phased") + ("/linear" if k & KERNEL_LINEAR_ORDER else "/xcd") +
+            "/" + order)
 FILL_SAME_LEVEL, FILL_NEUMANN, FILL_LEVELS, FILL_ALL = 1, 2, 4, 7
 STAGE_FILL_SAME_LEVEL, STAGE_GATHER_SAME_LEVEL, STAGE_FILL_SAME_LEVEL_X = 1, 2, 4
 MLP_NIN, MLP_NH, MLP_NOUT, MLP_NPARAM = 81, 64, 3, 9603
@@ -264,7 +273,7 @@ def ccz4_step_stage_flags(h, precision, s):
 
 
 def ccz4_autotune(h, Q, acc, Qx, precision=PREC_FP64, reps=3, stream=None):
-    ms = (ctypes.c_double * 4)()
+    ms = (ctypes.c_double * KERNEL_CONFIGS)()
     _check(lib().ccz4_autotune(h, _ptr(Q), _ptr(acc), _ptr(Qx), int(precision), int(reps), ms, _stream(stream)))
     return list(ms)
 

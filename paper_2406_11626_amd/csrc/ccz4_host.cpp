@@ -94,6 +94,7 @@ struct ccz4_ctx {
     DevBuf<PatchGeom> d_geom;
     DevBuf<FaceTask> d_phc, d_phn, d_phr, d_php;
     DevBuf<int32_t> d_nbr;
+    DevBuf<int32_t> d_order;                  // KV_ORDERS leaf permutations, npatch each
     DevBuf<BoundaryFace> d_bf;
     DevBuf<int32_t> d_pface;
     DevBuf<uint8_t> d_bmask;
@@ -325,6 +326,42 @@ extern "C" {
 
 const char *ccz4_last_error(void) { return g_err.c_str(); }
 
+// The orders in which a right-hand-side or stage launch may walk the leaves (levels in turn, each
+// level by its cube index (i, j, k)): 0 canonical (i fastest), 1 z-pencils (k fastest, then j, then
+// i), 2 bricks of 4^3 cubes (canonical inside a brick and between bricks), 3 Morton (bits of i, j,
+// k interleaved, i lowest).  The launch's logical patch q takes leaf order[q]; the leaves a stage
+// reads besides its own (the y and z face neighbours) are then processed closer in time.
+static std::vector<int32_t> leaf_orders(const std::vector<std::array<int, 4>> &leaf)
+{
+    const size_t n = leaf.size();
+    std::vector<int32_t> out(KV_ORDERS * n);
+    auto morton = [](uint32_t i, uint32_t j, uint32_t k) {
+        uint64_t m = 0;
+        for (int b = 0; b < 20; ++b)
+            m |= (uint64_t)((i >> b) & 1) << (3 * b) | (uint64_t)((j >> b) & 1) << (3 * b + 1) |
+                 (uint64_t)((k >> b) & 1) << (3 * b + 2);
+        return m;
+    };
+    for (int o = 0; o < KV_ORDERS; ++o) {
+        std::vector<std::pair<std::array<uint64_t, 3>, int32_t>> key(n);
+        for (size_t p = 0; p < n; ++p) {
+            const uint64_t l = (uint64_t)leaf[p][0], i = (uint64_t)leaf[p][1], j = (uint64_t)leaf[p][2],
+                           k = (uint64_t)leaf[p][3];
+            std::array<uint64_t, 3> kk{l, 0, 0};
+            if (o == 0) kk[1] = (k << 40) | (j << 20) | i;
+            else if (o == 1) kk[1] = (i << 40) | (j << 20) | k;
+            else if (o == 2) {
+                kk[1] = ((k >> 2) << 40) | ((j >> 2) << 20) | (i >> 2);
+                kk[2] = ((k & 3) << 4) | ((j & 3) << 2) | (i & 3);
+            } else kk[1] = morton((uint32_t)i, (uint32_t)j, (uint32_t)k);
+            key[p] = {kk, (int32_t)p};
+        }
+        std::sort(key.begin(), key.end());
+        for (size_t q = 0; q < n; ++q) out[o * n + q] = key[q].second;
+    }
+    return out;
+}
+
 ccz4_status ccz4_create(ccz4_ctx **out, const ccz4_grid_desc *g, const ccz4_params *prm)
 {
     if (!out) return fail(CCZ4_EINVAL, "out is NULL");
@@ -367,6 +404,7 @@ ccz4_status ccz4_create(ccz4_ctx **out, const ccz4_grid_desc *g, const ccz4_para
     if (e == hipSuccess) e = c->d_phr.upload(c->ph_res);
     if (e == hipSuccess) e = c->d_php.upload(c->ph_pro);
     if (e == hipSuccess) e = c->d_nbr.upload(c->nbr);
+    if (e == hipSuccess) e = c->d_order.upload(leaf_orders(c->leaf));
     if (e == hipSuccess) e = c->d_pre.alloc(c->leaf.size());
     if (e == hipSuccess) e = c->d_bf.upload(c->bface);
     c->pface.assign(c->leaf.size() * 6, -1);
@@ -401,6 +439,7 @@ void ccz4_destroy(ccz4_ctx *c)
     c->d_phr.release();
     c->d_php.release();
     c->d_nbr.release();
+    c->d_order.release();
     c->d_pre.release();
     c->d_bf.release();
     c->d_pface.release();
@@ -507,6 +546,12 @@ ccz4_status ccz4_plan_counts(const ccz4_ctx *c, int64_t *counts)
     return CCZ4_OK;
 }
 
+// The leaf permutation of launch configuration v.
+static const int32_t *order_of(const ccz4_ctx *c, int32_t v)
+{
+    return c->d_order.p + (size_t)((v >> KV_ORDER_SHIFT) & (KV_ORDERS - 1)) * c->leaf.size();
+}
+
 ccz4_status ccz4_rhs(ccz4_ctx *c, const double *Q, double *k, int32_t precision, void *stream)
 {
     if (!c) return fail(CCZ4_EINVAL, "ctx is NULL");
@@ -518,7 +563,8 @@ ccz4_status ccz4_rhs(ccz4_ctx *c, const double *Q, double *k, int32_t precision,
     if (!c->bface.empty() && !c->bg_valid)
         return fail(CCZ4_ESTATE, "Sommerfeld background not set (call ccz4_init_patches or ccz4_set_background)");
     HIP_TRY(launch_rhs(Q, k, c->d_geom.p, (int32_t)c->leaf.size(), c->prm, precision, c->kernel[precision],
-                       c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(), c->d_pface.p, S(stream)));
+                       order_of(c, c->kernel[precision]), c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(),
+                       c->d_pface.p, S(stream)));
     return CCZ4_OK;
 }
 
@@ -566,8 +612,9 @@ static hipError_t launch_stage_flags(const ccz4_ctx *c, int32_t s, double dt, co
     const bool push = flags & (CCZ4_STAGE_FILL_SAME_LEVEL | CCZ4_STAGE_FILL_SAME_LEVEL_X);
     const int32_t axes = (flags & CCZ4_STAGE_FILL_SAME_LEVEL) ? 7 : 1;
     return launch_stage(s, dt, Qs, Qn, acc, Qx, c->d_geom.p, (int32_t)c->leaf.size(), c->prm, precision, variant,
-                        c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(), c->d_pface.p, push ? c->d_nbr.p : nullptr,
-                        axes, (flags & CCZ4_STAGE_GATHER_SAME_LEVEL) ? c->d_nbr.p : nullptr, st);
+                        order_of(c, variant), c->d_bf.p, c->d_bg.p, (int32_t)c->bface.size(), c->d_pface.p,
+                        push ? c->d_nbr.p : nullptr, axes,
+                        (flags & CCZ4_STAGE_GATHER_SAME_LEVEL) ? c->d_nbr.p : nullptr, st);
 }
 
 ccz4_status ccz4_step_stage_flags(ccz4_ctx *c, int32_t precision, int32_t s, int32_t *flags)

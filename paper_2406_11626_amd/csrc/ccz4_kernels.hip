@@ -5,6 +5,8 @@
 // the contiguous x rows of a box.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ccz4_algebra.hpp"
 #include "ccz4_kernels.hpp"
 #include "ccz4_rhs_lds.hpp"
@@ -342,11 +344,11 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t b, int64_t nblk)
 template <typename T, int LOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WPE))) void k_rhs(const double *__restrict__ Q, double *__restrict__ K,
                                              const PatchGeom *__restrict__ geom, int32_t npatch,
-                                             RhsParams prm, int32_t linear)
+                                             RhsParams prm, int32_t linear, const int32_t *__restrict__ order)
 {
     const int64_t lb = linear ? (int64_t)blockIdx.x : xcd_logical_block(blockIdx.x, gridDim.x);
-    const int p = (int)(lb / 3);
-    if (p >= npatch || threadIdx.x >= 243) return;
+    if (lb / 3 >= npatch || threadIdx.x >= 243) return;
+    const int p = order[lb / 3];
     const int c = (int)(lb % 3) * 243 + threadIdx.x;
     const PatchGeom g = geom[p];
     CellRef cr;
@@ -593,15 +595,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CCZ4_RHS_WP
     const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
     const PatchGeom *__restrict__ geom, int32_t npatch, int32_t nb_slab, RhsParams prm, int32_t s, double dt,
     const BoundaryFace *__restrict__ bf, const double *__restrict__ bg, const int32_t *__restrict__ nbr,
-    int32_t paxes, int32_t linear)
+    int32_t paxes, int32_t linear, const int32_t *__restrict__ order)
 {
     if ((int32_t)blockIdx.x >= nb_slab) {
         stage_ghost_face((int)blockIdx.x - nb_slab, threadIdx.x, s, dt, Qs, Qn, acc, Qx, geom, bf, bg, prm.shift == 0);
         return;
     }
     const int64_t lb = linear ? (int64_t)blockIdx.x : xcd_logical_block(blockIdx.x, nb_slab);
-    const int p = (int)(lb / 3);
-    if (p >= npatch || threadIdx.x >= 243) return;
+    if (lb / 3 >= npatch || threadIdx.x >= 243) return;
+    const int p = order[lb / 3];
     const int c = (int)(lb % 3) * 243 + threadIdx.x;
     const PatchGeom g = geom[p];
     CellRef cr;
@@ -636,13 +638,7 @@ __device__ __forceinline__ void lds_cell_setup(double *lds, int sl, const PatchG
     const int cc = act ? tid : 242;
     const int x = cc % 9 + 3, y = (cc / 9) % 9 + 3, zl = cc / 81;
     C.s = lds;
-    C.c = zl * ZS + y * YS + x;
-#pragma unroll
-    for (int k = -3; k <= 3; ++k) {
-        const int z2 = zl + k;
-        C.zo[k + 3] = (z2 >= 0 && z2 <= 2) ? z2 * ZS + y * YS + x
-                                            : LDS_OWN + (z2 < 0 ? z2 + 3 : z2) * 90 + (y - 3) * LDS_HROW + (x - 2);
-    }
+    lds_cell_offsets(C, x, y, zl);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         C.i12[a] = 1.0 / (12.0 * g.dx[a]);
@@ -655,12 +651,12 @@ template <typename T, int LOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rhs_lds(
     const double *__restrict__ Q, double *__restrict__ K, const PatchGeom *__restrict__ geom, int32_t npatch,
     RhsParams prm, const BoundaryFace *__restrict__ bf, const double *__restrict__ bg,
-    const int32_t *__restrict__ pface, int32_t linear)
+    const int32_t *__restrict__ pface, int32_t linear, const int32_t *__restrict__ order)
 {
     __shared__ double lds[LDS_DOUBLES];
     const int64_t lb = linear ? (int64_t)blockIdx.x : xcd_logical_block(blockIdx.x, gridDim.x);
-    const int p = (int)(lb / 3);
-    if (p >= npatch) return;  // uniform over the work-group
+    if (lb / 3 >= npatch) return;  // uniform over the work-group
+    const int p = order[lb / 3];
     const int sl = (int)(lb % 3);
     const PatchGeom g = geom[p];
     LdsCell C;
@@ -736,12 +732,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const double *__restrict__ Qs, const double *__restrict__ Qn, double *__restrict__ acc, double *__restrict__ Qx,
     const PatchGeom *__restrict__ geom, int32_t npatch, int32_t nb_slab, RhsParams prm, int32_t s, double dt,
     const BoundaryFace *__restrict__ bf, const double *__restrict__ bg, const int32_t *__restrict__ pface,
-    const int32_t *__restrict__ nbr, int32_t paxes, const int32_t *__restrict__ gnbr, int32_t linear)
+    const int32_t *__restrict__ nbr, int32_t paxes, const int32_t *__restrict__ gnbr, int32_t linear,
+    const int32_t *__restrict__ order)
 {
     __shared__ double lds[LDS_DOUBLES];
     const int64_t lb = linear ? (int64_t)blockIdx.x : xcd_logical_block(blockIdx.x, nb_slab);
-    const int p = (int)(lb / 3);
-    if (p >= npatch) return;  // uniform over the work-group
+    if (lb / 3 >= npatch) return;  // uniform over the work-group
+    const int p = order[lb / 3];
     const int sl = (int)(lb % 3);
     const PatchGeom g = geom[p];
     LdsCell C;
@@ -904,63 +901,102 @@ __global__ __launch_bounds__(256) void k_rk4_ghost(int32_t s, double dt, const d
 // ------------------------------------------------------------------ constraints
 // H = R + 2/3 K^2 - At_ij At^ij with R = phi^2 gt^ij R_ij;
 // M_i = gt^kl (d_k At_li - Gt^m_li At_km - Gt^m_lk At_im - 3 At_ik P_l/phi) - 2/3 d_i K.
-__global__ __launch_bounds__(128) void k_constraints(const double *__restrict__ Q, double *__restrict__ HM,
-                                                     const PatchGeom *__restrict__ geom, int64_t ncell,
-                                                     double r_excise, double *__restrict__ part)
+// Only the first derivatives of D (Ricci tensor from the relations), P (Ricci tensor), At and K
+// (momentum constraint) enter: 28 slots.  One work-group per z-slab of a leaf stages them into LDS
+// in two rounds of 14 (the stage kernel's slab staging, own halos), forms each cell's FD4
+// differences from LDS, and takes the pointwise values of the staged slots from LDS too; the
+// other slots are read from the state.  Per-block partial sums (H^2, |M|^2, counted cells,
+// non-finite cells) in a fixed order for k_reduce_parts.
+constexpr int CONS_NB = 14;
+__global__ __launch_bounds__(256) void k_constraints_lds(const double *__restrict__ Q, double *__restrict__ HM,
+                                                         const PatchGeom *__restrict__ geom, int32_t npatch,
+                                                         double r_excise, double *__restrict__ part)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double lds[CONS_NB * LDS_SLOT];
+    __shared__ double red[4][256];
+    const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int p = (int)(lb / 3);
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     double h2 = 0.0, m2 = 0.0, cnt = 0.0, bad = 0.0;
-    if (t < ncell) {
-        const int p = (int)(t / NCELL);
-        const int c = (int)(t % NCELL);
-        const int x = c % 9 + 3, y = (c / 9) % 9 + 3, z = c / 81 + 3;
-        const int o = boff(x, y, z);
-        const double *Qp = Q + (int64_t)p * PS + o;
+    if (p < npatch) {  // uniform over the work-group
+        const int sl = (int)(lb % 3);
         const PatchGeom g = geom[p];
-        const int st[3] = {1, YS, ZS};
-        double q[NV];
-        bool fin = true;
-        for (int v = 0; v < NV; ++v) {
-            q[v] = Qp[v * CS];
-            fin = fin && isfinite(q[v]);
-        }
-        double dq[3][NDIFF];
+        const bool act = tid < 243;
+        const int cc = act ? tid : 242;
+        const int x = cc % 9 + 3, y = (cc / 9) % 9 + 3, zl = cc / 81;
+        LdsCell C;
+        C.s = lds;
+        lds_cell_offsets(C, x, y, zl);
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double i12 = 1.0 / (12.0 * g.dx[a]);
-            const int s = st[a];
-            for (int v = DOFF; v < DOFF + NDIFF; ++v) {
-                const double *f = Qp + v * CS;
-                dq[a][v - DOFF] = (8.0 * (f[s] - f[-s]) - (f[2 * s] - f[-2 * s])) * i12;
-            }
+            C.i12[a] = 1.0 / (12.0 * g.dx[a]);
+            C.koc[a] = 0.0;
         }
-        double hm[4];
-        constraints_algebra(q, dq, hm);
-        for (int j = 0; j < 4; ++j) fin = fin && isfinite(hm[j]);
-        if (HM)
-            for (int j = 0; j < 4; ++j) HM[((int64_t)p * 4 + j) * NCELL + c] = hm[j];
-        const double X = g.org[0] + (x - 2.5) * g.dx[0], Y = g.org[1] + (y - 2.5) * g.dx[1],
-                     Z = g.org[2] + (z - 2.5) * g.dx[2];
-        const double r = sqrt(X * X + Y * Y + Z * Z);
-        if (!fin) bad = 1.0;
-        else if (r >= r_excise) {
-            h2 = hm[0] * hm[0];
-            m2 = hm[1] * hm[1] + hm[2] * hm[2] + hm[3] * hm[3];
-            cnt = 1.0;
+        const HaloSrc hs{{0, 0, 0, 0}};
+        const double *qb = Q + (int64_t)p * PS;
+        const int z = zl + 3 + 3 * sl;
+        const int o = boff(x, y, z);
+        double q[NV], dq[3][NDIFF];
+        const int ra[CONS_NB] = {SD, SD + 1, SD + 2, SD + 3, SD + 4, SD + 5, SD + 6, SD + 7,
+                                 SD + 8, SD + 9, SD + 10, SD + 11, SD + 12, SD + 13};
+        lds_round(qb, lds, sl, ra, w, lane, hs);
+        if (act)
+#pragma unroll
+            for (int j = 0; j < CONS_NB; ++j) {
+                q[ra[j]] = lv(C, j, 0, 0);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) dq[a][ra[j] - DOFF] = fd(C, j, a);
+            }
+        const int rb[CONS_NB] = {SD + 14, SD + 15, SD + 16, SD + 17, SP, SP + 1, SP + 2,
+                                 SAT, SAT + 1, SAT + 2, SAT + 3, SAT + 4, SAT + 5, SK};
+        lds_round(qb, lds, sl, rb, w, lane, hs);
+        if (act) {
+#pragma unroll
+            for (int j = 0; j < CONS_NB; ++j) {
+                q[rb[j]] = lv(C, j, 0, 0);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) dq[a][rb[j] - DOFF] = fd(C, j, a);
+            }
+            // the remaining slots pointwise (every slot takes part in the finiteness count)
+#pragma unroll
+            for (int v = 0; v < SAT; ++v) q[v] = qb[v * CS + o];
+#pragma unroll
+            for (int v = STHETA; v < SD; ++v) q[v] = qb[v * CS + o];
+            q[SK0] = qb[SK0 * CS + o];
+            bool fin = true;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) fin = fin && isfinite(q[v]);
+            double hm[4];
+            constraints_algebra(q, dq, hm);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) fin = fin && isfinite(hm[j]);
+            const int c = sl * NFACE + tid;
+            if (HM)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) HM[((int64_t)p * 4 + j) * NCELL + c] = hm[j];
+            const double X = g.org[0] + (x - 2.5) * g.dx[0], Y = g.org[1] + (y - 2.5) * g.dx[1],
+                         Z = g.org[2] + (z - 2.5) * g.dx[2];
+            const double r = sqrt(X * X + Y * Y + Z * Z);
+            if (!fin) bad = 1.0;
+            else if (r >= r_excise) {
+                h2 = hm[0] * hm[0];
+                m2 = hm[1] * hm[1] + hm[2] * hm[2] + hm[3] * hm[3];
+                cnt = 1.0;
+            }
         }
     }
     // block reduction (deterministic order)
-    __shared__ double red[4][128];
-    red[0][threadIdx.x] = h2;
-    red[1][threadIdx.x] = m2;
-    red[2][threadIdx.x] = cnt;
-    red[3][threadIdx.x] = bad;
+    red[0][tid] = h2;
+    red[1][tid] = m2;
+    red[2][tid] = cnt;
+    red[3][tid] = bad;
     __syncthreads();
-    for (int w = 64; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int j = 0; j < 4; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s)
+            for (int j = 0; j < 4; ++j) red[j][tid] += red[j][tid + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0)
+    if (tid == 0)
         for (int j = 0; j < 4; ++j) part[(int64_t)blockIdx.x * 4 + j] = red[j][0];
 }
 
@@ -1160,13 +1196,7 @@ __global__ __launch_bounds__(256) void k_reconstruct_lds(double *__restrict__ Q,
     const int x = cc % 9 + 3, y = (cc / 9) % 9 + 3, zl = cc / 81;
     LdsCell C;
     C.s = lds;
-    C.c = zl * ZS + y * YS + x;
-#pragma unroll
-    for (int k = -3; k <= 3; ++k) {
-        const int z2 = zl + k;
-        C.zo[k + 3] = (z2 >= 0 && z2 <= 2) ? z2 * ZS + y * YS + x
-                                            : LDS_OWN + (z2 < 0 ? z2 + 3 : z2) * 90 + (y - 3) * LDS_HROW + (x - 2);
-    }
+    lds_cell_offsets(C, x, y, zl);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         C.i12[a] = 1.0 / (12.0 * g.dx[a]);
@@ -1337,8 +1367,8 @@ hipError_t launch_fill(double *Q, const FaceTask *tasks, int32_t ntask, int32_t 
 }
 
 hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t npatch, const RhsParams &p,
-                      int32_t precision, int32_t variant, const BoundaryFace *bf, const double *bg, int32_t nbf,
-                      const int32_t *pface, hipStream_t st)
+                      int32_t precision, int32_t variant, const int32_t *order, const BoundaryFace *bf,
+                      const double *bg, int32_t nbf, const int32_t *pface, hipStream_t st)
 {
     // the LDS kernel computes the Sommerfeld ghosts' right-hand side inside the slab work-groups;
     // the phased kernel leaves it to k_rhs_sommerfeld
@@ -1350,30 +1380,30 @@ hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t
         if (p.advection) {
             if (precision == 1)
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<float, 1>), g, b, 0, st, Q, K, geom, npatch, p, bf, bg,
-                                   slab_ghosts, lin);
+                                   slab_ghosts, lin, order);
             else
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<double, 1>), g, b, 0, st, Q, K, geom, npatch, p, bf, bg,
-                                   slab_ghosts, lin);
+                                   slab_ghosts, lin, order);
         } else {
             if (precision == 1)
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<float, 0>), g, b, 0, st, Q, K, geom, npatch, p, bf, bg,
-                                   slab_ghosts, lin);
+                                   slab_ghosts, lin, order);
             else
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs_lds<double, 0>), g, b, 0, st, Q, K, geom, npatch, p, bf, bg,
-                                   slab_ghosts, lin);
+                                   slab_ghosts, lin, order);
         }
     } else {
         const dim3 g((unsigned)nb), b(256);
         if (p.advection) {
             if (precision == 1)
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs<float, 1>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs<float, 1>), g, b, 0, st, Q, K, geom, npatch, p, lin, order);
             else
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs<double, 1>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs<double, 1>), g, b, 0, st, Q, K, geom, npatch, p, lin, order);
         } else {
             if (precision == 1)
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs<float, 0>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs<float, 0>), g, b, 0, st, Q, K, geom, npatch, p, lin, order);
             else
-                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs<double, 0>), g, b, 0, st, Q, K, geom, npatch, p, lin);
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rhs<double, 0>), g, b, 0, st, Q, K, geom, npatch, p, lin, order);
         }
         if (nbf > 0) {
             const hipError_t e = hipGetLastError();
@@ -1389,8 +1419,9 @@ hipError_t launch_rhs(const double *Q, double *K, const PatchGeom *geom, int32_t
 // LDS kernel each slab work-group updates the ghost cells beside its own planes.
 hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn, double *acc, double *Qx,
                         const PatchGeom *geom, int32_t npatch, const RhsParams &p, int32_t precision,
-                        int32_t variant, const BoundaryFace *bf, const double *bg, int32_t nbf, const int32_t *pface,
-                        const int32_t *nbr, int32_t paxes, const int32_t *gnbr, hipStream_t st)
+                        int32_t variant, const int32_t *order, const BoundaryFace *bf, const double *bg, int32_t nbf,
+                        const int32_t *pface, const int32_t *nbr, int32_t paxes, const int32_t *gnbr,
+                        hipStream_t st)
 {
     // the LDS kernel updates the Sommerfeld ghosts inside the slab work-groups (per-leaf face table)
     const int32_t *slab_ghosts = nbf > 0 ? pface : nullptr;
@@ -1403,34 +1434,34 @@ hipError_t launch_stage(int32_t s, double dt, const double *Qs, const double *Qn
         if (p.advection) {
             if (precision == 1)
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<float, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, bf, bg, slab_ghosts, nbr, paxes, gnbr, lin);
+                                   ns, p, s, dt, bf, bg, slab_ghosts, nbr, paxes, gnbr, lin, order);
             else
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<double, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, bf, bg, slab_ghosts, nbr, paxes, gnbr, lin);
+                                   ns, p, s, dt, bf, bg, slab_ghosts, nbr, paxes, gnbr, lin, order);
         } else {
             if (precision == 1)
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<float, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, bf, bg, slab_ghosts, nbr, paxes, gnbr, lin);
+                                   ns, p, s, dt, bf, bg, slab_ghosts, nbr, paxes, gnbr, lin, order);
             else
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage_lds<double, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch,
-                                   ns, p, s, dt, bf, bg, slab_ghosts, nbr, paxes, gnbr, lin);
+                                   ns, p, s, dt, bf, bg, slab_ghosts, nbr, paxes, gnbr, lin, order);
         }
     } else {
         const dim3 g((unsigned)nb), b(256);
         if (p.advection) {
             if (precision == 1)
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage<float, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
-                                   p, s, dt, bf, bg, nbr, paxes, lin);
+                                   p, s, dt, bf, bg, nbr, paxes, lin, order);
             else
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage<double, 1>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
-                                   p, s, dt, bf, bg, nbr, paxes, lin);
+                                   p, s, dt, bf, bg, nbr, paxes, lin, order);
         } else {
             if (precision == 1)
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage<float, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
-                                   p, s, dt, bf, bg, nbr, paxes, lin);
+                                   p, s, dt, bf, bg, nbr, paxes, lin, order);
             else
                 hipLaunchKernelGGL(HIP_KERNEL_NAME(k_stage<double, 0>), g, b, 0, st, Qs, Qn, acc, Qx, geom, npatch, ns,
-                                   p, s, dt, bf, bg, nbr, paxes, lin);
+                                   p, s, dt, bf, bg, nbr, paxes, lin, order);
         }
     }
     return hipGetLastError();
@@ -1467,14 +1498,14 @@ hipError_t launch_rk4(int32_t s, double dt, const double *Qn, const double *K, d
     return hipGetLastError();
 }
 
-int64_t constraints_blocks(int32_t npatch) { return ((int64_t)npatch * NCELL + 127) / 128; }
+// one work-group per z-slab, a multiple of 8 for the XCD block order (at least 8)
+int64_t constraints_blocks(int32_t npatch) { return std::max<int64_t>(8, ((int64_t)npatch * 3 + 7) / 8 * 8); }
 
 hipError_t launch_constraints(const double *Q, double *HM, const PatchGeom *geom, int32_t npatch,
                               double r_excise, double *part, double *out3, hipStream_t st)
 {
-    const int64_t n = (int64_t)npatch * NCELL;
     const int64_t nb = constraints_blocks(npatch);
-    hipLaunchKernelGGL(k_constraints, dim3((unsigned)nb), dim3(128), 0, st, Q, HM, geom, n, r_excise, part);
+    hipLaunchKernelGGL(k_constraints_lds, dim3((unsigned)nb), dim3(256), 0, st, Q, HM, geom, npatch, r_excise, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, st, part, nb, out3);

@@ -27,14 +27,30 @@
 
 namespace ccz4 {
 
-constexpr int LDS_OWN = 3 * ZS;                   // 720 doubles: the slab's planes, 15 x 16 each
+// Row pitch of the staged own planes in LDS (doubles): the box row (16), or 18, whose odd pair
+// count spreads the rows of a wave's reads over the LDS banks (the extra pair is a repeat copy).
+#ifndef CCZ4_LDS_ROW
+#define CCZ4_LDS_ROW 16
+#endif
+constexpr int LROW = CCZ4_LDS_ROW;
+static_assert(LROW == 16 || LROW == 18, "LDS row pitch: 16 or 18 doubles");
+constexpr int LPAIRS = LROW / 2;                  // 16-byte copies per staged row
+constexpr int LPLANE = NBX * LROW;                // one staged plane, 15 rows
+constexpr int LDS_OWN = 3 * LPLANE;               // the slab's planes
+constexpr int LDS_OWN_PAIRS = 3 * NBX * LPAIRS;   // 360 or 405 copies
+constexpr int LDS_OWN_CHUNKS = (LDS_OWN_PAIRS + 63) / 64;
 constexpr int LDS_HROW = 10;                      // halo row: x = 2..11 (16-byte aligned pairs)
 constexpr int LDS_HALO = 6 * 9 * LDS_HROW;        // 540 doubles
-constexpr int LDS_SLOT = LDS_OWN + LDS_HALO;      // 1260 doubles = 10080 bytes
+constexpr int LDS_SLOT = LDS_OWN + LDS_HALO;      // 1260 (1350) doubles
 constexpr int LDS_NBUF = 15;
 constexpr int LDS_DOUBLES = LDS_NBUF * LDS_SLOT;  // 151200 bytes
 
 typedef __attribute__((address_space(3))) void lds_void_t;
+
+// cache-policy bits of the staging copies (0: the default policy)
+#ifndef CCZ4_STAGE_CPOL
+#define CCZ4_STAGE_CPOL 0
+#endif
 
 // Where the y and z face halos of a patch are read from: d[2 (a - 1) + (side > 0)] (a = 1, 2) is
 // added to the element index of a halo cell of the face of axis a on that side.  0 reads the
@@ -48,7 +64,8 @@ struct HaloSrc {
 };
 
 // Issue the direct global->LDS copies of slot v of slab sl into buffer b (does not wait).
-// Own planes: 360 pairs in six 64-lane chunks, the rows y <= 2 and y >= 12 from the y faces'
+// Own planes: 45 rows of LPAIRS pairs in 64-lane chunks (with an 18-double pitch the ninth pair of
+// a row repeats its eighth), the rows y <= 2 and y >= 12 from the y faces'
 // sources; halo rows: 270 pairs in five chunks, pair e being plane e / 45 (0..2 below, 3..5
 // above), row (e / 5) % 9, columns 2 + 2 (e % 5), planes outside the patch from the z faces'
 // sources.
@@ -59,12 +76,13 @@ __device__ __forceinline__ void lds_stage_slot(const double *__restrict__ qp, do
     double *dst = lds + b * LDS_SLOT;
     const double *own = box + (3 + 3 * sl) * ZS;
     const int w0 = (w + b) & 3;
-    for (int ch = w0; ch < 6; ch += 4)
-        if (ch * 64 + lane < 360) {
-            const int e = 2 * (ch * 64 + lane), r = e >> 4, y = r % 15;
+    for (int ch = w0; ch < LDS_OWN_CHUNKS; ch += 4)
+        if (ch * 64 + lane < LDS_OWN_PAIRS) {
+            const int q = ch * 64 + lane, r = q / LPAIRS, j = q % LPAIRS, y = r % 15;
+            const int e = r * XS + 2 * (j < 8 ? j : 7);
             // selects, not an index into hs.d: a lane-dependent index would put the array in memory
             const int64_t d = y <= 2 ? hs.d[0] : (y >= 12 ? hs.d[1] : 0);
-            __builtin_amdgcn_global_load_lds((const void *)(own + e + d), (lds_void_t *)(dst + ch * 128), 16, 0, 0);
+            __builtin_amdgcn_global_load_lds((const void *)(own + e + d), (lds_void_t *)(dst + ch * 128), 16, 0, CCZ4_STAGE_CPOL);
         }
     const int w1 = (w + b + 2) & 3;
     for (int ch = w1; ch < 5; ch += 4) {
@@ -74,7 +92,7 @@ __device__ __forceinline__ void lds_stage_slot(const double *__restrict__ qp, do
             const int z = hp < 3 ? 3 * sl + hp : 3 * sl + 3 + hp;
             const int64_t zd = z <= 2 ? hs.d[2] : (z >= 12 ? hs.d[3] : 0);
             __builtin_amdgcn_global_load_lds((const void *)(box + (z * ZS + (row + 3) * YS + 2 + 2 * pr) + zd),
-                                             (lds_void_t *)(dst + LDS_OWN + ch * 128), 16, 0, 0);
+                                             (lds_void_t *)(dst + LDS_OWN + ch * 128), 16, 0, CCZ4_STAGE_CPOL);
         }
     }
 }
@@ -119,7 +137,20 @@ struct LdsCell {
 __device__ __forceinline__ double lv(const LdsCell &c, int b, int a, int k)
 {
     const double *f = c.s + b * LDS_SLOT;
-    return a == 0 ? f[c.c + k] : (a == 1 ? f[c.c + k * YS] : f[c.zo[k + 3]]);
+    return a == 0 ? f[c.c + k] : (a == 1 ? f[c.c + k * LROW] : f[c.zo[k + 3]]);
+}
+
+// The LDS offsets of cell (x, y) (box indices) in plane zl (0..2) of the staged slab: its own
+// index and those of its seven z-neighbours (own planes, or the halo rows below and above).
+__device__ __forceinline__ void lds_cell_offsets(LdsCell &C, int x, int y, int zl)
+{
+    C.c = zl * LPLANE + y * LROW + x;
+#pragma unroll
+    for (int k = -3; k <= 3; ++k) {
+        const int z2 = zl + k;
+        C.zo[k + 3] = (z2 >= 0 && z2 <= 2) ? z2 * LPLANE + y * LROW + x
+                                            : LDS_OWN + (z2 < 0 ? z2 + 3 : z2) * 90 + (y - 3) * LDS_HROW + (x - 2);
+    }
 }
 
 __device__ __forceinline__ double fd(const LdsCell &c, int b, int a)
@@ -217,19 +248,63 @@ __device__ __forceinline__ int fresh(int o)
     return o;
 }
 
-// The pointwise metric of the cell at offset o: g, its inverse and its determinant.
-template <typename T>
-__device__ __forceinline__ void load_metric(const double *__restrict__ qp, int o, double gd[6], double igd[6],
-                                            double &detg, T g[6], T ig[6])
+// The pointwise metric of the cell, its slots read by ld(v): g, its inverse and its determinant.
+template <typename T, typename Ld>
+__device__ __forceinline__ void load_metric_with(Ld ld, double gd[6], double igd[6], double &detg, T g[6], T ig[6])
 {
 #pragma unroll
-    for (int s = 0; s < 6; ++s) gd[s] = qp[(SG + s) * CS + o];
+    for (int s = 0; s < 6; ++s) gd[s] = ld(SG + s);
     metric_inverse(gd, igd, detg);
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
         g[s] = cvt<T>(gd[s]);
         ig[s] = cvt<T>(igd[s]);
     }
+}
+
+// ... of the cell at offset o of the patch box
+template <typename T>
+__device__ __forceinline__ void load_metric(const double *__restrict__ qp, int o, double gd[6], double igd[6],
+                                            double &detg, T g[6], T ig[6])
+{
+    load_metric_with<T>([&](int v) -> double { return qp[v * CS + o]; }, gd, igd, detg, g, ig);
+}
+
+// The LDS buffer that holds slot v during round r of rhs_slab_lds, or -1 (see the round lists).
+__device__ __forceinline__ constexpr int round_buffer(int r, int v)
+{
+    if (r == 1) return (v >= SAT && v < SAT + 6) ? v - SAT : ((v >= SB && v < SB + 9) ? 6 + v - SB : -1);
+    if (r == 3)
+        return (v >= SD + 15 && v < SD + 18) ? v - SD - 15
+               : (v >= SP && v < SP + 3)     ? 3 + v - SP
+               : (v >= SA && v < SA + 3)     ? 6 + v - SA
+               : (v >= SGHAT && v < SGHAT + 3) ? 9 + v - SGHAT
+               : v == SK                     ? 12
+               : v == STHETA                 ? 13
+                                             : -1;
+    if (r == 4)
+        return (v >= SBB && v < SBB + 3)     ? v - SBB
+               : (v >= SG && v < SG + 6)     ? 3 + v - SG
+               : v == SALPHA                 ? 9
+               : (v >= SBETA && v < SBETA + 3) ? 10 + v - SBETA
+               : v == SPHI                   ? 13
+                                             : -1;
+    return -1;
+}
+
+// Pointwise value of slot v at the lane's cell during round R: from the staged copy in LDS when
+// the round stages v (the same double), else from the patch box at offset o.
+#ifndef CCZ4_PW_LDS
+#define CCZ4_PW_LDS 0
+#endif
+template <int R>
+__device__ __forceinline__ double pw(const double *__restrict__ qp, int o, const LdsCell &C, int v)
+{
+    if (CCZ4_PW_LDS) {
+        const int b = round_buffer(R, v);
+        if (b >= 0) return C.s[b * LDS_SLOT + C.c];
+    }
+    return qp[v * CS + o];
 }
 
 // The three FD4 derivatives and the Kreiss-Oliger sum of staged buffer b at the lane's cell,
@@ -390,7 +465,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
         {  // At: advection + KO, d_k tr(At), and the rest of the D equations
             const LdsCell C = fresh(C0);
             const int o = fresh(o0);
-            auto q = [&](int v) -> double { return qp[v * CS + o]; };
+            auto q = [&](int v) -> double { return pw<1>(qp, o, C, v); };
             double be[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) be[k] = q(SBETA + k);
@@ -503,7 +578,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
     if (act) {
         const LdsCell C = fresh(C0);
         const int o = fresh(o0);
-        auto q = [&](int v) -> double { return qp[v * CS + o]; };
+        auto q = [&](int v) -> double { return pw<3>(qp, o, C, v); };
         double be[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) be[k] = q(SBETA + k);
@@ -520,7 +595,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
         }
         {  // ---- Ricci sector: At, K, Theta; the curl term of B
             const int o1 = fresh(o);
-            auto q1 = [&](int v) -> double { return qp[v * CS + o1]; };
+            auto q1 = [&](int v) -> double { return pw<3>(qp, o1, C, v); };
             double gd[6], igd[6], detg;
             T g[6], ig[6];
             load_metric<T>(qp, o1, gd, igd, detg, g, ig);
@@ -739,7 +814,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
         CCZ4_PHASE_BARRIER();
         {  // ---- Ghat^i, and the part of b^i it shares
             const int o1 = fresh(o);
-            auto q1 = [&](int v) -> double { return qp[v * CS + o1]; };
+            auto q1 = [&](int v) -> double { return pw<3>(qp, o1, C, v); };
             double gd[6], igd[6], detg;
             T g[6], ig[6];
             load_metric<T>(qp, o1, gd, igd, detg, g, ig);
@@ -824,7 +899,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
         CCZ4_PHASE_BARRIER();
         {  // ---- A_k and P_k
             const int o1 = fresh(o);
-            auto q1 = [&](int v) -> double { return qp[v * CS + o1]; };
+            auto q1 = [&](int v) -> double { return pw<3>(qp, o1, C, v); };
             T Bm[3][3], A[3], P[3];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -873,7 +948,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
     if (act) {
         const LdsCell C = fresh(C0);
         const int o = fresh(o0);
-        auto q = [&](int v) -> double { return qp[v * CS + o]; };
+        auto q = [&](int v) -> double { return pw<4>(qp, o, C, v); };
         double be[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) be[k] = q(SBETA + k);
@@ -901,7 +976,7 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
         // gt_ij, alpha, beta^i, phi, K_0
         double gd[6], igd[6], detg;
         T g[6], ig[6];
-        load_metric<T>(qp, o, gd, igd, detg, g, ig);
+        load_metric_with<T>(q, gd, igd, detg, g, ig);
         T At[6];
 #pragma unroll
         for (int s = 0; s < 6; ++s) At[s] = cvt<T>(q(SAT + s));

@@ -10,10 +10,12 @@ from . import ccz4
 
 
 def evolve(ctx, Q, w, steps, regrid_every, theta_r, theta_c, max_level, indicator=None, conf=0.6,
-           precision=ccz4.PREC_FP64, on_regrid=None):
+           precision=ccz4.PREC_FP64, on_regrid=None, on_tags=None):
     """Returns (ctx, Q, log): the final context and state, and per-regrid records (step, leaves
     before and after, REFINE tags of the plain criterion and of the combination, time of the
-    regrid) plus the stepping time.  Q enters with filled halos."""
+    regrid) plus the stepping time.  Q enters with filled halos.  With an indicator,
+    on_tags(rec, ctx, Q, plain_tags, feat) is called at each regrid before the combination replaces
+    the plain tags (to score the network against them)."""
     import torch
     dt = w.dt_for(ctx) if hasattr(w, "dt_for") else w.dt()
     log = {"regrids": [], "step_seconds": 0.0, "cell_stages": 0}
@@ -30,6 +32,8 @@ def evolve(ctx, Q, w, steps, regrid_every, theta_r, theta_c, max_level, indicato
                 HM = torch.empty((ctx.n_patches, 4, 729), dtype=torch.float64, device="cuda")
                 ctx.constraints(Q, HM)
                 feat = ctx.features(Q, HM)
+                if on_tags:
+                    on_tags(rec, ctx, Q, tags, feat)
                 combined = ctx.tag_learned(indicator.forward(feat), tags, conf, max_level)
                 rec["learned_refine"] = int((combined == 1).sum().item())
                 tags = combined

@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle as orc  # noqa: E402
-from gpu_helpers import INTERIOR, SLABS, parity_error, same_level_halo_mask, to_gpu, to_host  # noqa: E402
+from gpu_helpers import INTERIOR, SLABS, oracle_sensitivity, parity_error, same_level_halo_mask, to_gpu, to_host  # noqa: E402
 from paper_2406_11626_amd import ccz4, scenarios  # noqa: E402
 from seeded_inputs import box_centers, smooth_state  # noqa: E402
 
@@ -162,32 +162,40 @@ def _so_steps(w, n0, prm, refined=(), steps=2, perturb=False, kernel=ccz4.KERNEL
     pr = oparams(prm)
     dt = w.dt()
     sg = ccz4.StepGraph(ctx, Qd, bufs, dt) if graph else None
+
+    def run(Q):
+        for _ in range(steps):
+            Q = m.rk4_step(pr, Q, dt)
+        return Q
     for _ in range(steps):
         if sg is not None:
             sg.launch()
         else:
             ctx.rk4_step_fused(Qd, dt, bufs, push=push)
-        Qo = m.rk4_step(pr, Qo, dt)
     torch.cuda.synchronize()
     if sg is not None:
         sg.close()
-    return ctx, m, to_host(Qd), Qo
+    Q0 = Qo
+    Qo = run(Q0.copy())
+    # the oracle's own sensitivity to one-ulp changes of the initial state (gpu_helpers.KAPPA)
+    sens = oracle_sensitivity(run, Q0, ref=Qo)
+    return ctx, m, to_host(Qd), Qo, sens
 
 
 @pytest.mark.parametrize("push", [True, False])
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_so_fused_steps_gauge_wave_match_oracle(kernel, push):
     w = scenarios.config(1)
-    _, _, g, Qo = _so_steps(w, w.n0, so_params(w), steps=6, kernel=kernel, push=push)
-    e = parity_error(g, Qo)
+    _, _, g, Qo, sens = _so_steps(w, w.n0, so_params(w), steps=6, kernel=kernel, push=push)
+    e = parity_error(g, Qo, sens=sens, tol=1e-11)
     assert e.max() <= 1e-11, (e.argmax(), e.max())
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_so_fused_steps_puncture_sommerfeld_match_oracle(kernel):
     w = scenarios.config(2)
-    _, m, g, Qo = _so_steps(w, (2, 2, 2), so_params(w), steps=2, perturb=True, kernel=kernel)
-    e = parity_error(g, Qo)
+    _, m, g, Qo, sens = _so_steps(w, (2, 2, 2), so_params(w), steps=2, perturb=True, kernel=kernel)
+    e = parity_error(g, Qo, sens=sens, tol=1e-11)
     assert e.max() <= 1e-11, (e.argmax(), e.max())
 
 
@@ -196,15 +204,15 @@ def test_so_fused_steps_static_amr_match_oracle():
     restriction and prolongation after each stage."""
     w = scenarios.config(2)
     refined = [(0, 1, 1, 1)]
-    _, m, g, Qo = _so_steps(w, (3, 3, 3), so_params(w), refined=refined, steps=2, perturb=True)
-    e = parity_error(g, Qo)
+    _, m, g, Qo, sens = _so_steps(w, (3, 3, 3), so_params(w), refined=refined, steps=2, perturb=True)
+    e = parity_error(g, Qo, sens=sens, tol=1e-11)
     assert e.max() <= 1e-11, (e.argmax(), e.max())
 
 
 def test_so_step_graph_matches_oracle():
     w = scenarios.config(2)
-    _, _, g, Qo = _so_steps(w, (2, 2, 2), so_params(w), steps=2, perturb=True, graph=True)
-    e = parity_error(g, Qo)
+    _, _, g, Qo, sens = _so_steps(w, (2, 2, 2), so_params(w), steps=2, perturb=True, graph=True)
+    e = parity_error(g, Qo, sens=sens, tol=1e-11)
     assert e.max() <= 1e-11, (e.argmax(), e.max())
 
 
