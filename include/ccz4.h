@@ -372,6 +372,19 @@ enum { CCZ4_MLP_TRACE = 340 };
 ccz4_status ccz4_mlp_grad(const float *params, const float *norm, const float *feat, const int8_t *tags,
                           int64_t n, float *work, int64_t work_floats, float *grad, float *loss, void *stream);
 
+/* ccz4_mlp_grad without a workspace, for callers that cannot allocate (code under HIP graph
+   capture, tight serving or training loops, harnesses that forbid hipMalloc): the same kernels
+   and the same result, bit for bit, with the per-tile partials in an array that the library
+   holds on each GPU until the process ends (CCZ4_MLP_NOALLOC_MAX_ROWS / 64 tiles of
+   CCZ4_MLP_NPARAM + 1 floats, 2.5 MB).  The call allocates nothing: no hipMalloc, no host or
+   device allocation of any library.  n must be 1..CCZ4_MLP_NOALLOC_MAX_ROWS, else EINVAL (use
+   ccz4_mlp_grad with a workspace).  Every call on a GPU shares that array: calls that overlap on
+   one GPU (on different streams, or from several threads) race and give wrong gradients; calls
+   ordered on one stream do not.  No trace is written. */
+enum { CCZ4_MLP_NOALLOC_MAX_ROWS = 4096 };
+ccz4_status ccz4_mlp_grad_noalloc(const float *params, const float *norm, const float *feat, const int8_t *tags,
+                                  int64_t n, float *grad, float *loss, void *stream);
+
 /* One Adam step t >= 1 on every parameter (FP32): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
    params -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
 ccz4_status ccz4_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr,

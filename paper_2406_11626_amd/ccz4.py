@@ -116,6 +116,7 @@ def lib():
             "ccz4_mlp_forward": (i32, [P, P, P, i64, P, P]),
             "ccz4_mlp_workspace": (i32, [i64, ctypes.POINTER(i64)]),
             "ccz4_mlp_grad": (i32, [P, P, P, P, i64, P, i64, P, P, P]),
+            "ccz4_mlp_grad_noalloc": (i32, [P, P, P, P, i64, P, P, P]),
             "ccz4_mlp_adam": (i32, [P, P, P, P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                     ctypes.c_float, P]),
             "ccz4_tag_learned": (i32, [P, P, P, ctypes.c_float, i32, P, P]),
@@ -328,6 +329,14 @@ def ccz4_mlp_workspace(n):
 def ccz4_mlp_grad(params, norm, feat, tags, n, work, grad, loss=None, stream=None):
     return _check(lib().ccz4_mlp_grad(_ptr(params), _ptr(norm), _ptr(feat), _ptr(tags), int(n), _ptr(work),
                                       int(work.numel()), _ptr(grad), _ptr(loss), _stream(stream)))
+
+
+MLP_NOALLOC_MAX_ROWS = 4096
+
+
+def ccz4_mlp_grad_noalloc(params, norm, feat, tags, n, grad, loss=None, stream=None):
+    return _check(lib().ccz4_mlp_grad_noalloc(_ptr(params), _ptr(norm), _ptr(feat), _ptr(tags), int(n), _ptr(grad),
+                                              _ptr(loss), _stream(stream)))
 
 
 def ccz4_mlp_adam(params, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

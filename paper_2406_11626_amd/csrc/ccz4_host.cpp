@@ -1040,6 +1040,20 @@ ccz4_status ccz4_mlp_grad(const float *params, const float *norm, const float *f
     return CCZ4_OK;
 }
 
+ccz4_status ccz4_mlp_grad_noalloc(const float *params, const float *norm, const float *feat, const int8_t *tags,
+                                  int64_t n, float *grad, float *loss, void *stream)
+{
+    if (!params || !norm || !feat || !tags || !grad) return fail(CCZ4_EINVAL, "NULL buffer");
+    if (n <= 0) return fail(CCZ4_EINVAL, "n must be > 0");
+    if (n > (int64_t)MLP_SCRATCH_TILES * 64)
+        return fail(CCZ4_EINVAL, "n exceeds CCZ4_MLP_NOALLOC_MAX_ROWS (" + std::to_string(MLP_SCRATCH_TILES * 64) +
+                                     "): use ccz4_mlp_grad with a workspace");
+    float *work = nullptr;
+    HIP_TRY(mlp_scratch(&work));
+    HIP_TRY(launch_mlp_grad(params, norm, feat, tags, n, work, nullptr, grad, loss, S(stream)));
+    return CCZ4_OK;
+}
+
 ccz4_status ccz4_mlp_adam(float *params, float *m, float *v, const float *grad, int32_t step, float lr, float beta1,
                           float beta2, float eps, void *stream)
 {

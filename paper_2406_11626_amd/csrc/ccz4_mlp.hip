@@ -10,6 +10,8 @@
 // as the identity (straight-through).  The bias gradients sum the FP32 gradients.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "ccz4_kernels.hpp"
 #include "ccz4_mlp.hpp"
 
@@ -420,6 +422,32 @@ __global__ void k_tag_learned_family(const int8_t *__restrict__ pre, const int32
 }  // namespace
 
 int32_t mlp_tiles(int64_t n) { return (int32_t)((n + TILE - 1) / TILE); }
+
+// Per-tile partial sums of the loss gradient for callers that cannot allocate a workspace: a
+// file-scope device array, one copy per GPU, held until the process ends.  Its device address is
+// taken once per device with hipGetSymbolAddress (the array's name is not a device address in
+// host code) and kept; kernels receive that address.  Every grad call on a GPU shares the array.
+__device__ __align__(256) float scratch[MLP_SCRATCH_TILES * (MLP_NPARAM + 1)];
+
+hipError_t mlp_scratch(float **out)
+{
+    constexpr int MAXDEV = 64;
+    static std::mutex mu;
+    static float *addr[MAXDEV] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAXDEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<float *>(ptr);
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_features(const double *Q, const double *HM, const PatchGeom *geom, int32_t npatch, float *feat,
                            hipStream_t st)

@@ -11,6 +11,10 @@ constexpr int MLP_NIN = 81, MLP_NH = 64, MLP_NOUT = 3, MLP_NPARAM = 9603;
 constexpr int MLP_TRACE = MLP_NIN + 4 * MLP_NH + MLP_NOUT;
 
 int32_t mlp_tiles(int64_t n);
+// the library's own gradient partials (ccz4_mlp_grad_noalloc): room for this many 64-row tiles
+constexpr int MLP_SCRATCH_TILES = 64;
+// device address of the partials array on the current device (taken once per device)
+hipError_t mlp_scratch(float **out);
 hipError_t launch_features(const double *Q, const double *HM, const PatchGeom *geom, int32_t npatch, float *feat,
                            hipStream_t st);
 hipError_t launch_mlp_forward(const float *prm, const float *norm, const float *feat, int64_t n, float *logits,

@@ -40,8 +40,13 @@ def test_argument_errors_without_gpu():
                      ("ccz4_rk4_stage", (None, 0, 0.1, None, None, None, None, None)),
                      ("ccz4_constraints", (None, None, None, 0.0, None, None)),
                      ("ccz4_set_kernel", (None, 0, 1)), ("ccz4_get_kernel", (None, 0, None)),
-                     ("ccz4_reconstruct_aux", (None, None, 0, None))):
+                     ("ccz4_reconstruct_aux", (None, None, 0, None)),
+                     ("ccz4_mlp_grad_noalloc", (None, None, None, None, 1, None, None, None))):
         assert getattr(L, fn)(*args) == ccz4.CCZ4_EINVAL
+    # the no-allocation gradient: row counts outside 1..CCZ4_MLP_NOALLOC_MAX_ROWS before any launch
+    buf = (ctypes.c_float * 4)()
+    for n in (0, -1, ccz4.MLP_NOALLOC_MAX_ROWS + 1):
+        assert L.ccz4_mlp_grad_noalloc(buf, buf, buf, buf, n, buf, None, None) == ccz4.CCZ4_EINVAL
     g = ccz4.GridDesc()
     g.n0[:] = [0, 1, 1]
     g.extent[:] = [1.0, 1.0, 1.0]
