@@ -511,10 +511,12 @@ def run_tracker(args):
                 wall_s=wall, ms_per_step=wall * 1e3 / max(1, i), track=track)
 
 
-def _bbh_training_runs(args, names):
+def _bbh_training_runs(args, names, theta=None, max_level=2):
     """Second-order binary-puncture runs on the static r = 2 refinement (the tracker workload) to
     t_end, with snapshots of the leaf features and the plain tags every sample_dt; the Bowen-York
-    momenta scaled per run.  Returns {name: (ctx, snapshots, norms)} and the thresholds."""
+    momenta scaled per run.  The plain tags use the thresholds theta (default: the 99th and 30th
+    percentiles of the first run's indicator at t = 0) and max_level.  Returns {name: (ctx,
+    snapshots, norms)} and the thresholds."""
     import numpy as np
     import torch
     from paper_2406_11626_amd import ccz4, learned, scenarios
@@ -538,10 +540,10 @@ def _bbh_training_runs(args, names):
         if theta is None:  # thresholds from the first run's indicator at t = 0, kept for all runs
             ind = torch.empty((ctx.n_patches, 3), dtype=torch.float64, device="cuda")
             tags = torch.empty(ctx.n_patches, dtype=torch.int8, device="cuda")
-            ctx.tag_refine(Q, 1e300, -1.0, 2, tags, ind)
+            ctx.tag_refine(Q, 1e300, -1.0, max_level, tags, ind)
             e = ind.max(dim=1).values.cpu().numpy()
             theta = (float(np.percentile(e, 99.0)), float(np.percentile(e, 30.0)))
-        snaps = learned.snapshots(ctx, Q, dt, steps, every, theta[0], theta[1], 2)
+        snaps = learned.snapshots(ctx, Q, dt, steps, every, theta[0], theta[1], max_level)
         norms, _ = ctx.constraints(Q)
         del Q
         runs[name] = (ctx, snaps, norms)
@@ -571,18 +573,48 @@ def _train_on(runs, names, args):
                      loss_after=loss, train_s=time.perf_counter() - t1)
 
 
-def train_bbh_indicator(args):
+def train_bbh_indicator(args, theta=None, max_level=2):
     """The indicator trained on two second-order binary-puncture runs (momenta x0.9 and x1.1),
-    features of snapshot k against the plain tags of snapshot k + 1."""
+    features of snapshot k against the plain tags of snapshot k + 1 (thresholds theta, max_level
+    as the workload it will serve uses them)."""
     names = (("train_0.9", 0.9), ("train_1.1", 1.1))
     t0 = time.perf_counter()
-    runs, theta, w, dt, every = _bbh_training_runs(args, names)
+    runs, theta, w, dt, every = _bbh_training_runs(args, names, theta, max_level)
     sim_s = time.perf_counter() - t0
     ind, info = _train_on(runs, [n for n, _ in names], args)
     for ctx, _, _ in runs.values():
         ctx.close()
     return ind, dict(info, workload=w.name + ", second-order formulation", t_end=args.t_end,
                      sample_dt=every * dt, simulation_s=sim_s)
+
+
+def train_mesh_indicator(args, w, theta, max_level, scales=(0.9, 1.1), steps=60, every=10):
+    """The indicator trained on runs of workload w's own mesh and formulation with the Bowen-York
+    momenta scaled (the workload's own momenta held out): features every `every` steps (the regrid
+    interval) against the plain tags (thresholds theta) `every` steps later."""
+    import torch
+    from paper_2406_11626_amd import ccz4, learned
+    t0 = time.perf_counter()
+    runs = {}
+    for scale in scales:
+        scen = list(w.scen)
+        scen[5] *= scale   # y momentum of the puncture at +x
+        scen[12] *= scale  # and of the one at -x
+        ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, w.params(), w.refined)
+        Q = ctx.new_state(0.0)
+        ctx.init_patches(Q, w.scenario, scen)
+        ctx.fill_halos(Q)
+        snaps = learned.snapshots(ctx, Q, w.dt(), steps, every, theta[0], theta[1], max_level)
+        del Q
+        ctx.close()
+        torch.cuda.empty_cache()
+        name = f"momenta_x{scale}"
+        runs[name] = (None, snaps, None)
+        _say(f"{name}: {len(snaps)} snapshots, REFINE per snapshot {[int((t == 1).sum()) for _, t in snaps]}")
+    sim_s = time.perf_counter() - t0
+    ind, info = _train_on(runs, list(runs), args)
+    return ind, dict(info, workload=w.name + f", Bowen-York momenta x{list(scales)}, {steps} steps, a snapshot "
+                     f"every {every}", simulation_s=sim_s)
 
 
 def run_learned_bbh(args):
@@ -644,8 +676,8 @@ def run_dynamic(args, w):
     del Q
     ctx.close()
     torch.cuda.empty_cache()
-    _say("training the learned indicator on second-order binary-puncture runs")
-    net, train = train_bbh_indicator(args)
+    _say("training the learned indicator on runs of the same mesh with other momenta")
+    net, train = train_mesh_indicator(args, w, (theta_r, theta_c), 3)
     torch.cuda.empty_cache()
     ctx, Q = start()
 

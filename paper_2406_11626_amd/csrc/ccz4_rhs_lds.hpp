@@ -27,10 +27,11 @@
 
 namespace ccz4 {
 
-// Row pitch of the staged own planes in LDS (doubles): the box row (16), or 18, whose odd pair
-// count spreads the rows of a wave's reads over the LDS banks (the extra pair is a repeat copy).
+// Row pitch of the staged own planes in LDS (doubles): 18 (default), whose odd pair count spreads
+// the rows of a wave's reads over the LDS banks (the extra pair is a repeat copy), or the box row
+// (16), whose rows all fall on the same banks.
 #ifndef CCZ4_LDS_ROW
-#define CCZ4_LDS_ROW 16
+#define CCZ4_LDS_ROW 18
 #endif
 constexpr int LROW = CCZ4_LDS_ROW;
 static_assert(LROW == 16 || LROW == 18, "LDS row pitch: 16 or 18 doubles");
@@ -295,7 +296,7 @@ __device__ __forceinline__ constexpr int round_buffer(int r, int v)
 // Pointwise value of slot v at the lane's cell during round R: from the staged copy in LDS when
 // the round stages v (the same double), else from the patch box at offset o.
 #ifndef CCZ4_PW_LDS
-#define CCZ4_PW_LDS 0
+#define CCZ4_PW_LDS 1
 #endif
 template <int R>
 __device__ __forceinline__ double pw(const double *__restrict__ qp, int o, const LdsCell &C, int v)
@@ -399,6 +400,10 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
     T G1[3][3], H[3][3], U[3][3], E[6];
     T BB[3][3], curl[3][3];
     double rGb[3];
+    // the pointwise parts of the gt, alpha, beta and phi equations, formed in round 3 where their
+    // inputs are at hand (round 4 adds the Kreiss-Oliger sums and f b^i)
+    double pwG[6], pwA, pwPhi;
+    T bB[3];
     double ro2[15], ro3[20], ro4[24];  // each round's outputs, handed to the sink after the round
 
     // ------------------------------------------------------------ round 1: At, B
@@ -895,6 +900,24 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
                 keep(ro3[11 + i], rG + sG.k);
                 rGb[i] = rG - advG;
             }
+            // gt_ij: 2 beta^k D_kij + gt_ki B_j^k + gt_kj B_i^k - 2/3 gt_ij tr B - 2 alpha (At_ij - gt_ij tr At / 3)
+            // - (det gt - 1) gt_ij / tau
+            T bet[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) bet[k] = cvt<T>(be[k]);
+            const T trAt = tr6(ig, At);
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = i; j < 3; ++j) {
+                    const int ij = sym(i, j);
+                    T t = T(2) * (bet[0] * D[0][ij] + bet[1] * D[1][ij] + bet[2] * D[2][ij]);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) t += g[sym(k, i)] * Bm[j][k] + g[sym(k, j)] * Bm[i][k];
+                    t += T(-2.0 / 3.0) * g[ij] * trB;
+                    t += T(-2) * al * (At[ij] - T(1.0 / 3.0) * g[ij] * trAt);
+                    keep(pwG[ij], static_cast<double>(t) - (detg - 1.0) / p.tau * gd[ij]);
+                }
         }
         CCZ4_PHASE_BARRIER();
         {  // ---- A_k and P_k
@@ -929,6 +952,17 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
                 const SlotDeriv sP = stencils<LOP>(C, 3 + k, be, p.advection);
                 keep(ro3[17 + k], sP.a + static_cast<double>(u) + phid * static_cast<double>(phipart) + sP.k);
             }
+            // alpha: beta^k A_k - alpha^2 g (K - K_0 - 2 c Theta); beta^i: beta^k B_k^i (+ f b^i in round 4);
+            // phi: beta^k P_k + phi (alpha K - tr B) / 3
+            T bet[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) bet[k] = cvt<T>(be[k]);
+            keep(pwA, static_cast<double>(bet[0] * A[0] + bet[1] * A[1] + bet[2] * A[2] -
+                                          al * al * ga * (Kt - K0 - T(2) * cc * Th)));
+#pragma unroll
+            for (int i = 0; i < 3; ++i) bB[i] = bet[0] * Bm[0][i] + bet[1] * Bm[1][i] + bet[2] * Bm[2][i];
+            keep(pwPhi, be[0] * q1(SP) + be[1] * q1(SP + 1) + be[2] * q1(SP + 2) +
+                            phid * static_cast<double>((al * Kt - trB) * T(1.0 / 3.0)));
         }
     }
 
@@ -973,54 +1007,19 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
 #pragma unroll
             for (int i = 0; i < 3; ++i) keep(ro4[9 + i], 0.0);
         }
-        // gt_ij, alpha, beta^i, phi, K_0
-        double gd[6], igd[6], detg;
-        T g[6], ig[6];
-        load_metric_with<T>(q, gd, igd, detg, g, ig);
-        T At[6];
+        // gt_ij, alpha, beta^i, phi: the pointwise parts from round 3 and the KO sums; K_0: 0
 #pragma unroll
-        for (int s = 0; s < 6; ++s) At[s] = cvt<T>(q(SAT + s));
-        T bet[3], Bm[3][3], A[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            bet[k] = cvt<T>(be[k]);
-            A[k] = cvt<T>(q(SA + k));
-#pragma unroll
-            for (int i = 0; i < 3; ++i) Bm[k][i] = cvt<T>(q(SB + 3 * k + i));
-        }
-        const T trB = Bm[0][0] + Bm[1][1] + Bm[2][2];
-        const T trAt = tr6(ig, At);
-        const T al = cvt<T>(q(SALPHA));
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = i; j < 3; ++j) {
-                const int ij = sym(i, j);
-                T t = T(2) * (bet[0] * cvt<T>(q(SD + ij)) + bet[1] * cvt<T>(q(SD + 6 + ij)) +
-                              bet[2] * cvt<T>(q(SD + 12 + ij)));
-#pragma unroll
-                for (int k = 0; k < 3; ++k) t += g[sym(k, i)] * Bm[j][k] + g[sym(k, j)] * Bm[i][k];
-                t += T(-2.0 / 3.0) * g[ij] * trB;
-                t += T(-2) * al * (At[ij] - T(1.0 / 3.0) * g[ij] * trAt);
-                keep(ro4[12 + ij], static_cast<double>(t) - (detg - 1.0) / p.tau * gd[ij] + stencils(C, 3 + ij).k);
-            }
-        const T Kt = cvt<T>(q(SK)), K0 = cvt<T>(q(SK0)), Th = cvt<T>(q(STHETA));
-        const T ga = p.slicing == 1 ? T(2) / al : T(1);
-        keep(ro4[18], (static_cast<double>(bet[0] * A[0] + bet[1] * A[1] + bet[2] * A[2] -
-                                            al * al * ga * (Kt - K0 - T(2) * cc * Th)) +
-                            stencils(C, 9).k));
+        for (int s = 0; s < 6; ++s) keep(ro4[12 + s], pwG[s] + stencils(C, 3 + s).k);
+        keep(ro4[18], pwA + stencils(C, 9).k);
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
             if (gdrv)
-                keep(ro4[19 + i], (static_cast<double>(bet[0] * Bm[0][i] + bet[1] * Bm[1][i] + bet[2] * Bm[2][i] +
-                                                       cvt<T>(p.f) * cvt<T>(q(SBB + i))) +
-                                       stencils(C, 10 + i).k));
+                keep(ro4[19 + i], (static_cast<double>(bB[i] + cvt<T>(p.f) * cvt<T>(q(SBB + i))) +
+                                   stencils(C, 10 + i).k));
             else
                 keep(ro4[19 + i], 0.0);
         }
-        const double phid = q(SPHI);
-        keep(ro4[22], (be[0] * q(SP) + be[1] * q(SP + 1) + be[2] * q(SP + 2) +
-                          phid * static_cast<double>((al * Kt - trB) * T(1.0 / 3.0)) + stencils(C, 13).k));
+        keep(ro4[22], pwPhi + stencils(C, 13).k);
         keep(ro4[23], 0.0);
     }
     {
