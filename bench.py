@@ -902,7 +902,7 @@ def main():
     Q64 = r64.pop("Q", None)
     if not args.no_mixed:
         _say("mixed-precision fused step")
-        rm = run_gpu(args, w, 1, total_steps=horizon, keep=True)
+        rm = run_gpu(args, w, 1, total_steps=max(horizon, r64["steps_total"]), keep=True)
         vm = rm["cells"] * stages / rm["wall"]
         Qm = rm.pop("Q")
         per_slot, emax, kmax = state_error(Qm, Q64)
@@ -919,7 +919,7 @@ def main():
                                                             "relative to the largest)"}}
     if not args.no_plain:
         _say("plain unfused FP64 path")
-        rp = run_plain(args, w, total_steps=horizon, keep=True)
+        rp = run_plain(args, w, total_steps=max(horizon, r64["steps_total"]), keep=True)
         vp = rp["cells"] * stages / rp["wall"]
         Qp = rp.pop("Q")
         per_slot, emax, kmax = state_error(Qp, Q64)
