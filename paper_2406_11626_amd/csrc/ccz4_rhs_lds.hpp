@@ -366,6 +366,79 @@ __device__ __forceinline__ void keep(double &r, double v)
     asm volatile("" : "+v"(r));
 }
 
+// Round 3's Ghat^i sector: its right-hand side (ro3[11..13]), the part of b^i's right-hand side it
+// shares (rGb) and the pointwise part of the gt_ij equation (pwG), from the cell's metric, D, At,
+// B, A, P / phi, the Christoffel symbols and Z, and the contractions carried from rounds 1 and 2.
+template <typename T, int LOP>
+__device__ __forceinline__ void ghat_sector(const LdsCell &C, const RhsParams &p, const double be[3], const T g[6],
+                                            const T ig[6], const double gd[6], double detg, const T (&D)[3][6],
+                                            const T (&Gt)[3][6], const T Gtv[3], const T At[6], const T (&Am)[3][3],
+                                            const T (&Bm)[3][3], const T A[3], const T Ph[3], T trB, T al, T Kt, T Th,
+                                            const T Zl[3], const T GB[3], const T sdBtr[3], const T dtrA[3], T red,
+                                            T sfac, double (&ro3)[20], double (&rGb)[3], double (&pwG)[6])
+{
+    T Aup[6];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j)
+            Aup[sym(i, j)] = Am[i][0] * ig[sym(0, j)] + Am[i][1] * ig[sym(1, j)] + Am[i][2] * ig[sym(2, j)];
+    const T kap1 = cvt<T>(p.kappa1), kap3 = cvt<T>(p.kappa3);
+    T dTh[3], dK[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        dTh[k] = cvt<T>(fd(C, 13, k));
+        dK[k] = cvt<T>(fd(C, 12, k));
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        T t = GB[i];
+        T u = T(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const T igik = ig[sym(i, k)];
+            t += T(2) * al * igik * (dTh[k] + red * dtrA[k]) - T(4.0 / 3.0) * al * igik * dK[k];
+            t += sfac * T(1.0 / 3.0) * igik * sdBtr[k];
+            t += T(-2) * igik * (Th * A[k] + T(2.0 / 3.0) * al * Kt * Zl[k] + al * kap1 * Zl[k]);
+            u += igik * Zl[k];
+        }
+        t += T(2.0 / 3.0) * Gtv[i] * trB - (Gtv[0] * Bm[0][i] + Gtv[1] * Bm[1][i] + Gtv[2] * Bm[2][i]);
+        T ga = tr6(Aup, Gt[i]) - T(3) * (Aup[sym(i, 0)] * Ph[0] + Aup[sym(i, 1)] * Ph[1] + Aup[sym(i, 2)] * Ph[2]);
+        t += T(2) * al * ga;
+        t += T(-2) * (Aup[sym(i, 0)] * A[0] + Aup[sym(i, 1)] * A[1] + Aup[sym(i, 2)] * A[2]);
+        T zb = T(0);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const T zk = ig[sym(k, 0)] * Zl[0] + ig[sym(k, 1)] * Zl[1] + ig[sym(k, 2)] * Zl[2];
+            zb += zk * Bm[k][i];
+        }
+        t += T(2) * kap3 * (T(2.0 / 3.0) * u * trB - zb);
+        const SlotDeriv sG = stencils<LOP>(C, 9 + i, be, p.advection);
+        const double advG = sG.a;
+        const double rG = advG + static_cast<double>(t);
+        keep(ro3[11 + i], rG + sG.k);
+        rGb[i] = rG - advG;
+    }
+    // gt_ij: 2 beta^k D_kij + gt_ki B_j^k + gt_kj B_i^k - 2/3 gt_ij tr B - 2 alpha (At_ij - gt_ij tr At / 3)
+    // - (det gt - 1) gt_ij / tau
+    T bet[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) bet[k] = cvt<T>(be[k]);
+    const T trAt = tr6(ig, At);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j) {
+            const int ij = sym(i, j);
+            T t = T(2) * (bet[0] * D[0][ij] + bet[1] * D[1][ij] + bet[2] * D[2][ij]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) t += g[sym(k, i)] * Bm[j][k] + g[sym(k, j)] * Bm[i][k];
+            t += T(-2.0 / 3.0) * g[ij] * trB;
+            t += T(-2) * al * (At[ij] - T(1.0 / 3.0) * g[ij] * trAt);
+            keep(pwG[ij], static_cast<double>(t) - (detg - 1.0) / p.tau * gd[ij]);
+        }
+}
+
 // Output slots of rounds 2, 3 and 4, in the order of the round's output buffer.
 __device__ constexpr int R2_OUT[15] = {SD, SD + 1, SD + 2, SD + 3, SD + 4, SD + 5, SD + 6, SD + 7,
                                        SD + 8, SD + 9, SD + 10, SD + 11, SD + 12, SD + 13, SD + 14};
@@ -393,6 +466,10 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
     // the red terms of the Ghat equation (2 alpha gt^ik d_k tr At, with d_k gt^nm = -2 D_k^nm)
     // belong to the first-order formulation only
     const T red = p.formulation ? T(0) : T(1);
+    // Round 3's Ghat sector shares the Ricci sector's loads and Christoffel symbols when the algebra is
+    // FP32 (room in the register file); with FP64 algebra it reloads them in a block of its own, which
+    // keeps the register peak of the Ricci sector below spilling.
+    constexpr bool GHAT_IN_RICCI = sizeof(T) == 4;
 
     // carried between rounds
     T dtrA[3], sdBtr[3], GB[3], partD[3][6];
@@ -815,9 +892,12 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
                         curl[k][i] = a2mu * cu;
                     }
             }
+            if constexpr (GHAT_IN_RICCI)  // the same metric, D, At, B, A, P / phi and Christoffel symbols
+                ghat_sector<T, LOP>(C, p, be, g, ig, gd, detg, D, Gt, Gtv, At, Am, Bm, A, Pphi, trB, al, Kt, Th, Zl, GB,
+                                    sdBtr, dtrA, red, sfac, ro3, rGb, pwG);
         }
         CCZ4_PHASE_BARRIER();
-        {  // ---- Ghat^i, and the part of b^i it shares
+        if constexpr (!GHAT_IN_RICCI) {  // ---- Ghat^i, and the part of b^i it shares
             const int o1 = fresh(o);
             auto q1 = [&](int v) -> double { return pw<3>(qp, o1, C, v); };
             double gd[6], igd[6], detg;
@@ -833,20 +913,12 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
             T Dup[3][6], Gl[3][6], Gt[3][6], Gtv[3];
             raise_D(ig, D, Dup);
             christoffel(ig, D, Gl, Gt, Gtv);
-            T Aup[6];
-            {
-                T Am[3][3];
+            T Am[3][3];
 #pragma unroll
-                for (int i = 0; i < 3; ++i)
+            for (int i = 0; i < 3; ++i)
 #pragma unroll
-                    for (int j = 0; j < 3; ++j)
-                        Am[i][j] = ig[sym(i, 0)] * At[sym(0, j)] + ig[sym(i, 1)] * At[sym(1, j)] + ig[sym(i, 2)] * At[sym(2, j)];
-#pragma unroll
-                for (int i = 0; i < 3; ++i)
-#pragma unroll
-                    for (int j = i; j < 3; ++j)
-                        Aup[sym(i, j)] = Am[i][0] * ig[sym(0, j)] + Am[i][1] * ig[sym(1, j)] + Am[i][2] * ig[sym(2, j)];
-            }
+                for (int j = 0; j < 3; ++j)
+                    Am[i][j] = ig[sym(i, 0)] * At[sym(0, j)] + ig[sym(i, 1)] * At[sym(1, j)] + ig[sym(i, 2)] * At[sym(2, j)];
             T Bm[3][3], A[3], Ph[3];
             const double iphid = 1.0 / q1(SPHI);
 #pragma unroll
@@ -864,60 +936,8 @@ __device__ __forceinline__ void rhs_slab_lds(const double *__restrict__ qp, doub
 #pragma unroll
             for (int i = 0; i < 3; ++i)
                 Zl[i] = T(0.5) * (g[sym(i, 0)] * dG[0] + g[sym(i, 1)] * dG[1] + g[sym(i, 2)] * dG[2]);
-            const T kap1 = cvt<T>(p.kappa1), kap3 = cvt<T>(p.kappa3);
-            T dTh[3], dK[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                dTh[k] = cvt<T>(fd(C, 13, k));
-                dK[k] = cvt<T>(fd(C, 12, k));
-            }
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                T t = GB[i];
-                T u = T(0);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const T igik = ig[sym(i, k)];
-                    t += T(2) * al * igik * (dTh[k] + red * dtrA[k]) - T(4.0 / 3.0) * al * igik * dK[k];
-                    t += sfac * T(1.0 / 3.0) * igik * sdBtr[k];
-                    t += T(-2) * igik * (Th * A[k] + T(2.0 / 3.0) * al * Kt * Zl[k] + al * kap1 * Zl[k]);
-                    u += igik * Zl[k];
-                }
-                t += T(2.0 / 3.0) * Gtv[i] * trB - (Gtv[0] * Bm[0][i] + Gtv[1] * Bm[1][i] + Gtv[2] * Bm[2][i]);
-                T ga = tr6(Aup, Gt[i]) - T(3) * (Aup[sym(i, 0)] * Ph[0] + Aup[sym(i, 1)] * Ph[1] + Aup[sym(i, 2)] * Ph[2]);
-                t += T(2) * al * ga;
-                t += T(-2) * (Aup[sym(i, 0)] * A[0] + Aup[sym(i, 1)] * A[1] + Aup[sym(i, 2)] * A[2]);
-                T zb = T(0);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const T zk = ig[sym(k, 0)] * Zl[0] + ig[sym(k, 1)] * Zl[1] + ig[sym(k, 2)] * Zl[2];
-                    zb += zk * Bm[k][i];
-                }
-                t += T(2) * kap3 * (T(2.0 / 3.0) * u * trB - zb);
-                const SlotDeriv sG = stencils<LOP>(C, 9 + i, be, p.advection);
-                const double advG = sG.a;
-                const double rG = advG + static_cast<double>(t);
-                keep(ro3[11 + i], rG + sG.k);
-                rGb[i] = rG - advG;
-            }
-            // gt_ij: 2 beta^k D_kij + gt_ki B_j^k + gt_kj B_i^k - 2/3 gt_ij tr B - 2 alpha (At_ij - gt_ij tr At / 3)
-            // - (det gt - 1) gt_ij / tau
-            T bet[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) bet[k] = cvt<T>(be[k]);
-            const T trAt = tr6(ig, At);
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = i; j < 3; ++j) {
-                    const int ij = sym(i, j);
-                    T t = T(2) * (bet[0] * D[0][ij] + bet[1] * D[1][ij] + bet[2] * D[2][ij]);
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) t += g[sym(k, i)] * Bm[j][k] + g[sym(k, j)] * Bm[i][k];
-                    t += T(-2.0 / 3.0) * g[ij] * trB;
-                    t += T(-2) * al * (At[ij] - T(1.0 / 3.0) * g[ij] * trAt);
-                    keep(pwG[ij], static_cast<double>(t) - (detg - 1.0) / p.tau * gd[ij]);
-                }
+            ghat_sector<T, LOP>(C, p, be, g, ig, gd, detg, D, Gt, Gtv, At, Am, Bm, A, Ph, trB, al, Kt, Th, Zl, GB, sdBtr,
+                                dtrA, red, sfac, ro3, rGb, pwG);
         }
         CCZ4_PHASE_BARRIER();
         {  // ---- A_k and P_k
