@@ -905,7 +905,7 @@ __global__ __launch_bounds__(256) void k_rk4_ghost(int32_t s, double dt, const d
 // (momentum constraint) enter: 28 slots.  One work-group per z-slab of a leaf stages them into LDS
 // in two rounds of 14 (the stage kernel's slab staging, own halos), forms each cell's FD4
 // differences from LDS, and takes the pointwise values of the staged slots from LDS too; the
-// other slots are read from the state.  Per-block partial sums (H^2, |M|^2, counted cells,
+// other slots are read from the state, their loads in flight with the second round's copies.  Per-block partial sums (H^2, |M|^2, counted cells,
 // non-finite cells) in a fixed order for k_reduce_parts.
 constexpr int CONS_NB = 14;
 __global__ __launch_bounds__(256) void k_constraints_lds(const double *__restrict__ Q, double *__restrict__ HM,
@@ -949,7 +949,15 @@ __global__ __launch_bounds__(256) void k_constraints_lds(const double *__restric
             }
         const int rb[CONS_NB] = {SD + 14, SD + 15, SD + 16, SD + 17, SP, SP + 1, SP + 2,
                                  SAT, SAT + 1, SAT + 2, SAT + 3, SAT + 4, SAT + 5, SK};
-        lds_round(qb, lds, sl, rb, w, lane, hs);
+        lds_issue(qb, lds, sl, rb, w, lane, hs);
+        // the remaining slots pointwise (every slot takes part in the finiteness count), in
+        // flight together with the second round's copies; an idle lane reads cell 242's values
+#pragma unroll
+        for (int v = 0; v < SAT; ++v) q[v] = qb[v * CS + o];
+#pragma unroll
+        for (int v = STHETA; v < SD; ++v) q[v] = qb[v * CS + o];
+        q[SK0] = qb[SK0 * CS + o];
+        lds_wait();
         if (act) {
 #pragma unroll
             for (int j = 0; j < CONS_NB; ++j) {
@@ -957,12 +965,6 @@ __global__ __launch_bounds__(256) void k_constraints_lds(const double *__restric
 #pragma unroll
                 for (int a = 0; a < 3; ++a) dq[a][rb[j] - DOFF] = fd(C, j, a);
             }
-            // the remaining slots pointwise (every slot takes part in the finiteness count)
-#pragma unroll
-            for (int v = 0; v < SAT; ++v) q[v] = qb[v * CS + o];
-#pragma unroll
-            for (int v = STHETA; v < SD; ++v) q[v] = qb[v * CS + o];
-            q[SK0] = qb[SK0 * CS + o];
             bool fin = true;
 #pragma unroll
             for (int v = 0; v < NV; ++v) fin = fin && isfinite(q[v]);
