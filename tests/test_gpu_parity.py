@@ -10,7 +10,7 @@ torch = pytest.importorskip("torch")
 
 import oracle as orc  # noqa: E402
 from gpu_helpers import (FLOOR, INTERIOR, SLABS, oracle_sensitivity, parity_error, perturbed_runs,  # noqa: E402
-                         same_level_halo_mask, sensitivity, to_gpu, to_host)
+                         same_level_halo_mask, sensitivity, to_gpu, to_host, ulp_perturbed)
 from paper_2406_11626_amd import ccz4, scenarios  # noqa: E402
 from seeded_inputs import box_centers, smooth_state  # noqa: E402
 
@@ -413,6 +413,99 @@ def test_full_size_step_graph_sampled():
     assert bm.any()
     # the step moved the state: the comparison is not one of unchanged data
     assert np.abs(ref[:, 3:12, 3:12, 3:12] - Q0[:, 3:12, 3:12, 3:12]).max() > 1e-10
+
+
+def _subbox_oracle(w, ijk, margin=2):
+    """An oracle mesh of the level-0 leaves within `margin` leaves of leaf ijk (clipped to the
+    domain), with the workload's spacing, boundary condition and initial data: one RK4 step
+    moves information 12 cells (four stages of reach 3), less than the 18 cells of two leaves,
+    so the step's result on leaf ijk does not see the sub-box's own faces inside the domain."""
+    L = w.extent[0] / w.n0[0]
+    lo = [max(0, c - margin) for c in ijk]
+    n = [min(w.n0[a] - 1, ijk[a] + margin) - lo[a] + 1 for a in range(3)]
+    m = orc.Mesh(tuple(n), tuple(w.origin[a] + lo[a] * L for a in range(3)), tuple(n[a] * L for a in range(3)), w.bc)
+    Q = m.zeros()
+    m.init(Q, w.scenario, w.scen)
+    return m, lo, Q
+
+
+def nonzero_perturbed_runs(fn, Q, trials=2, seed=1234):
+    """perturbed_runs with the zeros of Q left alone (one unit in the last place of a zero is a
+    subnormal number, which slows the oracle's arithmetic many times over on a large box)."""
+    return [fn(np.where(Q == 0.0, Q, ulp_perturbed(Q, seed + t))) for t in range(trials)]
+
+
+def test_full_size_step_graph_config4_sampled():
+    """The single puncture on its full 24^3-leaf mesh (13,824 leaves, 23.5 GB per state), one RK4
+    step in the launch configuration of the benchmark (autotuned stage kernel, block and leaf
+    order, the step's halo flags, the captured step graph), against the oracle on sampled leaves.
+    The oracle cannot step the whole mesh in a test, so each sampled leaf is stepped on an oracle
+    sub-box of the leaves around it; the sub-box's initial data (bit-identical geometry) are
+    uploaded into the GPU state, so that both sides start from the same values wherever the
+    sampled leaf's step can look.  Samples: the two domain corners, the leaves at the puncture,
+    a boundary face and edge leaf, an interior leaf."""
+    w = scenarios.config(4)
+    ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, w.params(), w.refined)
+    assert ctx.n_patches == 13824
+    index = {tuple(r[1:]): p for p, r in enumerate(ctx.ids)}
+    samples = [(0, 0, 0), (23, 23, 23), (11, 11, 11), (12, 12, 12), (0, 12, 23), (5, 17, 9)]
+    Qd = ctx.new_state(0.0)
+    ctx.init_patches(Qd, w.scenario, w.scen)
+    subs = []
+    for ijk in samples:
+        m, lo, Q = _subbox_oracle(w, ijk)
+        full = [index[(r[1] + lo[0], r[2] + lo[1], r[3] + lo[2])] for r in m.ids]
+        np.testing.assert_array_equal(ctx.geom[full], m.geom)  # the same leaves, bit for bit
+        Qd[torch.tensor(full, device="cuda")] = to_gpu(Q)
+        here = [p for p, r in enumerate(m.ids) if (r[1] + lo[0], r[2] + lo[1], r[3] + lo[2]) == ijk][0]
+        subs.append((m, Q, here, index[ijk]))
+    ctx.set_background(Qd)  # the boundary background of the uploaded leaves, as on the oracle side
+    ctx.fill_halos(Qd)
+    ctx.autotune(Qd, reps=1)
+    ctx.fill_halos(Qd)
+    dt = w.dt()
+    bufs = (ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0))
+    g = ctx.step_graph(Qd, bufs, dt)
+    g.launch()
+    torch.cuda.synchronize()
+    g.close()
+    del bufs
+    got = to_host(Qd, [s[3] for s in subs])
+    del Qd
+    torch.cuda.empty_cache()
+    pr = oparams(w.params())
+    for n, (m, Q, here, p) in enumerate(subs):
+        m.set_background(Q)
+        m.fill_halos(Q)
+
+        def run(Q0, m=m):
+            return m.rk4_step(pr, Q0, dt)
+        Q0 = Q.copy()
+        ref = run(Q0.copy())
+        r1, g1 = ref[here:here + 1], got[n:n + 1]
+        runs = None
+        e = parity_error(g1, r1, INTERIOR)
+        if e.max() > 1e-11:  # a cancellation residual: the oracle's own one-ulp sensitivity decides
+            runs = nonzero_perturbed_runs(run, Q0)
+            e = parity_error(g1, r1, INTERIOR, sens=sensitivity(r1, [r[here:here + 1] for r in runs]), tol=1e-11)
+        assert e.max() <= 1e-11, (samples[n], "interior", e.argmax(), e.max())
+        bm = np.zeros((1, 15, 15, 15), bool)  # the sampled leaf's ghost slabs on the domain's faces
+        for a, c in enumerate(samples[n]):
+            for side, cut_a in ((c == 0, slice(0, 3)), (c == w.n0[a] - 1, slice(12, 15))):
+                if side:
+                    cut = [slice(3, 12)] * 3
+                    cut[2 - a] = cut_a
+                    bm[(0,) + tuple(cut)] = True
+        if bm.any():
+            gh = lambda a: np.where(bm[..., None], a, 0.0)  # noqa: E731
+            eg = parity_error(gh(g1), gh(r1), SLABS)
+            if eg.max() > 1e-11:
+                runs = runs or nonzero_perturbed_runs(run, Q0)
+                eg = parity_error(gh(g1), gh(r1), SLABS, tol=1e-11,
+                                  sens=sensitivity(gh(r1), [gh(r[here:here + 1]) for r in runs], SLABS))
+            assert eg.max() <= 1e-11, (samples[n], "ghosts", eg.argmax(), eg.max())
+        # the step moved the state
+        assert np.abs(r1[:, 3:12, 3:12, 3:12] - Q0[here:here + 1, 3:12, 3:12, 3:12]).max() > 1e-10
 
 
 # ------------------------------------------------------------------ fused stage
