@@ -681,7 +681,7 @@ def run_dynamic(args, w):
     torch.cuda.empty_cache()
     ctx, Q = start()
 
-    def judge(rec, ctx_, Q_, plain_tags, feat):
+    def score_against_plain(rec, ctx_, Q_, plain_tags, feat):
         logits = net.forward(feat)
         own = (torch.argmax(logits, dim=1) - 1).to(torch.int8)
         miss, extra = learned.miss_rate(own, plain_tags)
@@ -690,7 +690,7 @@ def run_dynamic(args, w):
 
     _say("config 5, plain criterion with the learned indicator")
     ctx, Q, logl = dynamic.evolve(ctx, Q, w, args.steps, 10, theta_r, theta_c, 3, indicator=net, conf=0.6,
-                                  on_tags=judge)
+                                  on_tags=score_against_plain)
     norms, _ = ctx.constraints(Q, r_excise=0.5)
     lrn = dict(value=logl["cell_stages"] / logl["step_seconds"], ms_per_step=logl["step_seconds"] * 1e3 / args.steps,
                leaves_final=dynamic.levels(ctx), regrids=logl["regrids"],
