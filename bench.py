@@ -265,14 +265,22 @@ def run_gpu(args, w, precision, formulation=0, advection=0, total_steps=0, keep=
         graph.launch(stream)
         done += 1
     torch.cuda.synchronize()
+    # the timed steps in up to five equal repetitions, each bracketed by events on the launch stream
+    nrep = min(5, args.steps)
+    bounds = [round(r * args.steps / nrep) for r in range(nrep + 1)]
+    marks = {b: torch.cuda.Event(enable_timing=True) for b in bounds}
     t0 = time.perf_counter()
+    marks[0].record(stream)
     for i in range(args.steps):
         graph.launch(stream)
         done += 1
+        if i + 1 in marks:
+            marks[i + 1].record(stream)
         if args.progress:
             _say(f"graph step {i + 1}/{args.steps}")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    rep_ms = [marks[b0].elapsed_time(marks[b1]) / (b1 - b0) for b0, b1 in zip(bounds, bounds[1:]) if b1 > b0]
     while done < total_steps:  # untimed, up to the drift horizon
         graph.launch(stream)
         done += 1
@@ -318,7 +326,7 @@ def run_gpu(args, w, precision, formulation=0, advection=0, total_steps=0, keep=
         (" + k_rhs_sommerfeld" if nbf and not kc & ccz4.KERNEL_LDS else "")
     recon_ms = [a.elapsed_time(b) for a, b in recon_events]
     avg = lambda v: sum(v) / len(v)  # noqa: E731
-    out = dict(wall=wall, wall_eager=wall_eager, tune_ms=tune_ms, cells=cells, patches=ctx.n_patches, rhs_ms=rhs_ms,
+    out = dict(wall=wall, wall_eager=wall_eager, rep_ms=rep_ms, tune_ms=tune_ms, cells=cells, patches=ctx.n_patches, rhs_ms=rhs_ms,
                reconstruct_ms=avg(recon_ms) if recon_ms else None, stage_ms=avg(stage_ms),
                stage_ms_by_s=[avg([t for (s, _, _, _), t in zip(events, stage_ms) if s == q]) for q in range(4)],
                stage_bytes=avg(launch_bytes), halo_bytes=avg(halo_bytes), ghost_bytes=avg(ghost_bytes),
@@ -715,15 +723,16 @@ def _cpu_model():
 
 def cpu_baseline(w, target_s):
     """The oracle (plain C, as it stands; OpenMP over patches changes no arithmetic) on a bounded
-    piece of the workload: the 8^3-patch sub-box around the puncture at the workload's spacing
-    (512 patches, 373,248 cells).  All host threads: whole RK4 steps (per stage a fill of the
+    piece of the workload: the whole mesh up to 16^3 leaves, else the 8^3-patch sub-box around the
+    puncture at the workload's spacing (512 patches, 373,248 cells).  All host threads: whole RK4 steps (per stage a fill of the
     sub-box, the right-hand side of every patch and the stage combine) until target_s / 2 has
     passed.  One thread: one stage on a sample of patches sized to target_s / 2, the fill and
     combine pro-rated."""
     import numpy as np
     import oracle as orc
     from paper_2406_11626_amd import ccz4, scenarios
-    sw = scenarios.subbox(w) if not w.refined else w
+    # workloads of up to 16^3 leaves whole; larger uniform ones by the 8^3-leaf sub-box
+    sw = scenarios.subbox(w) if not w.refined and w.n0[0] * w.n0[1] * w.n0[2] > 4096 else w
     m = orc.Mesh(sw.n0, sw.origin, sw.extent, sw.bc, sw.refined)
     Q = m.zeros()
     m.init(Q, sw.scenario, sw.scen)
@@ -777,7 +786,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--drift-steps", type=int, default=50,
                     help="steps since the initial data after which the constraint norms are compared")
@@ -875,6 +884,8 @@ def main():
                            "copied; every halo copied at the last stage)",
                    "launch_config": r64["kernel"], "autotune": r64["tune_ms"]},
         "eager_ms_per_step": r64["wall_eager"] * 1e3 / args.steps,
+        "repetitions_ms_per_step": [round(x, 3) for x in r64["rep_ms"]],
+        "median_ms_per_step": float(sorted(r64["rep_ms"])[len(r64["rep_ms"]) // 2]),
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": r64["kernel"], "avg_ms": r64["stage_ms"], "avg_ms_by_stage": r64["stage_ms_by_s"],

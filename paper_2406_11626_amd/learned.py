@@ -98,13 +98,64 @@ def miss_rate(predicted, truth):
     return miss, extra
 
 
+def face_neighbours(ids, n0, periodic=False):
+    """Leaves sharing a face with each leaf of a 2:1-balanced forest (ids: (n, 4) rows of level,
+    i, j, k; n0: the level-0 cube counts): across each face, the leaf of the same level, else the
+    coarser leaf that contains that cube, else the finer leaves that touch the face.  A list of
+    index arrays."""
+    index = {tuple(int(v) for v in r): p for p, r in enumerate(ids)}
+    out = []
+    for me, (lev, i, j, k) in enumerate(tuple(int(v) for v in r) for r in ids):
+        size = [n0[a] * 3 ** lev for a in range(3)]
+        nb = set()
+        for a in range(3):
+            for side in (-1, 1):
+                c = [i, j, k]
+                c[a] += side
+                if not 0 <= c[a] < size[a]:
+                    if not periodic:
+                        continue
+                    c[a] %= size[a]
+                q = index.get((lev, *c))
+                if q is None and lev > 0:
+                    q = index.get((lev - 1, c[0] // 3, c[1] // 3, c[2] // 3))
+                if q is not None:
+                    if q != me:  # a periodic axis of one cube wraps onto the leaf itself
+                        nb.add(q)
+                    continue
+                others = [b for b in range(3) if b != a]
+                for u in range(3):  # the nine finer leaves across the face
+                    for v in range(3):
+                        f = [3 * c[0], 3 * c[1], 3 * c[2]]
+                        f[a] += 0 if side > 0 else 2
+                        f[others[0]] += u
+                        f[others[1]] += v
+                        q = index.get((lev + 1, *f))
+                        if q is not None:
+                            nb.add(q)
+        out.append(np.array(sorted(nb), dtype=np.int64))
+    return out
+
+
+def adjacent_fallback(comb, plain, neighbours):
+    """The combination with the plain criterion deciding on every leaf that shares a face with a
+    leaf it tags REFINE (the network's additions there are dropped)."""
+    c = comb.cpu().numpy().copy()
+    pl = plain.cpu().numpy()
+    near = np.array([bool(np.any(pl[nb] == 1)) if len(nb) else False for nb in neighbours])
+    c[near] = pl[near]
+    return c
+
+
 def anticipation(ind, ctx, snaps, conf=0.6, max_level=2):
     """Score of the indicator on consecutive snapshots [(feat, plain tags)]: for each pair (k, k+1)
     the tags at k are used as the prediction of the plain tags at k+1.  Returns the mean over
     pairs of (miss rate, extra REFINE tags) for the plain criterion alone, for the combination
-    with the network (ccz4_tag_learned) and for the network's arg-max alone."""
+    with the network (ccz4_tag_learned), for that combination with the plain criterion deciding
+    on every leaf next to a plain REFINE, and for the network's arg-max alone."""
     import torch
-    out = {"plain": [], "combined": [], "network": []}
+    out = {"plain": [], "combined": [], "combined_adjacent_fallback": [], "network": []}
+    neighbours = face_neighbours(ctx.ids, ctx.n0, ctx.bc == ccz4.BC_PERIODIC)
     for k in range(len(snaps) - 1):
         feat, plain = snaps[k]
         truth = snaps[k + 1][1]
@@ -113,5 +164,7 @@ def anticipation(ind, ctx, snaps, conf=0.6, max_level=2):
         net = (torch.argmax(logits, dim=1) - 1).to(torch.int8)
         out["plain"].append(miss_rate(plain, truth))
         out["combined"].append(miss_rate(comb, truth))
+        out["combined_adjacent_fallback"].append(
+            miss_rate(torch.from_numpy(adjacent_fallback(comb, plain, neighbours)), truth))
         out["network"].append(miss_rate(net, truth))
     return {k: tuple(np.mean(np.array(v, dtype=np.float64), axis=0)) for k, v in out.items()}
