@@ -859,13 +859,19 @@ int64_t orc_find_leaf(const orc_mesh *m, const double x[3])
     return -1;
 }
 
-/* trilinear weights: cell-centre coordinate u = (x - o)/dx - 1/2 in interior units */
+/* Trilinear interpolation (Sec. 3.8) at x: the weights come from the cell-centre coordinate
+   u = (x - o)/dx - 1/2 of the leaf holding x, in interior units.  Each of the eight cells is read
+   from the interior of the leaf that holds its centre when that leaf has the same level (so that
+   no value is taken from an edge or corner region of a halo, which no fill writes); a cell whose
+   centre lies outside the domain or in a leaf of another level is read from the holding leaf's
+   own box (its face halo, filled by the boundary or coarse-fine fill). */
 static int tracer_interp(const orc_mesh *m, const double *Q, const double x[3], int nslot, const int *slots,
                          double *out)
 {
     const int64_t p = orc_find_leaf(m, x);
     double org[3], dx[3], t[3];
-    int i0[3], a, s, cx, cy, cz;
+    int i0[3], a, s, c;
+    const double *cellv[8];
     if (p < 0) return 0;
     patch_geom(m, p, org, dx);
     for (a = 0; a < 3; a++) {
@@ -874,15 +880,30 @@ static int tracer_interp(const orc_mesh *m, const double *Q, const double x[3], 
         i0[a] = (int)f + HH; /* box index of the lower centre: 2..11 */
         t[a] = u - f;
     }
-    const double *box = Q + p * (int64_t)ORC_BOXCELLS * NV;
+    for (c = 0; c < 8; c++) {
+        const int b[3] = {i0[0] + (c & 1), i0[1] + ((c >> 1) & 1), i0[2] + ((c >> 2) & 1)};
+        int64_t q = p;
+        int bq[3] = {b[0], b[1], b[2]};
+        if (b[0] < HH || b[0] >= HH + PP || b[1] < HH || b[1] >= HH + PP || b[2] < HH || b[2] >= HH + PP) {
+            double xc[3], oq[3], dq[3];
+            for (a = 0; a < 3; a++) xc[a] = org[a] + ((double)(b[a] - HH) + 0.5) * dx[a];
+            q = orc_find_leaf(m, xc);
+            if (q >= 0 && m->id[4 * q] == m->id[4 * p]) {
+                patch_geom(m, q, oq, dq);
+                for (a = 0; a < 3; a++) bq[a] = (int)floor((xc[a] - oq[a]) / dq[a]) + HH;
+            } else {
+                q = p;
+            }
+        }
+        cellv[c] = Q + q * (int64_t)ORC_BOXCELLS * NV + cix(bq[0], bq[1], bq[2]) * NV;
+    }
     for (s = 0; s < nslot; s++) {
         double v = 0.0;
-        for (cz = 0; cz < 2; cz++)
-            for (cy = 0; cy < 2; cy++)
-                for (cx = 0; cx < 2; cx++) {
-                    const double w = (cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1]) * (cz ? t[2] : 1.0 - t[2]);
-                    v += w * box[cix(i0[0] + cx, i0[1] + cy, i0[2] + cz) * NV + slots[s]];
-                }
+        for (c = 0; c < 8; c++) {
+            const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+            const double w = (cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1]) * (cz ? t[2] : 1.0 - t[2]);
+            v += w * cellv[c][slots[s]];
+        }
         out[s] = v;
     }
     return 1;

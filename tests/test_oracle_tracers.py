@@ -55,6 +55,38 @@ def test_trilinear_exact_on_multilinear_fields():
     np.testing.assert_allclose(out[:, 0], f(pts[:, 0], pts[:, 1], pts[:, 2]), rtol=0, atol=1e-13)
 
 
+def test_trilinear_near_leaf_edges_reads_no_edge_or_corner_halo_cell():
+    """A fill writes face halos only.  Near an edge (two faces) or a corner (three faces) of a leaf
+    some of the eight cells lie in an edge or corner region of the leaf's halo; they must come
+    from the interiors of the same-level leaves that hold them.  With interiors set to a
+    multilinear field, every halo cell NaN before the fill, the samples at points within half a
+    cell of inner edges and corners are exact (a single NaN read would show)."""
+    m = orc.Mesh((3, 3, 3), (0.0, 0.0, 0.0), (3.0, 3.0, 3.0), 0)
+    rng = np.random.default_rng(7)
+    c = rng.normal(size=8)
+
+    def f(x, y, z):
+        return c[0] + c[1] * x + c[2] * y + c[3] * z + c[4] * x * y + c[5] * x * z + c[6] * y * z + c[7] * x * y * z
+
+    Q = fill_global(m, f, 9)
+    inner = np.zeros((15, 15, 15), bool)
+    inner[3:12, 3:12, 3:12] = True
+    Q[:, ~inner, :] = np.nan
+    m.fill_halos(Q)
+    assert np.isnan(Q[:, 1, 1, 5, 9]).all()  # an edge-region cell of every leaf stays unwritten
+    h = 0.5 / 9  # half a cell
+    pts = []
+    for _ in range(60):
+        e = rng.choice([1.0, 2.0], size=3) + rng.uniform(-h, h, size=3) * 0.999
+        free = rng.integers(0, 3)
+        e2 = e.copy()
+        e2[free] = rng.uniform(0.2, 2.8)  # near an edge: two coordinates at inner faces
+        pts += [e, e2]
+    pts = np.array(pts)
+    out = m.tracer_sample(Q, pts, [9])
+    np.testing.assert_allclose(out[:, 0], f(pts[:, 0], pts[:, 1], pts[:, 2]), rtol=0, atol=1e-12)
+
+
 def test_trilinear_error_closed_form_on_a_quadratic():
     """For f = x^2 the trilinear interpolant between centres x_i and x_i + h errs by exactly
     h^2 t (1 - t) at x = x_i + t h."""
