@@ -845,15 +845,28 @@ int orc_max_threads(void)
  * around it in the leaf that holds it; puncture trackers (Sec. 4.2.3) move with velocity -beta by
  * the explicit Euler rule x <- x + dt v.
  * ---------------------------------------------------------------------------------------- */
+/* The leaf holding x.  The point's cube at the mesh's finest level has the index
+   K = floor((x - origin) / edge) along each axis, and the leaf of level l holding x is the one
+   whose cube (l, i) satisfies i * 3^(L - l) <= K < (i + 1) * 3^(L - l), L the finest level.  One
+   rounded index serves every level, so the leaves tile the domain without gaps or overlaps even
+   for points within rounding of a face (testing x against each leaf's own floating-point box,
+   or flooring at each level separately, can leave such a point in no leaf). */
 int64_t orc_find_leaf(const orc_mesh *m, const double x[3])
 {
     int64_t p;
+    int a, top = 0;
+    double K[3];
+    for (p = 0; p < m->np; p++)
+        if (m->id[4 * p] > top) top = m->id[4 * p];
+    for (a = 0; a < 3; a++) K[a] = floor((x[a] - m->origin[a]) / (m->extent[a] / lev_n(m, top, a)));
     for (p = 0; p < m->np; p++) {
-        double org[3], dx[3];
-        int a, in = 1;
-        patch_geom(m, p, org, dx);
-        for (a = 0; a < 3; a++)
-            if (!(x[a] >= org[a] && x[a] < org[a] + PP * dx[a])) in = 0;
+        int in = 1, l;
+        double s = 1.0;
+        for (l = m->id[4 * p]; l < top; l++) s *= 3.0;
+        for (a = 0; a < 3 && in; a++) {
+            const double i = (double)m->id[4 * p + 1 + a];
+            if (!(K[a] >= i * s && K[a] < (i + 1.0) * s)) in = 0;
+        }
         if (in) return p;
     }
     return -1;

@@ -41,6 +41,35 @@ def test_find_leaf_matches_geometry():
     assert m.find_leaf(np.array([5.0, 0.0, 0.0])) == -1
 
 
+def test_find_leaf_leaves_no_gap_at_faces():
+    """Points on leaf faces and corners, and within rounding of them, lie in exactly one leaf:
+    the lookup compares integer cube indices, so the leaves tile the domain without the gaps that
+    a test against each leaf's own floating-point box can leave (a puncture tracker sitting at
+    z = -3e-26 next to the face z = 0 of a leaf of edge 0.5 fell into such a gap)."""
+    from paper_2406_11626_amd import scenarios
+    w = scenarios.binary_tracking([2.0])
+    m = orc.Mesh(w.n0, w.origin, w.extent, w.bc, w.refined)
+    x = np.array([3.0, 5.711970443685167e-10, -3.4465858856376157e-26])
+    p = m.find_leaf(x)
+    # x - origin rounds the offset away: the point belongs to the leaf above the face, and to one
+    assert p >= 0 and m.geom[p, 2] == 0.0
+    m = amr_mesh()
+    rng = np.random.default_rng(3)
+    corners = np.unique(np.concatenate([m.geom[:, :3], m.geom[:, :3] + 9 * m.geom[:, 3:]]), axis=0)
+    lo, hi = np.array([-1.0, -1.0, -0.5]), np.array([1.0, 1.0, 0.5])
+    for c in corners:
+        for _ in range(6):
+            x = c + rng.choice([-1e-300, 0.0, 1e-300, -1e-17, 1e-17], size=3)
+            p = m.find_leaf(x)
+            if np.all(x > lo + 1e-12) and np.all(x < hi - 1e-12):
+                assert p >= 0, x  # inner faces and corners: always in a leaf
+            elif np.any(x < lo - 1e-12) or np.any(x > hi + 1e-12):
+                assert p < 0, x
+            if p >= 0:
+                o, e = m.geom[p, :3], 9 * m.geom[p, 3:]
+                assert np.all(x >= o - 1e-12) and np.all(x <= o + e + 1e-12)
+
+
 def test_trilinear_exact_on_multilinear_fields():
     m = amr_mesh()
     rng = np.random.default_rng(1)
