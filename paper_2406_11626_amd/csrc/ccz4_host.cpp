@@ -662,6 +662,21 @@ ccz4_status ccz4_reconstruct_aux(ccz4_ctx *c, double *Q, int32_t flags, void *st
     return CCZ4_OK;
 }
 
+// The point lookup of the tracer kernel: the domain corner and the cube edge of the finest level
+// of the mesh (the edge as extent / (n0 * 3^top), the same rounded quotient as the leaf geometry's).
+static LeafLookup leaf_lookup(const ccz4_ctx *c)
+{
+    LeafLookup lk{};
+    for (const auto &l : c->leaf) lk.top = std::max(lk.top, (int32_t)l[0]);
+    int32_t f = 1;
+    for (int32_t l = 0; l < lk.top; ++l) f *= 3;
+    for (int a = 0; a < 3; ++a) {
+        lk.org[a] = c->origin[a];
+        lk.fine[a] = c->extent[a] / (double)(c->n0[a] * f);
+    }
+    return lk;
+}
+
 ccz4_status ccz4_tracers_sample(ccz4_ctx *c, const double *Q, int64_t n, const double *pos, int32_t nslots,
                                 const int32_t *slots, double *out, void *stream)
 {
@@ -678,8 +693,8 @@ ccz4_status ccz4_tracers_sample(ccz4_ctx *c, const double *Q, int64_t n, const d
         if (slots[s] < 0 || slots[s] >= NV) return fail(CCZ4_EINVAL, "slot out of range");
         sl.v[s] = slots[s];
     }
-    HIP_TRY(launch_tracers(Q, c->d_geom.p, (int32_t)c->leaf.size(), n, const_cast<double *>(pos), sl, out, 0.0, 0,
-                           S(stream)));
+    HIP_TRY(launch_tracers(Q, c->d_geom.p, (int32_t)c->leaf.size(), n, const_cast<double *>(pos), sl, leaf_lookup(c),
+                           out, 0.0, 0, S(stream)));
     return CCZ4_OK;
 }
 
@@ -694,7 +709,8 @@ ccz4_status ccz4_tracers_advance(ccz4_ctx *c, const double *Q, int64_t n, double
     if (!pos) return fail(CCZ4_EINVAL, "pos is NULL");
     TracerSlots sl;
     sl.n = 0;
-    HIP_TRY(launch_tracers(Q, c->d_geom.p, (int32_t)c->leaf.size(), n, pos, sl, nullptr, dt, 1, S(stream)));
+    HIP_TRY(launch_tracers(Q, c->d_geom.p, (int32_t)c->leaf.size(), n, pos, sl, leaf_lookup(c), nullptr, dt, 1,
+                           S(stream)));
     return CCZ4_OK;
 }
 

@@ -1230,57 +1230,107 @@ hipError_t launch_reconstruct(double *Q, const PatchGeom *geom, int32_t npatch, 
     return hipGetLastError();
 }
 
+// The cube index of coordinate v at the finest level, and whether leaf g (level l, lower corner
+// org + i * edge_l) holds that index: i * 3^(top - l) <= K < (i + 1) * 3^(top - l).  One rounded
+// index serves every level, so the leaves tile the domain without gaps or overlaps even for points
+// within rounding of a face.
+__device__ __forceinline__ double fine_index(const LeafLookup &lk, int a, double v)
+{
+    return floor((v - lk.org[a]) / lk.fine[a]);
+}
+__device__ __forceinline__ bool leaf_holds(const LeafLookup &lk, const PatchGeom &g, const double K[3])
+{
+    double s = 1.0;
+    for (int l = g.level; l < lk.top; ++l) s *= 3.0;
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double i = rint((g.org[a] - lk.org[a]) / (lk.fine[a] * s));
+        in = in && K[a] >= i * s && K[a] < (i + 1.0) * s;
+    }
+    return in;
+}
+
 // Tracers (Sec. 3.8): one work-group per point.  The lanes test a strided share of the leaves for
-// the one whose interior box [o, o + 9 dx) holds the point; then each of the requested slots is
-// the trilinear interpolation of the 2^3 cell centres around the point (box indices 2..12, the
-// leaf's filled halos supplying the outermost ones).  advance: the point moves by dt * (-beta)
+// the one holding the point (leaf_holds); the trilinear weights come from the 2^3 cell centres
+// around the point at that leaf's spacing.  A cell inside the leaf's interior is read there; a
+// cell outside it is read from the interior of the leaf of the same level that holds its centre
+// (a second strided search), so that no value comes from an edge or corner region of a halo,
+// which no fill writes; a cell whose centre is outside the domain or in a leaf of another level is
+// read from the leaf's own box (its face halo, filled by the boundary or coarse-fine fill).  Each
+// requested slot is then interpolated by one lane.  advance: the point moves by dt * (-beta)
 // (puncture tracker, explicit Euler).  A point outside every leaf samples NaN and stays.
 __global__ __launch_bounds__(256) void k_tracers(const double *__restrict__ Q, const PatchGeom *__restrict__ geom,
                                                  int32_t npatch, double *__restrict__ pos, TracerSlots sl,
-                                                 double *__restrict__ out, double dt, int32_t advance)
+                                                 LeafLookup lk, double *__restrict__ out, double dt,
+                                                 int32_t advance)
 {
     __shared__ int leaf;
+    __shared__ int owner[8];
     __shared__ double beta[3];
     const int64_t i = blockIdx.x;
     if (threadIdx.x == 0) leaf = -1;
+    if (threadIdx.x < 8) owner[threadIdx.x] = -1;
     __syncthreads();
     const double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
-    for (int p = (int)threadIdx.x; p < npatch; p += (int)blockDim.x) {
-        const PatchGeom g = geom[p];
-        bool in = true;
+    const double K[3] = {fine_index(lk, 0, x[0]), fine_index(lk, 1, x[1]), fine_index(lk, 2, x[2])};
+    for (int p = (int)threadIdx.x; p < npatch; p += (int)blockDim.x)
+        if (leaf_holds(lk, geom[p], K)) leaf = p;  // one leaf holds a point: one lane at most
+    __syncthreads();
+    const int p = leaf;  // uniform over the work-group
+    int i0[3] = {3, 3, 3};
+    double w[3] = {0.0, 0.0, 0.0};
+    PatchGeom gp{};
+    if (p >= 0) {
+        gp = geom[p];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) in = in && x[a] >= g.org[a] && x[a] < g.org[a] + 9.0 * g.dx[a];
-        if (in) leaf = p;  // leaves do not overlap: one lane at most
+        for (int a = 0; a < 3; ++a) {
+            const double u = (x[a] - gp.org[a]) / gp.dx[a] - 0.5;
+            const double f = floor(u);
+            i0[a] = (int)f + 3;  // box index of the lower centre: 2..11
+            w[a] = u - f;
+        }
+        // owners of the cells outside the leaf's interior (one leaf holds a centre: one lane each)
+        for (int q = (int)threadIdx.x; q < npatch; q += (int)blockDim.x) {
+            const PatchGeom g = geom[q];
+            if (q == p || g.level != gp.level) continue;
+            for (int c = 0; c < 8; ++c) {
+                const int b[3] = {i0[0] + (c & 1), i0[1] + ((c >> 1) & 1), i0[2] + ((c >> 2) & 1)};
+                if (b[0] >= 3 && b[0] <= 11 && b[1] >= 3 && b[1] <= 11 && b[2] >= 3 && b[2] <= 11) continue;
+                double Kc[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    Kc[a] = fine_index(lk, a, gp.org[a] + ((double)(b[a] - 3) + 0.5) * gp.dx[a]);
+                if (leaf_holds(lk, g, Kc)) owner[c] = q;
+            }
+        }
     }
     __syncthreads();
-    const int p = leaf;
     const int nout = advance ? 3 : sl.n;
     const int t = (int)threadIdx.x;
     if (t < nout) {
         const int v = advance ? SBETA + t : sl.v[t];
         double val = __builtin_nan("");
         if (p >= 0) {
-            const PatchGeom g = geom[p];
-            int i0[3];
-            double w[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double u = (x[a] - g.org[a]) / g.dx[a] - 0.5;
-                const double f = floor(u);
-                i0[a] = (int)f + 3;
-                w[a] = u - f;
-            }
-            const double *b = Q + (int64_t)p * PS + v * CS;
             val = 0.0;
 #pragma unroll
-            for (int cz = 0; cz < 2; ++cz)
+            for (int c = 0; c < 8; ++c) {
+                const int cx = c & 1, cy = (c >> 1) & 1, cz = (c >> 2) & 1;
+                int b[3] = {i0[0] + cx, i0[1] + cy, i0[2] + cz};
+                int q = owner[c];
+                if (q >= 0) {
+                    const PatchGeom g = geom[q];
 #pragma unroll
-                for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-                    for (int cx = 0; cx < 2; ++cx) {
-                        const double wt = (cx ? w[0] : 1.0 - w[0]) * (cy ? w[1] : 1.0 - w[1]) * (cz ? w[2] : 1.0 - w[2]);
-                        val += wt * b[boff(i0[0] + cx, i0[1] + cy, i0[2] + cz)];
+                    for (int a = 0; a < 3; ++a) {
+                        const double xc = gp.org[a] + ((double)(b[a] - 3) + 0.5) * gp.dx[a];
+                        b[a] = min(11, max(3, (int)floor((xc - g.org[a]) / g.dx[a]) + 3));
                     }
+                } else {
+                    q = p;
+                }
+                const double wt = (cx ? w[0] : 1.0 - w[0]) * (cy ? w[1] : 1.0 - w[1]) * (cz ? w[2] : 1.0 - w[2]);
+                val += wt * Q[(int64_t)q * PS + v * CS + boff(b[0], b[1], b[2])];
+            }
         }
         if (advance) beta[t] = val;
         else out[i * sl.n + t] = val;
@@ -1294,10 +1344,10 @@ __global__ __launch_bounds__(256) void k_tracers(const double *__restrict__ Q, c
 }
 
 hipError_t launch_tracers(const double *Q, const PatchGeom *geom, int32_t npatch, int64_t n, double *pos,
-                          const TracerSlots &sl, double *out, double dt, int32_t advance, hipStream_t st)
+                          const TracerSlots &sl, const LeafLookup &lk, double *out, double dt, int32_t advance, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tracers, dim3((unsigned)n), dim3(256), 0, st, Q, geom, npatch, pos, sl, out, dt, advance);
+    hipLaunchKernelGGL(k_tracers, dim3((unsigned)n), dim3(256), 0, st, Q, geom, npatch, pos, sl, lk, out, dt, advance);
     return hipGetLastError();
 }
 

@@ -38,7 +38,7 @@ hipError_t launch_regrid(const double *Qo, double *Qn, const RegridTask *tasks, 
 hipError_t launch_reconstruct(double *Q, const PatchGeom *geom, int32_t npatch, const int32_t *nbr, int32_t paxes,
                               const int32_t *gnbr, hipStream_t st);
 hipError_t launch_tracers(const double *Q, const PatchGeom *geom, int32_t npatch, int64_t n, double *pos,
-                          const TracerSlots &sl, double *out, double dt, int32_t advance, hipStream_t st);
+                          const TracerSlots &sl, const LeafLookup &lk, double *out, double dt, int32_t advance, hipStream_t st);
 hipError_t launch_tag_tracers(const TrackBox *box, int32_t npatch, int64_t n, const double *pos, const TrackRadii &R,
                               int32_t max_level, int8_t *tags, hipStream_t st);
 int64_t constraints_blocks(int32_t npatch);

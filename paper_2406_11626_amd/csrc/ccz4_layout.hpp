@@ -89,6 +89,15 @@ struct TracerSlots {
     int32_t v[NV];
 };
 
+// Leaf lookup of points: the domain's lower corner, the cube edge of the finest level present and
+// that level.  A point's cube index at the finest level, floor((x - org) / fine), decides the leaf
+// of every level (passed by value).
+struct LeafLookup {
+    double org[3];
+    double fine[3];
+    int32_t top, pad;
+};
+
 // Per-level radii of tracker-based refinement (passed by value)
 constexpr int MAX_TRACK_LEVELS = 16;
 struct TrackRadii {

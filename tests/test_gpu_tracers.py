@@ -60,6 +60,66 @@ def test_tracer_samples_match_oracle():
     assert np.abs(got[ok] - want[ok]).max() <= 1e-13 * np.abs(want[ok]).max()
 
 
+def test_tracer_samples_near_leaf_edges_match_oracle():
+    """Points within half a cell of inner leaf edges and corners, on a mesh with refined leaves,
+    interiors set to a multilinear field and every halo cell NaN before the fill (which writes
+    face halos only): the eight cells come from the same-level leaves that hold them, so samples
+    whose cells all have a same-level owner are exact, and the rest (next to coarse-fine edges)
+    read the face halo, or NaN from an unwritten edge region, exactly as the oracle does."""
+    ctx, m = pair()
+    rng = np.random.default_rng(11)
+    c = rng.normal(size=8)
+
+    def f(x, y, z):
+        return c[0] + c[1] * x + c[2] * y + c[3] * z + c[4] * x * y + c[5] * x * z + c[6] * y * z + c[7] * x * y * z
+
+    Q = m.zeros()
+    for p in range(m.np):
+        P = box_centers(m.geom[p, :3], m.geom[p, 3:])
+        Q[p, ..., 9] = f(P[..., 0], P[..., 1], P[..., 2])
+    inner = np.zeros((15, 15, 15), bool)
+    inner[3:12, 3:12, 3:12] = True
+    Q[:, ~inner, :] = np.nan
+    m.fill_halos(Q)
+    pts = []
+    h = 0.5 / 9  # half a level-0 cell
+    for _ in range(200):  # near the inner level-0 edges (x, y in {-0.5, 0.5}, z = 0) and around them
+        e = np.array([rng.choice([-0.5, 0.5]), rng.choice([-0.5, 0.5]), 0.0]) + rng.uniform(-h, h, 3) * 0.999
+        e[rng.integers(0, 3)] = rng.uniform(-1.4, 1.4) if rng.random() < 0.5 else e[0]
+        pts.append(e)
+    pts = np.array(pts)
+    want = m.tracer_sample(Q, pts, [9])
+    got = ctx.tracers_sample(to_gpu(Q), torch.tensor(pts, device="cuda"), [9]).cpu().numpy()
+    assert np.array_equal(np.isnan(got), np.isnan(want))
+    ok = ~np.isnan(want[:, 0])
+    assert ok.sum() > 100
+    assert np.abs(got[ok, 0] - want[ok, 0]).max() <= 1e-13 * np.abs(want[ok, 0]).max()
+    # where every cell has a level-0 owner the sample is the field itself
+    lev0 = np.array([m.ids[m.find_leaf(x), 0] == 0 for x in pts])
+    np.testing.assert_allclose(want[ok & lev0, 0], f(*pts[ok & lev0].T), rtol=0, atol=1e-12)
+
+
+def test_tracer_points_within_rounding_of_faces_match_oracle():
+    """Points on leaf faces and corners and within rounding of them (offsets down to subnormal)
+    are found in a leaf exactly where the oracle finds one: both take the point's cube index at
+    the finest level, so no point falls between two leaves."""
+    ctx, m = pair()
+    Qo = state(m, 72)
+    rng = np.random.default_rng(5)
+    corners = np.unique(np.concatenate([m.geom[:, :3], m.geom[:, :3] + 9 * m.geom[:, 3:]]), axis=0)
+    pts = np.array([c + rng.choice([-1e-300, 0.0, 1e-300, -1e-17, 1e-17, -3e-26], size=3)
+                    for c in corners for _ in range(3)])
+    slots = [7, 8, 9, 17]
+    want = m.tracer_sample(Qo, pts, slots)
+    got = ctx.tracers_sample(to_gpu(Qo), torch.tensor(pts, device="cuda"), slots).cpu().numpy()
+    assert np.array_equal(np.isnan(got), np.isnan(want))
+    ok = ~np.isnan(want)
+    inner = np.all(pts > np.array(ORIGIN) + 1e-12, axis=1) & np.all(pts < np.array(ORIGIN) + np.array(EXTENT) - 1e-12,
+                                                                     axis=1)
+    assert ok[inner].all()  # every point inside the domain is in a leaf
+    assert np.abs(got[ok] - want[ok]).max() <= 1e-13 * np.abs(want[ok]).max()
+
+
 def test_tracker_euler_steps_match_oracle():
     ctx, m = pair()
     Qo = state(m, 71)
