@@ -774,7 +774,8 @@ def cpu_baseline(w, target_s):
     t_one = t_rhs + (t_fill + t_stage) * n / m.np
     orc.set_threads(threads)
     return dict(value=all_rate, unit="cell-updates/s", cores=used, kind="oracle",
-                sample=f"{steps} RK4 steps (4 stages of fill + RHS + stage combine) of the {m.np}-patch sub-box "
+                sample=f"{steps} RK4 steps (4 stages of fill + RHS + stage combine) of the "
+                       f"{'whole ' + str(m.np) + '-patch mesh' if sw is w else str(m.np) + '-patch sub-box'} "
                        f"({cells} cells) {sw.name}, on {used} host threads: {t_all:.1f} s",
                 nproc=os.cpu_count(), cpu_model=_cpu_model(),
                 single_thread={"value": n * 729 / t_one, "unit": "cell-updates/s", "cores": 1,
