@@ -317,6 +317,29 @@ def run_gpu(args, w, precision, formulation=0, advection=0, total_steps=0, keep=
     halo_bytes = [HALO_BYTES_PER_FACE * pushed(fl) for s, _, _, fl in events]
     ghost_bytes = [GHOST_VECTORS[s] * 8 * NV * 243 * nbf for s, _, _, fl in events]
     norms, st = ctx.constraints(Q, r_excise=1.0)
+    monitor = None
+    if rhs and precision == ccz4.PREC_FP64 and not so:
+        # the other calls of the path on the final state, each timed with events on the stream:
+        # the constraint monitor (norms only), the plain refinement criterion (its indicator
+        # evaluates the constraints too) and the initial data (into the spent Q2)
+        tags = torch.empty(ctx.n_patches, dtype=torch.int8, device="cuda")
+
+        def timed(fn, reps=5):
+            fn()
+            ts = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                fn()
+                b.record(stream)
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(b))
+            return sorted(ts)[len(ts) // 2]
+        monitor = {"constraints_ms": timed(lambda: ctx.constraints(Q, None, 1.0, stream)),
+                   "tag_refine_ms": timed(lambda: ctx.tag_refine(Q, 1e300, -1.0, 2, tags, stream=stream)),
+                   "init_patches_ms": timed(lambda: ctx.init_patches(Q2, w.scenario, w.scen, stream)),
+                   "cells": ctx.n_patches * 729, "timing": "median of 5 calls, HIP events on the stream"}
+        del tags
     kc = ctx.get_kernel(precision)
     targs = ("<double, " if precision == ccz4.PREC_FP64 else "<float, ") + ("1>" if advection else "0>")
     border = " (" + ccz4.kernel_config_name(kc).split("/", 1)[1] + ")"
@@ -326,7 +349,7 @@ def run_gpu(args, w, precision, formulation=0, advection=0, total_steps=0, keep=
         (" + k_rhs_sommerfeld" if nbf and not kc & ccz4.KERNEL_LDS else "")
     recon_ms = [a.elapsed_time(b) for a, b in recon_events]
     avg = lambda v: sum(v) / len(v)  # noqa: E731
-    out = dict(wall=wall, wall_eager=wall_eager, rep_ms=rep_ms, tune_ms=tune_ms, cells=cells, patches=ctx.n_patches, rhs_ms=rhs_ms,
+    out = dict(wall=wall, wall_eager=wall_eager, rep_ms=rep_ms, tune_ms=tune_ms, monitor=monitor, cells=cells, patches=ctx.n_patches, rhs_ms=rhs_ms,
                reconstruct_ms=avg(recon_ms) if recon_ms else None, stage_ms=avg(stage_ms),
                stage_ms_by_s=[avg([t for (s, _, _, _), t in zip(events, stage_ms) if s == q]) for q in range(4)],
                stage_bytes=avg(launch_bytes), halo_bytes=avg(halo_bytes), ghost_bytes=avg(ghost_bytes),
@@ -911,6 +934,8 @@ def main():
                               "frac_ideal_bytes": RHS_IDEAL_BYTES_PER_CELL * r64["cells"] /
                               (r64["rhs_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                               "fp64": fp64_rate(ops_rhs, r64["rhs_ms"])}
+    if r64.get("monitor"):
+        line["monitor_calls"] = r64["monitor"]
     Q64 = r64.pop("Q", None)
     if not args.no_mixed:
         _say("mixed-precision fused step")
