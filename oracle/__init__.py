@@ -278,7 +278,8 @@ class Mesh:
         _mesh_geom(self._h, self.geom)
 
     def __del__(self):
-        if getattr(self, "_h", None):
+        # at interpreter shutdown the module's globals may already be gone: the process frees all
+        if getattr(self, "_h", None) and _mesh_destroy is not None:
             _mesh_destroy(self._h)
             self._h = None
 
