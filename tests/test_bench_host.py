@@ -116,7 +116,9 @@ def test_committed_profiles_parse():
     assert files
     for path, keys in files:
         rec = {}
-        for ln in open(path):
+        with open(path) as fh:
+            lines = fh.read().splitlines()
+        for ln in lines:
             if ln.startswith("- ") and ":" in ln:
                 k, v = ln[2:].split(":", 1)
                 rec[k.strip()] = v.strip()

@@ -19,7 +19,9 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "app
 
 def load_matrices():
     mats, cur = {}, None
-    for ln in open(GOLDEN):
+    with open(GOLDEN) as fh:
+        lines = fh.read().splitlines()
+    for ln in lines:
         ln = ln.strip()
         if not ln or ln.startswith("#"):
             continue
