@@ -11,7 +11,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 import oracle as orc  # noqa: E402
-from gpu_helpers import INTERIOR, SLABS, oracle_sensitivity, parity_error, same_level_halo_mask, to_gpu, to_host  # noqa: E402
+from gpu_helpers import (INTERIOR, SLABS, oracle_sensitivity, parity_error, same_level_halo_mask,  # noqa: E402
+                         sensitivity, to_gpu, to_host, ulp_perturbed)
 from paper_2406_11626_amd import ccz4, scenarios  # noqa: E402
 from seeded_inputs import box_centers, smooth_state  # noqa: E402
 
@@ -214,6 +215,69 @@ def test_so_step_graph_matches_oracle():
     _, _, g, Qo, sens = _so_steps(w, (2, 2, 2), so_params(w), steps=2, perturb=True, graph=True)
     e = parity_error(g, Qo, sens=sens, tol=1e-11)
     assert e.max() <= 1e-11, (e.argmax(), e.max())
+
+
+def test_full_size_so_step_graph_config4_sampled():
+    """The second-order formulation on the full 24^3-leaf puncture mesh, one captured RK4 step
+    (with its reconstructions) in the benchmark's launch configuration, against the oracle on
+    sampled leaves.  Each sampled leaf is stepped on an oracle sub-box of the leaves within three
+    of it: per stage the stencils reach 3 cells and the reconstruction 2 more, so one step and the
+    initial reconstruction reach 22 cells, less than the 27 of three leaves.  The sub-boxes'
+    initial data (bit-identical geometry) are uploaded into the GPU state before the
+    reconstruction, so that both sides start from the same values wherever the step can look."""
+    w = scenarios.config(4)
+    prm = so_params(w)
+    ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, prm, w.refined)
+    index = {tuple(r[1:]): p for p, r in enumerate(ctx.ids)}
+    samples = [(0, 0, 0), (0, 12, 23), (12, 12, 12)]  # a corner, a boundary face and edge, the puncture
+    L = w.extent[0] / w.n0[0]
+    Qd = ctx.new_state(0.0)
+    ctx.init_patches(Qd, w.scenario, w.scen)
+    subs = []
+    for ijk in samples:
+        lo = [max(0, c - 3) for c in ijk]
+        n = [min(w.n0[a] - 1, ijk[a] + 3) - lo[a] + 1 for a in range(3)]
+        m = orc.Mesh(tuple(n), tuple(w.origin[a] + lo[a] * L for a in range(3)), tuple(n[a] * L for a in range(3)), w.bc)
+        Q = m.zeros()
+        m.init(Q, w.scenario, w.scen)
+        full = [index[(r[1] + lo[0], r[2] + lo[1], r[3] + lo[2])] for r in m.ids]
+        np.testing.assert_array_equal(ctx.geom[full], m.geom)
+        Qd[torch.tensor(full, device="cuda")] = to_gpu(Q)
+        here = [q for q, r in enumerate(m.ids) if (r[1] + lo[0], r[2] + lo[1], r[3] + lo[2]) == ijk][0]
+        subs.append((m, Q, here, index[ijk]))
+    ctx.set_background(Qd)
+    ctx.fill_halos(Qd)
+    ctx.reconstruct(Qd, True)
+    ctx.fill_halos(Qd)
+    ctx.autotune(Qd, reps=1)
+    ctx.fill_halos(Qd)
+    dt = w.dt()
+    bufs = (ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0))
+    g = ctx.step_graph(Qd, bufs, dt)
+    g.launch()
+    torch.cuda.synchronize()
+    g.close()
+    del bufs
+    got = to_host(Qd, [s_[3] for s_ in subs])
+    del Qd
+    torch.cuda.empty_cache()
+    pr = oparams(prm)
+    for k, (m, Q, here, _) in enumerate(subs):
+        m.set_background(Q)
+        m.fill_halos(Q)
+        m.reconstruct(Q)
+        m.fill_halos(Q)
+
+        def run(Q0, m=m):
+            return m.rk4_step(pr, Q0, dt)
+        ref = run(Q.copy())
+        r1, g1 = ref[here:here + 1], got[k:k + 1]
+        e = parity_error(g1, r1)
+        if e.max() > 1e-11:  # a cancellation residual: the oracle's own one-ulp sensitivity decides
+            runs = [run(np.where(Q == 0.0, Q, ulp_perturbed(Q, 1234 + t))) for t in range(2)]
+            e = parity_error(g1, r1, sens=sensitivity(r1, [r_[here:here + 1] for r_ in runs]), tol=1e-11)
+        assert e.max() <= 1e-11, (samples[k], e.argmax(), e.max())
+        assert np.abs(r1[:, 3:12, 3:12, 3:12] - Q[here:here + 1, 3:12, 3:12, 3:12]).max() > 1e-10
 
 
 def test_reconstruct_rejects_bad_arguments():
