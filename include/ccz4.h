@@ -221,11 +221,15 @@ ccz4_status ccz4_step_stage_flags(ccz4_ctx *ctx, int32_t precision, int32_t s, i
 ccz4_status ccz4_reconstruct_aux(ccz4_ctx *ctx, double *Q, int32_t flags, void *stream);
 
 /* Tracers (Sec. 3.8, data probes).  For each of n points pos[n][3] (device, float64), the leaf
-   whose interior box [o, o + 9 dx) holds it, then for each of the nslots slots (host array, values
-   0..58) the trilinear interpolation of the 2^3 cell centres around the point; the leaf's halos
-   supply the centres beyond its interior, so Q's halos must be filled.  out[n][nslots] (device).
-   A point outside every leaf samples NaN.  n = 0 does nothing.  EINVAL on NULL pointers, n < 0,
-   nslots outside 1..59 or a slot outside 0..58. */
+   that holds it (the leaf whose cube contains the point's cube at the finest level, that cube's
+   index being floor((x - origin) / edge): every point of the domain is in exactly one leaf), then
+   for each of the nslots slots (host array, values 0..58) the trilinear interpolation of the 2^3
+   cell centres around the point at that leaf's spacing.  A centre outside the leaf's interior is
+   read from the interior of the same-level leaf that holds it, else (outside the domain, or in a
+   leaf of another level) from the leaf's face halo, so Q's halos must be filled (edge and corner
+   regions of halos are never read).  out[n][nslots] (device).  A point outside the domain samples
+   NaN.  n = 0 does nothing.  EINVAL on NULL pointers, n < 0, nslots outside 1..59 or a slot
+   outside 0..58. */
 ccz4_status ccz4_tracers_sample(ccz4_ctx *ctx, const double *Q, int64_t n, const double *pos, int32_t nslots,
                                 const int32_t *slots, double *out, void *stream);
 
