@@ -203,10 +203,8 @@ def run_gpu(args, w, precision, formulation=0, advection=0, total_steps=0, keep=
     so = ctx.second_order
     Q = ctx.new_state(0.0)
     ctx.init_patches(Q, w.scenario, w.scen)
-    Q1, Q2, acc = ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0)
     dt = w.dt()
     stream = torch.cuda.current_stream()
-    order = ((Q, Q1), (Q1, Q2), (Q2, Q1), (Q1, Q))
     rest = ccz4.FILL_NEUMANN | ccz4.FILL_LEVELS
     events, recon_events = [], []
     ctx.fill_halos(Q, stream)
@@ -220,6 +218,18 @@ def run_gpu(args, w, precision, formulation=0, advection=0, total_steps=0, keep=
         tune_ms = {"chosen": ccz4.kernel_config_name(ctx.get_kernel(precision)),
                    "ms": {ccz4.kernel_config_name(k): t for k, t in enumerate(ms)}}
     ctx.fill_halos(Q, stream)
+    # the work buffers: a pool of five, the rotation with the fastest steps kept (the placement of
+    # the buffers in physical memory moves a step by up to 8%); the trial steps advance Q
+    done = 0
+    place = None
+    if args.place:
+        (Q1, Q2, acc), pms = ctx.tune_step_buffers(Q, dt, precision, pool=5, steps=2, stream=stream)
+        done += 10
+        place = {"pool": 5, "steps_per_trial": 2, "ms_per_step": [round(x, 2) for x in pms],
+                 "chosen": int(min(range(5), key=lambda i: pms[i]))}
+    else:
+        Q1, Q2, acc = ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0)
+    order = ((Q, Q1), (Q1, Q2), (Q2, Q1), (Q1, Q))
 
     def step(timed):
         for s, (src, dst) in enumerate(order):
@@ -246,7 +256,6 @@ def run_gpu(args, w, precision, formulation=0, advection=0, total_steps=0, keep=
                     recon_events.append((r0, r1))
         ctx.fill_halos_kinds(Q, rest, stream)
 
-    done = 0
     for _ in range(args.warmup):
         step(False)
         done += 1
@@ -349,7 +358,7 @@ def run_gpu(args, w, precision, formulation=0, advection=0, total_steps=0, keep=
         (" + k_rhs_sommerfeld" if nbf and not kc & ccz4.KERNEL_LDS else "")
     recon_ms = [a.elapsed_time(b) for a, b in recon_events]
     avg = lambda v: sum(v) / len(v)  # noqa: E731
-    out = dict(wall=wall, wall_eager=wall_eager, rep_ms=rep_ms, tune_ms=tune_ms, monitor=monitor, cells=cells, patches=ctx.n_patches, rhs_ms=rhs_ms,
+    out = dict(wall=wall, wall_eager=wall_eager, rep_ms=rep_ms, tune_ms=tune_ms, monitor=monitor, place=place, cells=cells, patches=ctx.n_patches, rhs_ms=rhs_ms,
                reconstruct_ms=avg(recon_ms) if recon_ms else None, stage_ms=avg(stage_ms),
                stage_ms_by_s=[avg([t for (s, _, _, _), t in zip(events, stage_ms) if s == q]) for q in range(4)],
                stage_bytes=avg(launch_bytes), halo_bytes=avg(halo_bytes), ghost_bytes=avg(ghost_bytes),
@@ -372,10 +381,39 @@ def run_plain(args, w, total_steps=0, keep=False):
     ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, w.params(), w.refined)
     Q = ctx.new_state(0.0)
     ctx.init_patches(Q, w.scenario, w.scen)
-    Qs, k, acc = ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0)
     dt = w.dt()
     stream = torch.cuda.current_stream()
     ev = {"fill": [], "rhs": [], "rk4_stage": []}
+    done = 0
+
+    def plain_step(Qs, k, acc):
+        cur = Q
+        for s in range(4):
+            nxt = Q if s == 3 else Qs
+            ctx.fill_halos(cur, stream)
+            ctx.rhs(cur, k, ccz4.PREC_FP64, stream)
+            ctx.rk4_stage(s, dt, Q, k, acc, nxt, stream)
+            cur = nxt
+    # the work buffers chosen from a pool of five as for the fused path (same rule, same cost)
+    place = None
+    if args.place:
+        pool = [ctx.new_state(0.0) for _ in range(5)]
+        pms = []
+        for i in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(2):
+                plain_step(pool[i], pool[(i + 1) % 5], pool[(i + 2) % 5])
+            e1.record(stream)
+            e1.synchronize()
+            pms.append(e0.elapsed_time(e1) / 2)
+        done += 10
+        b = min(range(5), key=lambda i: pms[i])
+        Qs, k, acc = pool[b], pool[(b + 1) % 5], pool[(b + 2) % 5]
+        del pool
+        place = {"pool": 5, "steps_per_trial": 2, "ms_per_step": [round(x, 2) for x in pms], "chosen": b}
+    else:
+        Qs, k, acc = ctx.new_state(0.0), ctx.new_state(0.0), ctx.new_state(0.0)
 
     def timed(name, fn):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -398,7 +436,6 @@ def run_plain(args, w, total_steps=0, keep=False):
                 ctx.rk4_stage(s, dt, Q, k, acc, nxt, stream)
             cur = nxt
 
-    done = 0
     for _ in range(args.warmup):
         step(False)
         done += 1
@@ -421,7 +458,7 @@ def run_plain(args, w, total_steps=0, keep=False):
     ctx.fill_halos(Q, stream)
     norms, _ = ctx.constraints(Q, r_excise=1.0)
     ms = {n: sum(a.elapsed_time(b) for a, b in v) / len(v) for n, v in ev.items()}
-    out = dict(wall=wall, cells=ctx.n_patches * 729, norms=norms, steps_total=done, call_ms=ms)
+    out = dict(wall=wall, cells=ctx.n_patches * 729, norms=norms, steps_total=done, call_ms=ms, place=place)
     if keep:
         out["Q"] = Q
     del Q, Qs, k, acc
@@ -836,6 +873,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference kernel for the HBM byte counters)")
+    ap.add_argument("--no-place", dest="place", action="store_false",
+                    help="allocate the step's work buffers once instead of choosing among a pool")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the default launch configuration instead of timing the candidates first")
     ap.add_argument("--progress", action="store_true")
@@ -906,7 +945,7 @@ def main():
                    "stages_per_step": 4, "dt": w.dt(), "precision": "fp64",
                    "step": "HIP graph of 4 fused stages (y/z halos read from the neighbours, x-face halos "
                            "copied; every halo copied at the last stage)",
-                   "launch_config": r64["kernel"], "autotune": r64["tune_ms"]},
+                   "launch_config": r64["kernel"], "autotune": r64["tune_ms"], "placement": r64["place"]},
         "eager_ms_per_step": r64["wall_eager"] * 1e3 / args.steps,
         "repetitions_ms_per_step": [round(x, 3) for x in r64["rep_ms"]],
         "median_ms_per_step": float(sorted(r64["rep_ms"])[len(r64["rep_ms"]) // 2]),
@@ -946,7 +985,7 @@ def main():
         del Qm
         torch.cuda.empty_cache()
         line["mixed"] = {"value": vm, "ms_per_step": rm["wall"] * 1e3 / args.steps, "stage_avg_ms": rm["stage_ms"],
-                         "kernel": rm["kernel"], "speedup_vs_fp64": vm / value,
+                         "kernel": rm["kernel"], "speedup_vs_fp64": vm / value, "placement": rm["place"],
                          "L2_H": rm["norms"][0], "L2_M": rm["norms"][1], "steps": rm["steps_total"],
                          "dL2_H_rel": abs(rm["norms"][0] - l2h) / l2h if l2h else None,
                          "equal_constraint_violation": abs(rm["norms"][0] - l2h) <= 0.01 * l2h,
@@ -966,6 +1005,7 @@ def main():
         line["plain_fp64"] = {"value": vp, "ms_per_step": rp["wall"] * 1e3 / args.steps,
                               "call_ms": rp["call_ms"], "L2_H": lp, "L2_M": rp["norms"][1], "steps": rp["steps_total"],
                               "path": "per stage: ccz4_fill_halos, ccz4_rhs, ccz4_rk4_stage (eager launches)",
+                              "placement": rp["place"],
                               "state_error_vs_fused": {"max": emax, "slot": kmax},
                               "speedup_fused_fp64_over_plain": value / vp,
                               "speedup_mixed_over_plain": line["mixed"]["value"] / vp if "mixed" in line else None,

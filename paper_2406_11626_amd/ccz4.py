@@ -540,6 +540,32 @@ class Context:
         if push:
             self.fill_halos_kinds(Qn, rest, stream)
 
+    def tune_step_buffers(self, Qn, dt, precision=PREC_FP64, pool=5, steps=2, stream=None):
+        """Work buffers (Q1, Q2, acc) for fused steps on Qn, chosen for their place in memory.
+        The same step runs up to about 8% faster or slower depending on where the driver places
+        the state buffers in physical memory, and on which buffer plays which role.  This allocates
+        `pool` state buffers, times `steps` fused steps on Qn with each of the `pool` rotations
+        (i, i+1, i+2) of them in the three roles, keeps the fastest and frees the others.  Qn is
+        advanced by pool * steps RK4 steps: it must enter with its halos filled, and leaves with
+        them filled.  Returns ((Q1, Q2, acc), step times in ms per rotation)."""
+        import torch
+        st = stream if stream is not None else torch.cuda.current_stream()
+        bufs = [self.new_state(0.0) for _ in range(pool)]
+        ms = []
+        for i in range(pool):
+            trio = (bufs[i], bufs[(i + 1) % pool], bufs[(i + 2) % pool])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(steps):
+                self.rk4_step_fused(Qn, dt, trio, precision, st)
+            e1.record(st)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1) / steps)
+        best = min(range(pool), key=lambda i: ms[i])
+        keep = (bufs[best], bufs[(best + 1) % pool], bufs[(best + 2) % pool])
+        del bufs
+        return keep, ms
+
     def rk4_step(self, Qn, dt, bufs, precision=PREC_FP64, stream=None):
         """One RK4 step in place on Qn; bufs = (Qs, k, acc) work tensors of the state shape."""
         Qs, k, acc = bufs
