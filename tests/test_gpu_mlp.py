@@ -81,6 +81,21 @@ def test_forward_parity(n):
     assert rel(logits.cpu().numpy(), zo) <= 2e-3, rel(logits.cpu().numpy(), zo)
 
 
+def test_empty_batch():
+    """No rows: the forward pass writes nothing and needs no workspace; a gradient over no rows
+    (a mean over an empty set) is refused."""
+    prm, feat, norm, tags = mlp_inputs(64, 7)
+    logits = torch.full((1, 3), 5.0, dtype=torch.float32, device="cuda")
+    ccz4.ccz4_mlp_forward(dev(prm), dev(norm), dev(feat), 0, logits)
+    torch.cuda.synchronize()
+    assert torch.all(logits == 5.0)
+    assert ccz4.ccz4_mlp_workspace(0) == 0
+    work = torch.empty(ccz4.ccz4_mlp_workspace(64), dtype=torch.float32, device="cuda")
+    grad = torch.empty(ccz4.MLP_NPARAM, dtype=torch.float32, device="cuda")
+    with pytest.raises(ccz4.CCZ4Error):
+        ccz4.ccz4_mlp_grad(dev(prm), dev(norm), dev(feat), dev(tags), 0, work, grad)
+
+
 @pytest.mark.parametrize("n", [64, 331])
 def test_gradient_parity(n):
     prm, feat, norm, tags = mlp_inputs(n, 20 + n)

@@ -152,6 +152,28 @@ def test_tracker_tags_match_oracle(seed):
         assert (got == 1).any() or (got == -1).any()
 
 
+def test_empty_tracer_set():
+    """No tracers: sampling and advancing return at once and leave their buffers as they were, and
+    the tags by coordinates of an empty set are the oracle's: no leaf lies near a tracer, so every
+    leaf above the base level has its parent cube far from all of them (COARSEN) and the base
+    level keeps (KEEP)."""
+    radii = [0.8, 0.3]
+    ref = scenarios.sphere_refinement(N0, ORIGIN, EXTENT, [(0.2, -0.1, 0.05)], radii)
+    ctx, m = pair(ref)
+    Q = ctx.new_state(0.0)
+    pos = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    out = torch.full((1, 2), 7.0, dtype=torch.float64, device="cuda")
+    ccz4.ccz4_tracers_sample(ctx.h, Q, pos, [0, 1], out)
+    ccz4.ccz4_tracers_advance(ctx.h, Q, pos, 0.1)
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0)
+    want = m.tag_tracers(np.zeros((0, 3)), radii, 2)
+    got = ctx.tag_tracers(pos, radii, 2).cpu().numpy()
+    assert np.array_equal(got, want)
+    lev = np.asarray(ctx.ids)[:, 0]
+    assert (lev >= 1).any() and np.all(got[lev >= 1] == -1) and np.all(got[lev == 0] == 0)
+
+
 def test_tracer_arguments_are_checked():
     ctx, _ = pair()
     Q = ctx.new_state(0.0)
