@@ -11,9 +11,10 @@ time, with the state resident in HBM.
 
 Beside the FP64 graph step (the headline `value`) the line carries: the mixed-precision step and
 its state error against the FP64 step after the same number of steps (the FP64 GPU step is held
-to the oracle by the parity tests), the constraint norms of both over 50 steps, the plain
-unfused path (halo fill, right-hand side, RK4 stage as three calls per stage) timed on the same
-workload, the standalone right-hand-side kernel, and the oracle on the host cores.
+to the oracle by the parity tests), the constraint norms of both after at least 50 steps (every leg
+runs the same number), the plain unfused path (halo fill, right-hand side, RK4 stage as three
+calls per stage) timed on the same workload, the standalone right-hand-side kernel, and the oracle
+on the host cores.
 
 The roofline object is the fused stage kernel's: 3304 algorithmic bytes per cell-stage (every
 evolved slot with its three-cell face halos read once, Q^n and the accumulator read, the
