@@ -435,13 +435,14 @@ def nonzero_perturbed_runs(fn, Q, trials=2, seed=1234):
     return [fn(np.where(Q == 0.0, Q, ulp_perturbed(Q, seed + t))) for t in range(trials)]
 
 
-def _full_size_config4_step(samples, precision):
+def _full_size_config4_step(samples, precision, advection=0):
     """One captured RK4 step of the 24^3-leaf puncture in the benchmark's launch configuration for
     the precision; returns the GPU's sampled leaves after the step, per sample the oracle sub-box
     (mesh, initial state, index of the sampled leaf), and each slot's largest magnitude over the
     interiors of the whole mesh after the step."""
     w = scenarios.config(4)
-    ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, w.params(), w.refined)
+    prm = ccz4.params(**{**w.prm, "advection": advection})
+    ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, prm, w.refined)
     assert ctx.n_patches == 13824
     index = {tuple(r[1:]): p for p, r in enumerate(ctx.ids)}
     Qd = ctx.new_state(0.0)
@@ -468,7 +469,7 @@ def _full_size_config4_step(samples, precision):
     mesh_scale = np.array([float(Qd[:, v, 3:12, 3:12, 3:12].abs().max()) for v in range(ccz4.NV)])
     del Qd
     torch.cuda.empty_cache()
-    return w, got, [s[:3] for s in subs], mesh_scale
+    return w, prm, got, [s[:3] for s in subs], mesh_scale
 
 
 def _domain_ghost_mask(w, ijk):
@@ -483,18 +484,12 @@ def _domain_ghost_mask(w, ijk):
     return bm
 
 
-def test_full_size_step_graph_config4_sampled():
-    """The single puncture on its full 24^3-leaf mesh (13,824 leaves, 23.5 GB per state), one RK4
-    step in the launch configuration of the benchmark (autotuned stage kernel, block and leaf
-    order, the step's halo flags, the captured step graph), against the oracle on sampled leaves.
-    The oracle cannot step the whole mesh in a test, so each sampled leaf is stepped on an oracle
-    sub-box of the leaves around it; the sub-box's initial data (bit-identical geometry) are
-    uploaded into the GPU state, so that both sides start from the same values wherever the
-    sampled leaf's step can look.  Samples: the two domain corners, the leaves at the puncture,
-    a boundary face and edge leaf, an interior leaf."""
-    samples = [(0, 0, 0), (23, 23, 23), (11, 11, 11), (12, 12, 12), (0, 12, 23), (5, 17, 9)]
-    w, got, subs, _ = _full_size_config4_step(samples, ccz4.PREC_FP64)
-    pr = oparams(w.params())
+def _check_full_size_fp64(samples, advection=0):
+    """The FP64 step of _full_size_config4_step against the oracle on the sampled leaves: interior
+    and Sommerfeld ghost slabs at 1e-11 (cancellation residuals: four times the oracle's one-ulp
+    sensitivity)."""
+    w, prm, got, subs, _ = _full_size_config4_step(samples, ccz4.PREC_FP64, advection)
+    pr = oparams(prm)
     dt = w.dt()
     for n, (m, Q, here) in enumerate(subs):
         m.set_background(Q)
@@ -524,6 +519,24 @@ def test_full_size_step_graph_config4_sampled():
         assert np.abs(r1[:, 3:12, 3:12, 3:12] - Q0[here:here + 1, 3:12, 3:12, 3:12]).max() > 1e-10
 
 
+def test_full_size_step_graph_config4_sampled():
+    """The single puncture on its full 24^3-leaf mesh (13,824 leaves, 23.5 GB per state), one RK4
+    step in the launch configuration of the benchmark (autotuned stage kernel, block and leaf
+    order, the step's halo flags, the captured step graph), against the oracle on sampled leaves.
+    The oracle cannot step the whole mesh in a test, so each sampled leaf is stepped on an oracle
+    sub-box of the leaves around it; the sub-box's initial data (bit-identical geometry) are
+    uploaded into the GPU state, so that both sides start from the same values wherever the
+    sampled leaf's step can look.  Samples: the two domain corners, the leaves at the puncture,
+    a boundary face and edge leaf, an interior leaf."""
+    _check_full_size_fp64([(0, 0, 0), (23, 23, 23), (11, 11, 11), (12, 12, 12), (0, 12, 23), (5, 17, 9)])
+
+
+def test_full_size_lopsided_step_graph_config4_sampled():
+    """The same full-size check with lopsided advection (the upwind pairing of App. D's stencils,
+    the benchmark's lopsided leg): a domain corner, the leaf at the puncture, an interior leaf."""
+    _check_full_size_fp64([(0, 0, 0), (12, 12, 12), (5, 17, 9)], advection=1)
+
+
 # Mixed precision at the benchmark's resolution (dx = 1/12): the cells next to the puncture carry
 # terms in the right-hand sides of K, D and Theta that exceed those slots' sizes on the mesh far
 # more than on the coarse test meshes, and the FP32 rounding of those terms is what the mixed state
@@ -546,10 +559,10 @@ def test_full_size_mixed_precision_step_graph_config4_sampled():
     the puncture to the bound stated for it at this resolution."""
     samples = [(0, 0, 0), (12, 12, 12), (5, 17, 9)]
     bounds = [MIXED_BOUND, MIXED_BOUND_PUNCTURE, MIXED_BOUND]
-    w, got, subs, mesh_scale = _full_size_config4_step(samples, ccz4.PREC_MIXED)
+    w, prm, got, subs, mesh_scale = _full_size_config4_step(samples, ccz4.PREC_MIXED)
     top = mesh_scale.max()
     scale = np.where(mesh_scale > FLOOR * top, mesh_scale, top)
-    pr = oparams(w.params())
+    pr = oparams(prm)
     worst = 0.0
     for n, (m, Q, here) in enumerate(subs):
         m.set_background(Q)
