@@ -249,6 +249,42 @@ def test_constraints_parity_and_norms():
     assert st == ccz4.CCZ4_ENONFINITE and norms_d[2] >= 1
 
 
+def test_full_size_constraints_config4_sampled():
+    """The constraint monitor's launch over the full 24^3-leaf puncture (13,824 leaves): H and M_i
+    of sampled leaves against the oracle on sub-boxes of the leaves around each (the sub-boxes'
+    initial data uploaded into the GPU state, so that both sides read the same values), each
+    quantity measured against its largest magnitude over the mesh, as the small-mesh test measures
+    it over its whole mesh.  Samples: a domain corner, the two leaves that meet at the puncture
+    diagonally, an interior leaf."""
+    w = scenarios.config(4)
+    ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, w.params(), w.refined)
+    index = {tuple(r[1:]): p for p, r in enumerate(ctx.ids)}
+    Qd = ctx.new_state(0.0)
+    ctx.init_patches(Qd, w.scenario, w.scen)
+    samples = [(0, 0, 0), (11, 11, 11), (12, 12, 12), (5, 17, 9)]
+    subs = []
+    for ijk in samples:
+        m, lo, Q = _subbox_oracle(w, ijk, margin=1)
+        full = [index[(r[1] + lo[0], r[2] + lo[1], r[3] + lo[2])] for r in m.ids]
+        Qd[torch.tensor(full, device="cuda")] = to_gpu(Q)
+        here = [p for p, r in enumerate(m.ids) if (r[1] + lo[0], r[2] + lo[1], r[3] + lo[2]) == ijk][0]
+        subs.append((m, Q, here))
+    ctx.fill_halos(Qd)
+    HMd = torch.zeros((ctx.n_patches, 4, 729), dtype=torch.float64, device="cuda")
+    norms, st = ctx.constraints(Qd, HMd)
+    assert st == ccz4.CCZ4_OK and norms[2] == 0
+    scale = HMd.abs().amax(dim=(0, 2)).cpu().numpy()
+    g = HMd[torch.tensor([index[ijk] for ijk in samples], device="cuda")].cpu().numpy().transpose(0, 2, 1)
+    del Qd, HMd
+    torch.cuda.empty_cache()
+    for n, (m, Q, here) in enumerate(subs):
+        m.fill_halos(Q)
+        _, HMo = m.constraints(Q, want_fields=True)
+        d = np.abs(g[n] - HMo[here]).max(0)
+        assert (d <= TOL * scale).all(), (samples[n], d / scale)
+        assert np.abs(HMo[here]).max() > 0
+
+
 def test_tag_refine_parity():
     w = scenarios.config(2)
     refined = [(0, 0, 0, 0)]
