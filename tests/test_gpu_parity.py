@@ -308,6 +308,52 @@ def test_tag_refine_parity():
     assert set(np.unique(t)) <= {-1, 0, 1}
 
 
+def test_full_size_tag_refine_config4_sampled():
+    """The plain refinement criterion over the full 24^3-leaf puncture: the indicator (largest
+    adjacent differences of chi and alpha, dx^2 max|H|) of sampled leaves against the oracle on
+    sub-boxes of the leaves around each (initial data uploaded as in the other full-size tests)
+    at 1e-12 of each indicator's size on the mesh, and their tags with thresholds at the 99th and 30th percentiles of the mesh's
+    indicator (level-0 leaves: REFINE or KEEP).  Samples: a domain corner, the two leaves at the
+    puncture, an interior leaf."""
+    w = scenarios.config(4)
+    ctx = ccz4.Context(w.n0, w.origin, w.extent, w.bc, w.params(), w.refined)
+    index = {tuple(r[1:]): p for p, r in enumerate(ctx.ids)}
+    Qd = ctx.new_state(0.0)
+    ctx.init_patches(Qd, w.scenario, w.scen)
+    samples = [(0, 0, 0), (11, 11, 11), (12, 12, 12), (5, 17, 9)]
+    subs = []
+    for ijk in samples:
+        m, lo, Q = _subbox_oracle(w, ijk, margin=1)
+        full = [index[(r[1] + lo[0], r[2] + lo[1], r[3] + lo[2])] for r in m.ids]
+        Qd[torch.tensor(full, device="cuda")] = to_gpu(Q)
+        here = [p for p, r in enumerate(m.ids) if (r[1] + lo[0], r[2] + lo[1], r[3] + lo[2]) == ijk][0]
+        subs.append((m, Q, here))
+    ctx.fill_halos(Qd)
+    ind_d = torch.zeros((ctx.n_patches, 3), dtype=torch.float64, device="cuda")
+    tags_d = torch.zeros(ctx.n_patches, dtype=torch.int8, device="cuda")
+    ctx.tag_refine(Qd, 1e300, 0.0, 1, tags_d, ind_d)  # first pass: the indicator only
+    emax = ind_d.max(1).values.cpu().numpy()
+    theta_r, theta_c = float(np.quantile(emax, 0.99)), float(np.quantile(emax, 0.3))
+    ctx.tag_refine(Qd, theta_r, theta_c, 1, tags_d, ind_d)
+    sel = torch.tensor([index[ijk] for ijk in samples], device="cuda")
+    ind_g, tags_g = ind_d[sel].cpu().numpy(), tags_d[sel].cpu().numpy()
+    ind_scale = ind_d.amax(0).cpu().numpy()  # each indicator's largest value over the mesh
+    t_all = tags_d.cpu().numpy()
+    del Qd
+    torch.cuda.empty_cache()
+    assert (t_all == 1).sum() > 0 and set(np.unique(t_all)) <= {0, 1}
+    for n, (m, Q, here) in enumerate(subs):
+        m.fill_halos(Q)
+        ind_o = m.tag_indicator(Q)[here]
+        # each indicator to 1e-12 of its size on the mesh (the constraint term of a far-field leaf is
+        # the truncation residual of H, 1e-10 of its size at the puncture, and rounds accordingly)
+        assert (np.abs(ind_g[n] - ind_o) <= 1e-12 * ind_scale).all(), (samples[n], ind_g[n], ind_o)
+        e = ind_o.max()
+        if abs(e - theta_r) > 1e-12 * theta_r:  # ties decided in the same precision: none expected here
+            assert tags_g[n] == (1 if e >= theta_r else 0), (samples[n], e, theta_r, tags_g[n])
+    assert tags_g[2] == 1  # the leaf at the puncture refines
+
+
 # ------------------------------------------------------------------ whole steps
 
 def test_config1_ten_rk4_steps_match_oracle():
