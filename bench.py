@@ -995,7 +995,11 @@ def main():
                          "state_error_vs_fp64": {"max": emax, "slot": kmax, "per_slot": per_slot,
                                                  "measure": "max|Q_mixed - Q_fp64| / max|Q_fp64| per slot over "
                                                             "interior cells (slots below 1e-10 of the largest: "
-                                                            "relative to the largest)"}}
+                                                            "relative to the largest)"},
+                         # the parity tests' bounds for one or two mixed steps against the FP64 oracle, per
+                         # slot relative to the slot's size on the mesh
+                         "stated_bound_vs_oracle": {"per_slot": 1e-6,
+                                                    "leaves_touching_the_puncture_at_dx_1_12": 1e-4}}
     if not args.no_plain:
         _say("plain unfused FP64 path")
         rp = run_plain(args, w, total_steps=max(horizon, r64["steps_total"]), keep=True)
