@@ -60,14 +60,10 @@ def stage_bytes_per_cell(s):
     return QS_BYTES_PER_CELL + STREAM_BYTES_PER_CELL[s]
 
 
-# Standalone right-hand side, bytes per interior cell: the 58 evolved slots over the interior and
-# face halos (2187 cell-vectors per 729 cells) plus K_0 pointwise, and the 59 slots of k written.
-RHS_BYTES_PER_CELL = QS_BYTES_PER_CELL + 8 * NV
-# the same with every cell-vector read once (no halo duplication): the ideal lower bound
+# Standalone right-hand side with every cell-vector read once (no halo duplication) and k written:
+# the ideal lower bound beside the 1888 B per cell of its roofline (the Sommerfeld ghosts' right-hand
+# side, which its slab work-groups also compute, is counted in neither)
 RHS_IDEAL_BYTES_PER_CELL = 2 * 8 * NV
-# its Sommerfeld ghost right-hand side, cell-vectors per ghost cell: ghost and interior layers
-# (4 per 3 ghost cells), the background, k written
-RHS_GHOST_VECTORS = 4.0 / 3 + 2
 
 
 def stage_bytes(s, cells, pushed_faces, ghost_faces=0):
